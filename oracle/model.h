@@ -1,0 +1,36 @@
+/* Internal state of the CPU oracle.  TEST INFRASTRUCTURE ONLY. */
+#ifndef ISC_ORACLE_MODEL_H
+#define ISC_ORACLE_MODEL_H
+#include <vector>
+#include "oracle.h"
+
+struct orc_perf {
+    int32_t cell;
+    int32_t kind;     /* 1 producer, 2 injector */
+    double wi;        /* Peaceman well index, m^3 */
+    double bhp;       /* producer */
+    double q[ORC_NSPEC];  /* injector molar rates per species, mol/s */
+    double qE;        /* injector energy rate, W */
+    double q_total;   /* injector total molar rate (for sensitivity) */
+};
+
+struct orc_model {
+    orc_grid g;
+    orc_fluid fl;
+    int32_t n;                    /* cells */
+    std::vector<double> logk, kh, kz, poro;
+    double kvkh;
+    std::vector<int32_t> row_ptr, col_idx, diag_pos;
+    std::vector<orc_perf> perfs;
+    std::vector<orc_well> wells_in;        /* shallow copies for WI recompute */
+    std::vector<std::vector<int32_t>> well_cells;
+};
+
+namespace orc {
+/* neighbour list helpers */
+int32_t block_of(const orc_model& m, int32_t i, int32_t j);  /* index into J or -1 */
+double cell_volume(const orc_model& m);
+double depth(const orc_model& m, int32_t i);
+void compute_wells(orc_model& m);
+}
+#endif
