@@ -1,0 +1,218 @@
+/* libisc — MI355X (gfx950) Newton hot path of a fully implicit in-situ
+ * combustion (ISC) simulator.
+ *
+ * The operations follow He, Yang, Liu, Chen, "A New In-Situ Combustion
+ * Simulator for Parallel Computers":
+ *   - the PDE system of Section 2 (molar balances eq. 4.2, coke eq. 4.8,
+ *     energy eq. 4.3, constraints eqs. 4.4-4.7) reduced to eight unknowns per
+ *     cell (table "Modified mathematical system for ISC", with the two
+ *     composition constraints substituted);
+ *   - the implicit-Euler, 7-point finite-difference discretisation with harmonic
+ *     transmissibilities and upstream weighting of Section 3.1;
+ *   - Newton's method with an analytical Jacobian, J du = -f (abstract, Sec. 3);
+ *   - Gauss-Jordan decoupling C_L J du = -C_L f, C_L = blockdiag(J_ii^-1)
+ *     (Section 3.2);
+ *   - a block-ILU(0)-preconditioned restarted GMRES solve of the decoupled
+ *     system (the paper's own solver is BiCGSTAB with RAS or CPR-PF).
+ *
+ * Conventions
+ *   N = nx*ny*nz cells; cell i = ix + nx*(iy + ny*iz); iz grows with depth.
+ *   Unknowns (u):  0 p [Pa], 1 x_LO, 2 y_O2, 3 y_CO2, 4 T [K], 5 S_w, 6 S_g,
+ *                  7 C_c [mol/m^3]  — stored structure-of-arrays, u[8][N].
+ *   Rows (F, J):   0..5 molar balances of W, LO, HO, O2, CO2, N2 [mol/s],
+ *                  6 energy [W], 7 coke [mol/s] — stored F[N][8].
+ *   Jacobian:      block CSR with 8x8 row-major blocks Jval[nnzb][8][8];
+ *                  block (e, v) = dF_e/du_v.  Each row lists its existing
+ *                  neighbours in ascending cell order (z-, y-, x-, self, x+,
+ *                  y+, z+).  The pattern is owned by the context
+ *                  (isc_bcsr_pattern).
+ *   Pointers are device pointers on the context's device unless their name
+ *   ends in _h (host).  The caller owns every array passed in; the context
+ *   owns all workspace (Krylov bases, ILU factors, FP32 copies, scratch),
+ *   allocated once by isc_create and never during the hot calls.  Every call
+ *   is enqueued on the context's HIP stream; calls with a host (_h) output
+ *   synchronise that stream before returning.  A context is not thread-safe.
+ *   Errors: every function returns an isc_status; on error the outputs are
+ *   undefined and isc_last_error() describes the failure.
+ */
+#ifndef ISC_H
+#define ISC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t isc_status;
+enum {
+    ISC_OK = 0,
+    ISC_ERR_ARG = -1,             /* invalid argument */
+    ISC_ERR_HIP = -2,             /* HIP runtime error */
+    ISC_ERR_OOM = -3,             /* device allocation failed */
+    ISC_ERR_SINGULAR = -4,        /* singular diagonal block (bad_cell set) */
+    ISC_ERR_NONFINITE = -5,       /* NaN/Inf in the state or residual */
+    ISC_ERR_LINEAR_NOCONV = -6,   /* Krylov solve missed its tolerance */
+    ISC_ERR_NEWTON_NOCONV = -7    /* Newton missed its tolerance */
+};
+
+enum { ISC_NSPEC = 7, ISC_NGAS = 6, ISC_NREAC = 4, ISC_NTAB = 101 };
+
+/* SI physics card.  Species order W, LO, HO, O2, CO2, N2, coke; liquids
+ * W, LO, HO.  All correlations take T in K and p in Pa (Section 2.2). */
+typedef struct {
+    double M[ISC_NSPEC];               /* molar masses, kg/mol */
+    double Tc[ISC_NGAS], pc[ISC_NGAS]; /* critical T (K) and p (Pa) */
+    double rho_ref[3];                 /* liquid reference molar densities, mol/m^3 */
+    double cp_liq[3], ct1_liq[3];      /* liquid compressibility 1/Pa, expansivity 1/K */
+    double rho_coke;                   /* mol/m^3 */
+    double cpg[ISC_NGAS][4];           /* gas cp(T) = sum_j cpg[j] T^j, J/(mol K) */
+    double hvr[3], ev[3];              /* Hv(T) = hvr (Tc-T)^ev for T < Tc, J/mol */
+    double avisc[3], bvisc[3];         /* liquid mu = avisc exp(bvisc/T), Pa s */
+    double avg[ISC_NGAS], bvg[ISC_NGAS]; /* gas mu_c = avg T^bvg, Pa s */
+    double kv1[3], kv4[3], kv5[3];     /* K = kv1/p exp(kv4/(T - kv5)) */
+    double stoich[ISC_NREAC][ISC_NSPEC]; /* molar stoichiometry, reactants < 0 */
+    double Afreq[ISC_NREAC];           /* frequency factors (r1,r2,r4 1/(Pa s); r3 1/s) */
+    double Eact[ISC_NREAC];            /* activation energies, J/mol */
+    double Hreac[ISC_NREAC];           /* reaction enthalpies, J/mol, + exothermic */
+    double eps;                        /* PER correction constant */
+    double Ccmax;                      /* coke concentration limit, mol/m^3 */
+    double p_ref, T_ref;               /* reference state */
+    double cpor;                       /* rock compressibility 1/Pa (linear law) */
+    double cp_rock;                    /* rock volumetric heat capacity J/(m^3 K) */
+    double cp_coke;                    /* coke heat capacity J/(mol K) */
+    double Kcond[4];                   /* conductivities W/(m K): water, oil, gas, rock */
+    double grav, Rgas;                 /* m/s^2, J/(mol K) */
+    double krocw;                      /* k_ro at connate water (Stone II) */
+    double krw[ISC_NTAB], krow[ISC_NTAB]; /* SWT table at S_w = k/100 */
+    double krg[ISC_NTAB], krog[ISC_NTAB]; /* SLT table at S_g = k/100 */
+} isc_fluid;
+
+typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } isc_grid;
+
+enum { ISC_WELL_BHP_PRODUCER = 1, ISC_WELL_RATE_INJECTOR = 2 };
+/* One vertical well (well-modelling subsection, Peaceman index).  Producers
+ * hold a fixed bottom-hole pressure (target, Pa) with no backflow; injectors
+ * inject a fixed molar rate (target, mol/s) of gas of composition z_inj at
+ * T_inj, split over the perforations in proportion to their well index. */
+typedef struct {
+    int32_t kind;
+    int32_t nperf;
+    const int32_t* perf_cells_h;      /* host array of perforated cell indices */
+    double target;
+    double T_inj;
+    double z_inj[ISC_NSPEC];
+    double rw, skin;                  /* wellbore radius (m), skin */
+} isc_well;
+
+enum { ISC_FP64 = 0, ISC_MIXED = 1 };
+typedef struct {
+    int32_t restart;       /* GMRES restart length m (<= max_opts.restart) */
+    int32_t max_restarts;  /* cycles before ISC_ERR_LINEAR_NOCONV */
+    int32_t precision;     /* ISC_FP64, or ISC_MIXED: FP32 preconditioner and
+                              inner SpMV inside an FP64 flexible GMRES */
+    int32_t inner_iters;   /* ISC_MIXED: FP32 inner GMRES iterations per outer one */
+    double rtol;           /* stop when ||b - A x||_2 <= rtol ||b||_2 */
+} isc_solve_opts;
+
+typedef struct {
+    int32_t iters;               /* outer Krylov iterations */
+    int32_t inner_iters_total;   /* ISC_MIXED: inner iterations */
+    int32_t restarts;
+    int32_t reserved;
+    double relres_est;           /* Arnoldi residual estimate / ||b|| */
+    double relres_true;          /* ||b - A x|| / ||b|| recomputed at exit */
+} isc_solve_info;
+
+typedef struct {
+    isc_solve_opts lin;
+    double tol;                  /* convergence: scaled max-norm of F <= tol */
+} isc_newton_opts;
+
+typedef struct {
+    int32_t converged;           /* 1 if F already met tol (no solve was done) */
+    int32_t bad_cell;            /* singular cell, or -1 */
+    double res_scaled;           /* scaled max-norm of F at entry */
+    isc_solve_info lin;
+    float ms_assemble, ms_decouple, ms_precond, ms_krylov, ms_update;
+} isc_newton_info;
+
+typedef struct isc_ctx isc_ctx;
+
+/* Create a context for one grid.  logk: ln(k_h / m^2) per cell (device, [N]);
+ * kz = kv_over_kh * kh; poro: reference porosity per cell (device, [N]);
+ * wells_h: host array of nwells wells.  max_opts fixes the largest restart
+ * length and inner iteration count the context will be asked for (workspace
+ * is sized from it).  hip_stream: a hipStream_t (NULL = default stream). */
+isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const double* logk,
+                      double kv_over_kh, const double* poro, const isc_well* wells_h,
+                      int32_t nwells, const isc_solve_opts* max_opts_h, void* hip_stream,
+                      isc_ctx** out_h);
+isc_status isc_destroy(isc_ctx* ctx);
+
+/* Replace ln k (device [N], or NULL) and/or the reaction frequency factors
+ * (host [4], or NULL); transmissibilities and well indices are recomputed. */
+isc_status isc_set_params(isc_ctx* ctx, const double* logk, const double* A_h);
+
+/* Block CSR pattern (device pointers owned by the context) and its size. */
+isc_status isc_bcsr_pattern(const isc_ctx* ctx, const int32_t** row_ptr, const int32_t** col_idx,
+                            int32_t* nnzb_h);
+
+/* Residual F[N][8] and analytical Jacobian Jval[nnzb][8][8] of the implicit
+ * Euler step u_old -> u over dt seconds (Section 3.1 residuals F_W, F_O[i],
+ * F_G[i], F_E, F_Coke with the constraints substituted).  u, u_old: [8][N]. */
+isc_status isc_assemble(isc_ctx* ctx, const double* u, const double* u_old, double dt, double* F,
+                        double* Jval);
+
+/* Gauss-Jordan decoupling in place (Section 3.2): every block row
+ * [J_ii | J_i,nbr | F_i] becomes [I | J_ii^-1 J_i,nbr | J_ii^-1 F_i] by
+ * elimination with partial pivoting (row exchanges = dynamic equation
+ * alignment).  On a singular J_ii returns ISC_ERR_SINGULAR and *bad_cell_h. */
+isc_status isc_decouple(isc_ctx* ctx, double* Jval, double* F, int32_t* bad_cell_h);
+
+/* Solve Jdec x = b for a decoupled matrix (unit diagonal blocks, as left by
+ * isc_decouple) with block-ILU(0) (natural cell order) right-preconditioned
+ * restarted GMRES from x0 = 0.  b, x: [N][8].  info_h may be NULL. */
+isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* x,
+                     const isc_solve_opts* opts_h, isc_solve_info* info_h);
+
+/* One Newton iteration at (u, u_old, dt): assemble, scaled-norm test (if
+ * res <= tol: converged = 1, u unchanged), else decouple, BILU(0), GMRES and
+ * the safeguarded update of u in place (saturation halving rule of the PER
+ * subsection plus per-variable step limits). */
+isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double dt,
+                           const isc_newton_opts* opts_h, isc_newton_info* info_h);
+
+/* Component steps exposed for testing and profiling. */
+isc_status isc_spmv(isc_ctx* ctx, const double* Jdec, const double* x, double* y);
+isc_status isc_bilu0(isc_ctx* ctx, const double* Jdec, double* Dinv /* [N][8][8] */);
+isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv, const double* r,
+                           double* z);
+isc_status isc_update(isc_ctx* ctx, double* u, const double* du /* [N][8] */);
+isc_status isc_scaled_norm(isc_ctx* ctx, const double* F, double dt, double* res_h);
+
+/* Discrete adjoint of one implicit step for J_obj = sum_n dt_n q_oil(u^n):
+ * solves (dR^n/du^n)^T lam^n = (dj^n/du^n)^T - (dR^{n+1}/du^n)^T lam^{n+1}
+ * and accumulates g_logk += -(lam^n)^T dR^n/dlnk + dj^n/dlnk and
+ * g_A_h += -(lam^n)^T dR^n/dA.  lam_np1 may be NULL at the last step. */
+isc_status isc_adjoint(isc_ctx* ctx, const double* u_n, const double* u_nm1, double dt_n,
+                       const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
+                       double* g_A_h, isc_solve_info* info_h);
+
+/* Kernel-class timing with HIP events on the context's stream, for
+ * profiling.  enable = 1 clears the accumulators and starts timing; every
+ * launch of a class inside the calls above is then bracketed by an event
+ * pair; enable = 0 stops.  Always returns the accumulated milliseconds and
+ * launch counts (host arrays of ISC_PROF_NCLASS, may be NULL).  Classes:
+ * 0 SpMV, 1 BILU(0) apply (one forward plus one backward sweep, all levels),
+ * 2 assembly (property pass + face assembly), 3 decoupling, 4 BILU(0) factor
+ * (all levels), 5 Krylov vector work (orthogonalisation, updates, norms). */
+enum { ISC_PROF_SPMV = 0, ISC_PROF_ILU_APPLY, ISC_PROF_ASSEMBLE, ISC_PROF_DECOUPLE, ISC_PROF_ILU_FACTOR,
+       ISC_PROF_KRYLOV, ISC_PROF_NCLASS = 8 };
+isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* count_h);
+
+const char* isc_last_error(const isc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,600 @@
+// C-ABI of libisc: context management and the hot-path entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+// launchers defined in the kernel sources
+hipError_t isc_launch_props(isc_ctx*, const double* u, const double* u_old, double dt);
+hipError_t isc_launch_assemble(isc_ctx*, const double* u, double* F, double* J);
+hipError_t isc_launch_decouple(isc_ctx*, double* J, double* F, int32_t* bad_dev);
+hipError_t isc_launch_bilu0_factor(isc_ctx*, const double* A, double* Dinv, int32_t* bad);
+hipError_t isc_launch_bilu0_apply(isc_ctx*, const double* A, const double* Dinv, const double* r, double* z);
+hipError_t isc_launch_spmv(isc_ctx*, const double* A, const double* x, double* y);
+hipError_t isc_launch_update(isc_ctx*, double* u, const double* du, int32_t* flag_dev);
+hipError_t isc_launch_scaled_norm(isc_ctx*, const double* F, double dt, double* out_dev);
+hipError_t isc_launch_negate(isc_ctx*, const double* x, double* y);
+isc_status isc_gmres_fp64(isc_ctx*, const double* A, const double* Dinv, const double* b, double* x,
+                          const isc_solve_opts* o, isc_solve_info* info);
+isc_status isc_solve_mixed(isc_ctx*, const double* A, const double* b, double* x, const isc_solve_opts* o,
+                           isc_solve_info* info);
+isc_status isc_prepare_mixed(isc_ctx*, const double* A);
+isc_status isc_adjoint_impl(isc_ctx*, const double* u_n, const double* u_nm1, double dt_n,
+                            const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
+                            double* g_A_h, isc_solve_info* info_h);
+
+namespace {
+
+constexpr int FLAG_BAD = 0;      // int32 slot: singular cell (INT32_MAX = none)
+constexpr int FLAG_NONFIN = 1;   // int32 slot: non-finite update
+
+// gas enthalpy of species c at T (host copy of the cp integral, for the
+// injected-gas energy rate)
+double host_hgas(const isc_fluid& f, int c, double T) {
+    double h = 0.0, Tp = T, Rp = f.T_ref;
+    for (int j = 0; j < 4; ++j) {
+        h += f.cpg[c][j] / (j + 1) * (Tp - Rp);
+        Tp *= T;
+        Rp *= f.T_ref;
+    }
+    return h;
+}
+
+template <class T>
+isc_status dalloc(isc_ctx* ctx, T** p, size_t count) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        ctx->err = "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " + hipGetErrorString(e);
+        return ISC_ERR_OOM;
+    }
+    return ISC_OK;
+}
+
+#define TRY(x)                          \
+    do {                                \
+        isc_status s_ = (x);            \
+        if (s_ != ISC_OK) return s_;    \
+    } while (0)
+
+// transmissibilities of the +x, +y, +z faces (harmonic mean of A k / h)
+// and the perforation table (Peaceman well index, injection split)
+isc_status rebuild_static(isc_ctx* ctx) {
+    const isc_grid& g = ctx->g;
+    const int32_t n = ctx->n, nx = g.nx, ny = g.ny, nz = g.nz, nxy = nx * ny;
+    std::vector<double> tr((size_t)3 * n, 0.0);
+    const double ah[3] = {g.dy * g.dz / g.dx, g.dx * g.dz / g.dy, g.dx * g.dy / g.dz};
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+        const bool has[3] = {ix + 1 < nx, iy + 1 < ny, iz + 1 < nz};
+        const int32_t st[3] = {1, nx, nxy};
+        for (int d = 0; d < 3; ++d) {
+            if (!has[d]) continue;
+            const int32_t f = i + st[d];
+            const double ki = std::exp(ctx->logk_h[i]) * (d == 2 ? ctx->kvkh : 1.0);
+            const double kf = std::exp(ctx->logk_h[f]) * (d == 2 ? ctx->kvkh : 1.0);
+            const double ai = ah[d] * ki, af = ah[d] * kf;
+            tr[(size_t)d * n + i] = 2.0 * ai * af / (ai + af);
+        }
+    }
+    ISC_HIP(hipMemcpyAsync(ctx->trans, tr.data(), tr.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    // wells
+    std::vector<int32_t> slot(n, -1);
+    ctx->perf_h.assign((size_t)std::max(ctx->npf, 1) * isc::PERF_W, 0.0);
+    const double re = 0.14 * std::sqrt(g.dx * g.dx + g.dy * g.dy);
+    int32_t p = 0;
+    for (size_t w = 0; w < ctx->wells.size(); ++w) {
+        const isc_well& W = ctx->wells[w];
+        const std::vector<int32_t>& cells = ctx->well_cells[w];
+        std::vector<double> wi(cells.size());
+        double sum = 0.0;
+        for (size_t k = 0; k < cells.size(); ++k) {
+            wi[k] = 2.0 * M_PI * g.dz * std::exp(ctx->logk_h[cells[k]]) / (std::log(re / W.rw) + W.skin);
+            sum += wi[k];
+        }
+        double hinj = 0.0;
+        for (int c = 0; c < 6; ++c) hinj += W.z_inj[c] * host_hgas(ctx->fluid_h, c, W.T_inj);
+        for (size_t k = 0; k < cells.size(); ++k, ++p) {
+            double* pf = ctx->perf_h.data() + (size_t)p * isc::PERF_W;
+            if (slot[cells[k]] >= 0) {
+                ctx->err = "isc_create: a cell is perforated by more than one well";
+                return ISC_ERR_ARG;
+            }
+            slot[cells[k]] = p;
+            pf[0] = (double)W.kind;
+            pf[1] = wi[k];
+            if (W.kind == ISC_WELL_BHP_PRODUCER) {
+                pf[2] = W.target;
+            } else {
+                const double q = W.target * wi[k] / sum;
+                for (int c = 0; c < 7; ++c) pf[3 + c] = q * W.z_inj[c];
+                pf[10] = q * hinj;
+                pf[11] = q;
+            }
+        }
+    }
+    ISC_HIP(hipMemcpyAsync(ctx->well_slot, slot.data(), slot.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           ctx->stream));
+    ISC_HIP(hipMemcpyAsync(ctx->perf, ctx->perf_h.data(), ctx->perf_h.size() * sizeof(double),
+                           hipMemcpyHostToDevice, ctx->stream));
+    ISC_HIP(hipStreamSynchronize(ctx->stream));
+    return ISC_OK;
+}
+
+isc_status read_flag(isc_ctx* ctx, int slot, int32_t* out) {
+    ISC_HIP(hipMemcpyAsync(ctx->hflags + slot, ctx->flags + slot, sizeof(int32_t), hipMemcpyDeviceToHost,
+                           ctx->stream));
+    ISC_HIP(hipStreamSynchronize(ctx->stream));
+    *out = ctx->hflags[slot];
+    isc_prof_drain(ctx);
+    return ISC_OK;
+}
+
+__global__ void fill_flags(int32_t* f) {
+    f[FLAG_BAD] = INT32_MAX;
+    f[FLAG_NONFIN] = 0;
+}
+
+isc_status reset_flags(isc_ctx* ctx) {
+    hipLaunchKernelGGL(fill_flags, dim3(1), dim3(1), 0, ctx->stream, ctx->flags);
+    ISC_HIP(hipGetLastError());
+    return ISC_OK;
+}
+
+isc_status check_ctx(const isc_ctx* ctx) { return ctx ? ISC_OK : ISC_ERR_ARG; }
+
+}  // namespace
+
+extern "C" {
+
+isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const double* logk, double kv_over_kh,
+                      const double* poro, const isc_well* wells_h, int32_t nwells,
+                      const isc_solve_opts* max_opts_h, void* hip_stream, isc_ctx** out_h) {
+    if (!out_h) return ISC_ERR_ARG;
+    *out_h = nullptr;
+    isc_ctx* ctx = new isc_ctx();
+    auto fail = [&](isc_status s) {
+        // keep the message reachable through a leaked-on-error context is not
+        // possible; print it so the caller sees why creation failed
+        fprintf(stderr, "isc_create: %s\n", ctx->err.c_str());
+        isc_destroy(ctx);
+        return s;
+    };
+    if (!grid_h || !fluid_h || !logk || !poro || (nwells > 0 && !wells_h) || nwells < 0) {
+        ctx->err = "null argument";
+        return fail(ISC_ERR_ARG);
+    }
+    const isc_grid& g = *grid_h;
+    if (g.nx < 1 || g.ny < 1 || g.nz < 1 || !(g.dx > 0) || !(g.dy > 0) || !(g.dz > 0) || !(kv_over_kh > 0)) {
+        ctx->err = "invalid grid";
+        return fail(ISC_ERR_ARG);
+    }
+    const int64_t n64 = (int64_t)g.nx * g.ny * g.nz;
+    if (n64 * 7 > INT32_MAX / 2) {
+        ctx->err = "grid too large for 32-bit block indices";
+        return fail(ISC_ERR_ARG);
+    }
+    ctx->g = g;
+    ctx->n = (int32_t)n64;
+    ctx->kvkh = kv_over_kh;
+    ctx->fluid_h = *fluid_h;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&ctx->dev) != hipSuccess) {
+        ctx->err = "no HIP device";
+        return fail(ISC_ERR_HIP);
+    }
+    isc_solve_opts mo{30, 20, ISC_FP64, 0, 1e-8};
+    if (max_opts_h) mo = *max_opts_h;
+    if (mo.restart < 1 || mo.restart > 31) {
+        ctx->err = "max restart must be in [1, 31]";
+        return fail(ISC_ERR_ARG);
+    }
+    if (mo.inner_iters < 0 || mo.inner_iters > 31) {
+        ctx->err = "max inner_iters must be in [0, 31]";
+        return fail(ISC_ERR_ARG);
+    }
+    ctx->mmax = mo.restart;
+    ctx->inner_max = mo.inner_iters;
+    const int32_t n = ctx->n, nx = g.nx, ny = g.ny, nz = g.nz, nxy = nx * ny;
+
+    // block CSR pattern of the 7-point stencil, columns ascending
+    ctx->row_ptr_h.assign(n + 1, 0);
+    ctx->diag_pos_h.assign(n, 0);
+    ctx->col_idx_h.reserve((size_t)7 * n);
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+        const int32_t cand[7] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1, i,
+                                 ix + 1 < nx ? i + 1 : -1, iy + 1 < ny ? i + nx : -1, iz + 1 < nz ? i + nxy : -1};
+        for (int k = 0; k < 7; ++k) {
+            if (cand[k] < 0) continue;
+            if (cand[k] == i) ctx->diag_pos_h[i] = (int32_t)ctx->col_idx_h.size();
+            ctx->col_idx_h.push_back(cand[k]);
+        }
+        ctx->row_ptr_h[i + 1] = (int32_t)ctx->col_idx_h.size();
+    }
+    ctx->nnzb = ctx->row_ptr_h[n];
+    // hyperplane levels s = ix + iy + iz, rows ascending inside a level
+    ctx->nlev = nx + ny + nz - 2;
+    ctx->lvl_off_h.assign(ctx->nlev + 1, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t s = i % nx + (i / nx) % ny + i / nxy;
+        ctx->lvl_off_h[s + 1]++;
+    }
+    for (int32_t s = 0; s < ctx->nlev; ++s) ctx->lvl_off_h[s + 1] += ctx->lvl_off_h[s];
+    std::vector<int32_t> lvl_rows(n), fillp(ctx->lvl_off_h.begin(), ctx->lvl_off_h.end() - 1);
+    for (int32_t i = 0; i < n; ++i) lvl_rows[fillp[i % nx + (i / nx) % ny + i / nxy]++] = i;
+
+    // wells
+    int32_t npf = 0;
+    for (int32_t w = 0; w < nwells; ++w) {
+        const isc_well& W = wells_h[w];
+        if (W.nperf < 1 || !W.perf_cells_h ||
+            (W.kind != ISC_WELL_BHP_PRODUCER && W.kind != ISC_WELL_RATE_INJECTOR) || !(W.rw > 0)) {
+            ctx->err = "invalid well " + std::to_string(w);
+            return fail(ISC_ERR_ARG);
+        }
+        std::vector<int32_t> cells(W.perf_cells_h, W.perf_cells_h + W.nperf);
+        for (int32_t c : cells)
+            if (c < 0 || c >= n) {
+                ctx->err = "well perforation outside the grid";
+                return fail(ISC_ERR_ARG);
+            }
+        ctx->wells.push_back(W);
+        ctx->wells.back().perf_cells_h = nullptr;
+        ctx->well_cells.push_back(cells);
+        npf += W.nperf;
+    }
+    ctx->npf = npf;
+
+    // device allocations (all workspace lives for the context's lifetime)
+    const size_t nv = (size_t)n * isc::NU;
+    isc_status s = ISC_OK;
+#define ALLOC(p, cnt) if ((s = dalloc(ctx, &(p), (cnt))) != ISC_OK) return fail(s)
+    ALLOC(ctx->fluid_d, 1);
+    ALLOC(ctx->logk, n);
+    ALLOC(ctx->poro, n);
+    ALLOC(ctx->trans, (size_t)3 * n);
+    ALLOC(ctx->row_ptr, (size_t)n + 1);
+    ALLOC(ctx->col_idx, (size_t)ctx->nnzb);
+    ALLOC(ctx->diag_pos, (size_t)n);
+    ALLOC(ctx->well_slot, (size_t)n);
+    ALLOC(ctx->perf, (size_t)std::max(npf, 1) * isc::PERF_W);
+    ALLOC(ctx->lvl_rows, (size_t)n);
+    ALLOC(ctx->payload, (size_t)n * isc::PL);
+    ALLOC(ctx->F, nv);
+    ALLOC(ctx->J, (size_t)ctx->nnzb * isc::BS);
+    ALLOC(ctx->Dinv, (size_t)n * isc::BS);
+    ALLOC(ctx->du, nv);
+    ALLOC(ctx->rhs, nv);
+    ALLOC(ctx->V, nv * (ctx->mmax + 1));
+    ALLOC(ctx->w, nv);
+    ALLOC(ctx->tvec, nv);
+    ALLOC(ctx->tvec2, nv);
+    ALLOC(ctx->partial, (size_t)32 * isc::NPART);
+    ALLOC(ctx->small, (size_t)4096);
+    ALLOC(ctx->flags, (size_t)16);
+    if (ctx->inner_max > 0) {
+        ALLOC(ctx->Z, nv * ctx->mmax);
+        ALLOC(ctx->J32, (size_t)ctx->nnzb * isc::BS);
+        ALLOC(ctx->Dinv32, (size_t)n * isc::BS);
+        ALLOC(ctx->V32, nv * (ctx->inner_max + 1));
+        ALLOC(ctx->w32, nv);
+        ALLOC(ctx->t32, nv);
+        ALLOC(ctx->t32b, nv);
+        ALLOC(ctx->small32, (size_t)4096);
+    }
+#undef ALLOC
+    if (hipHostMalloc((void**)&ctx->hscratch, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&ctx->hflags, 16 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+        ctx->err = "hipHostMalloc failed";
+        return fail(ISC_ERR_OOM);
+    }
+    for (auto& e : ctx->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            ctx->err = "hipEventCreate failed";
+            return fail(ISC_ERR_HIP);
+        }
+    auto h2d = [&](void* dst, const void* src, size_t bytes) {
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream) == hipSuccess;
+    };
+    ctx->logk_h.resize(n);
+    ctx->poro_h.resize(n);
+    if (hipMemcpyAsync(ctx->logk_h.data(), logk, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(ctx->poro_h.data(), poro, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, ctx->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        ctx->err = "cannot read logk/poro (device pointers expected)";
+        return fail(ISC_ERR_ARG);
+    }
+    if (!h2d(ctx->fluid_d, &ctx->fluid_h, sizeof(isc_fluid)) ||
+        !h2d(ctx->logk, ctx->logk_h.data(), (size_t)n * sizeof(double)) ||
+        !h2d(ctx->poro, ctx->poro_h.data(), (size_t)n * sizeof(double)) ||
+        !h2d(ctx->row_ptr, ctx->row_ptr_h.data(), ((size_t)n + 1) * sizeof(int32_t)) ||
+        !h2d(ctx->col_idx, ctx->col_idx_h.data(), (size_t)ctx->nnzb * sizeof(int32_t)) ||
+        !h2d(ctx->diag_pos, ctx->diag_pos_h.data(), (size_t)n * sizeof(int32_t)) ||
+        !h2d(ctx->lvl_rows, lvl_rows.data(), (size_t)n * sizeof(int32_t))) {
+        ctx->err = "host to device copy failed";
+        return fail(ISC_ERR_HIP);
+    }
+    if ((s = rebuild_static(ctx)) != ISC_OK) return fail(s);
+    if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        ctx->err = "stream synchronisation failed";
+        return fail(ISC_ERR_HIP);
+    }
+    *out_h = ctx;
+    return ISC_OK;
+}
+
+isc_status isc_destroy(isc_ctx* ctx) {
+    if (!ctx) return ISC_OK;
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    else hipDeviceSynchronize();
+    void* ptrs[] = {ctx->fluid_d, ctx->logk,  ctx->poro,    ctx->trans,  ctx->row_ptr, ctx->col_idx,
+                    ctx->diag_pos, ctx->well_slot, ctx->perf, ctx->lvl_rows, ctx->payload, ctx->F,
+                    ctx->J,       ctx->Dinv,  ctx->du,      ctx->rhs,    ctx->V,       ctx->Z,
+                    ctx->w,       ctx->tvec,  ctx->tvec2,   ctx->partial, ctx->small,  ctx->flags,
+                    ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,     ctx->t32b,
+                    ctx->small32};
+    for (void* p : ptrs)
+        if (p) hipFree(p);
+    if (ctx->hscratch) hipHostFree(ctx->hscratch);
+    if (ctx->hflags) hipHostFree(ctx->hflags);
+    for (auto& e : ctx->ev)
+        if (e) hipEventDestroy(e);
+    isc_prof_drain(ctx);
+    for (auto& e : ctx->prof_pool) hipEventDestroy(e);
+    delete ctx;
+    return ISC_OK;
+}
+
+isc_status isc_set_params(isc_ctx* ctx, const double* logk, const double* A_h) {
+    TRY(check_ctx(ctx));
+    if (logk) {
+        ISC_HIP(hipMemcpyAsync(ctx->logk_h.data(), logk, (size_t)ctx->n * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+        ISC_HIP(hipStreamSynchronize(ctx->stream));
+        ISC_HIP(hipMemcpyAsync(ctx->logk, ctx->logk_h.data(), (size_t)ctx->n * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+        TRY(rebuild_static(ctx));
+    }
+    if (A_h) {
+        for (int r = 0; r < ISC_NREAC; ++r) ctx->fluid_h.Afreq[r] = A_h[r];
+        ISC_HIP(hipMemcpyAsync(ctx->fluid_d, &ctx->fluid_h, sizeof(isc_fluid), hipMemcpyHostToDevice, ctx->stream));
+        ISC_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    return ISC_OK;
+}
+
+isc_status isc_bcsr_pattern(const isc_ctx* ctx, const int32_t** row_ptr, const int32_t** col_idx,
+                            int32_t* nnzb_h) {
+    if (!ctx) return ISC_ERR_ARG;
+    if (row_ptr) *row_ptr = ctx->row_ptr;
+    if (col_idx) *col_idx = ctx->col_idx;
+    if (nnzb_h) *nnzb_h = ctx->nnzb;
+    return ISC_OK;
+}
+
+isc_status isc_assemble(isc_ctx* ctx, const double* u, const double* u_old, double dt, double* F, double* Jval) {
+    TRY(check_ctx(ctx));
+    if (!u || !u_old || !F || !Jval || !(dt > 0)) {
+        ctx->err = "isc_assemble: invalid argument";
+        return ISC_ERR_ARG;
+    }
+    ISC_HIP(isc_launch_props(ctx, u, u_old, dt));
+    ISC_HIP(isc_launch_assemble(ctx, u, F, Jval));
+    return ISC_OK;
+}
+
+isc_status isc_decouple(isc_ctx* ctx, double* Jval, double* F, int32_t* bad_cell_h) {
+    TRY(check_ctx(ctx));
+    if (!Jval || !F) {
+        ctx->err = "isc_decouple: invalid argument";
+        return ISC_ERR_ARG;
+    }
+    ISC_HIP(isc_launch_decouple(ctx, Jval, F, ctx->flags + FLAG_BAD));
+    int32_t bad;
+    TRY(read_flag(ctx, FLAG_BAD, &bad));
+    if (bad_cell_h) *bad_cell_h = bad == INT32_MAX ? -1 : bad;
+    if (bad != INT32_MAX) {
+        ctx->err = "isc_decouple: singular diagonal block at cell " + std::to_string(bad);
+        return ISC_ERR_SINGULAR;
+    }
+    return ISC_OK;
+}
+
+isc_status isc_bilu0(isc_ctx* ctx, const double* Jdec, double* Dinv) {
+    TRY(check_ctx(ctx));
+    TRY(reset_flags(ctx));
+    ISC_HIP(isc_launch_bilu0_factor(ctx, Jdec, Dinv, ctx->flags + FLAG_BAD));
+    int32_t bad;
+    TRY(read_flag(ctx, FLAG_BAD, &bad));
+    if (bad != INT32_MAX) {
+        ctx->err = "block ILU(0): singular pivot block at cell " + std::to_string(bad);
+        return ISC_ERR_SINGULAR;
+    }
+    return ISC_OK;
+}
+
+isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv, const double* r, double* z) {
+    TRY(check_ctx(ctx));
+    if (r == z) {
+        ctx->err = "isc_bilu0_apply: r and z must not alias";
+        return ISC_ERR_ARG;
+    }
+    ISC_HIP(isc_launch_bilu0_apply(ctx, Jdec, Dinv, r, z));
+    return ISC_OK;
+}
+
+isc_status isc_spmv(isc_ctx* ctx, const double* Jdec, const double* x, double* y) {
+    TRY(check_ctx(ctx));
+    if (x == y) {
+        ctx->err = "isc_spmv: x and y must not alias";
+        return ISC_ERR_ARG;
+    }
+    ISC_HIP(isc_launch_spmv(ctx, Jdec, x, y));
+    return ISC_OK;
+}
+
+isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* x, const isc_solve_opts* o,
+                     isc_solve_info* info_h) {
+    TRY(check_ctx(ctx));
+    if (!Jdec || !b || !x || !o || x == b) {
+        ctx->err = "isc_solve: invalid argument";
+        return ISC_ERR_ARG;
+    }
+    if (o->restart < 1 || o->restart > ctx->mmax || o->max_restarts < 1 || !(o->rtol > 0)) {
+        ctx->err = "isc_solve: restart must be in [1, max restart of the context], max_restarts >= 1, rtol > 0";
+        return ISC_ERR_ARG;
+    }
+    if (o->precision == ISC_MIXED) {
+        if (o->inner_iters < 1 || o->inner_iters > ctx->inner_max) {
+            ctx->err = "isc_solve: mixed precision needs 1 <= inner_iters <= the context's maximum";
+            return ISC_ERR_ARG;
+        }
+        TRY(isc_prepare_mixed(ctx, Jdec));
+        return isc_solve_mixed(ctx, Jdec, b, x, o, info_h);
+    }
+    TRY(isc_bilu0(ctx, Jdec, ctx->Dinv));
+    return isc_gmres_fp64(ctx, Jdec, ctx->Dinv, b, x, o, info_h);
+}
+
+isc_status isc_update(isc_ctx* ctx, double* u, const double* du) {
+    TRY(check_ctx(ctx));
+    TRY(reset_flags(ctx));
+    ISC_HIP(isc_launch_update(ctx, u, du, ctx->flags + FLAG_NONFIN));
+    int32_t nf;
+    TRY(read_flag(ctx, FLAG_NONFIN, &nf));
+    if (nf) {
+        ctx->err = "isc_update: non-finite state after the Newton update";
+        return ISC_ERR_NONFINITE;
+    }
+    return ISC_OK;
+}
+
+isc_status isc_scaled_norm(isc_ctx* ctx, const double* F, double dt, double* res_h) {
+    TRY(check_ctx(ctx));
+    ISC_HIP(isc_launch_scaled_norm(ctx, F, dt, ctx->small + 3000));
+    ISC_HIP(hipMemcpyAsync(ctx->hscratch, ctx->small + 3000, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    ISC_HIP(hipStreamSynchronize(ctx->stream));
+    *res_h = ctx->hscratch[0];
+    isc_prof_drain(ctx);
+    return ISC_OK;
+}
+
+isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double dt, const isc_newton_opts* o,
+                           isc_newton_info* info_h) {
+    TRY(check_ctx(ctx));
+    if (!u || !u_old || !o || !(dt > 0)) {
+        ctx->err = "isc_newton_step: invalid argument";
+        return ISC_ERR_ARG;
+    }
+    isc_newton_info inf{};
+    inf.bad_cell = -1;
+    hipEvent_t* ev = ctx->ev;
+    ISC_HIP(hipEventRecord(ev[0], ctx->stream));
+    int tk = isc_prof_begin(ctx, ISC_PROF_ASSEMBLE);
+    ISC_HIP(isc_launch_props(ctx, u, u_old, dt));
+    ISC_HIP(isc_launch_assemble(ctx, u, ctx->F, ctx->J));
+    isc_prof_end(ctx, tk);
+    ISC_HIP(hipEventRecord(ev[1], ctx->stream));
+    double res;
+    TRY(isc_scaled_norm(ctx, ctx->F, dt, &res));
+    inf.res_scaled = res;
+    if (!std::isfinite(res)) {
+        ctx->err = "isc_newton_step: non-finite residual";
+        if (info_h) *info_h = inf;
+        return ISC_ERR_NONFINITE;
+    }
+    if (res <= o->tol) {
+        inf.converged = 1;
+        ISC_HIP(hipEventElapsedTime(&inf.ms_assemble, ev[0], ev[1]));
+        if (info_h) *info_h = inf;
+        return ISC_OK;
+    }
+    TRY(reset_flags(ctx));
+    tk = isc_prof_begin(ctx, ISC_PROF_DECOUPLE);
+    ISC_HIP(isc_launch_decouple(ctx, ctx->J, ctx->F, ctx->flags + FLAG_BAD));
+    isc_prof_end(ctx, tk);
+    ISC_HIP(isc_launch_negate(ctx, ctx->F, ctx->rhs));
+    ISC_HIP(hipEventRecord(ev[2], ctx->stream));
+    isc_status st;
+    if (o->lin.precision == ISC_MIXED) {
+        if (o->lin.inner_iters < 1 || o->lin.inner_iters > ctx->inner_max) {
+            ctx->err = "isc_newton_step: mixed precision needs 1 <= inner_iters <= the context's maximum";
+            return ISC_ERR_ARG;
+        }
+        TRY(isc_prepare_mixed(ctx, ctx->J));
+    } else {
+        tk = isc_prof_begin(ctx, ISC_PROF_ILU_FACTOR);
+        ISC_HIP(isc_launch_bilu0_factor(ctx, ctx->J, ctx->Dinv, ctx->flags + FLAG_BAD));
+        isc_prof_end(ctx, tk);
+    }
+    ISC_HIP(hipEventRecord(ev[3], ctx->stream));
+    int32_t bad;
+    TRY(read_flag(ctx, FLAG_BAD, &bad));
+    if (bad != INT32_MAX) {
+        inf.bad_cell = bad;
+        ctx->err = "isc_newton_step: singular block at cell " + std::to_string(bad);
+        if (info_h) *info_h = inf;
+        return ISC_ERR_SINGULAR;
+    }
+    if (o->lin.restart < 1 || o->lin.restart > ctx->mmax) {
+        ctx->err = "isc_newton_step: restart exceeds the context's maximum";
+        return ISC_ERR_ARG;
+    }
+    if (o->lin.precision == ISC_MIXED)
+        st = isc_solve_mixed(ctx, ctx->J, ctx->rhs, ctx->du, &o->lin, &inf.lin);
+    else
+        st = isc_gmres_fp64(ctx, ctx->J, ctx->Dinv, ctx->rhs, ctx->du, &o->lin, &inf.lin);
+    ISC_HIP(hipEventRecord(ev[4], ctx->stream));
+    if (st != ISC_OK) {
+        if (info_h) *info_h = inf;
+        return st;
+    }
+    ISC_HIP(isc_launch_update(ctx, u, ctx->du, ctx->flags + FLAG_NONFIN));
+    ISC_HIP(hipEventRecord(ev[5], ctx->stream));
+    int32_t nf;
+    TRY(read_flag(ctx, FLAG_NONFIN, &nf));
+    ISC_HIP(hipEventElapsedTime(&inf.ms_assemble, ev[0], ev[1]));
+    ISC_HIP(hipEventElapsedTime(&inf.ms_decouple, ev[1], ev[2]));
+    ISC_HIP(hipEventElapsedTime(&inf.ms_precond, ev[2], ev[3]));
+    ISC_HIP(hipEventElapsedTime(&inf.ms_krylov, ev[3], ev[4]));
+    ISC_HIP(hipEventElapsedTime(&inf.ms_update, ev[4], ev[5]));
+    if (info_h) *info_h = inf;
+    if (nf) {
+        ctx->err = "isc_newton_step: non-finite state after the update";
+        return ISC_ERR_NONFINITE;
+    }
+    return ISC_OK;
+}
+
+isc_status isc_adjoint(isc_ctx* ctx, const double* u_n, const double* u_nm1, double dt_n, const double* lam_np1,
+                       double dt_np1, double* lam_n, double* g_logk, double* g_A_h, isc_solve_info* info_h) {
+    TRY(check_ctx(ctx));
+    return isc_adjoint_impl(ctx, u_n, u_nm1, dt_n, lam_np1, dt_np1, lam_n, g_logk, g_A_h, info_h);
+}
+
+isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* count_h) {
+    TRY(check_ctx(ctx));
+    ISC_HIP(hipStreamSynchronize(ctx->stream));
+    isc_prof_drain(ctx);
+    if (enable == 1) {
+        for (int c = 0; c < ISC_PROF_NCLASS; ++c) { ctx->prof_ms[c] = 0.0; ctx->prof_cnt[c] = 0; }
+        ctx->prof = true;
+    } else if (enable == 0) {
+        ctx->prof = false;
+    }
+    for (int c = 0; c < ISC_PROF_NCLASS; ++c) {
+        if (ms_h) ms_h[c] = ctx->prof_ms[c];
+        if (count_h) count_h[c] = ctx->prof_cnt[c];
+    }
+    return ISC_OK;
+}
+
+const char* isc_last_error(const isc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+}  // extern "C"

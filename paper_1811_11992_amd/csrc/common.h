@@ -1,0 +1,184 @@
+// Shared device/host definitions of libisc (HIP, gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/isc.h"
+
+namespace isc {
+
+constexpr int NU = 8;        // unknowns per cell
+constexpr int BS = 64;       // 8x8 block
+// Per-cell property payload written by the property pass and read by the
+// face-flux assembly (doubles, value followed by the 8 partial derivatives):
+//   [0, 72)     local residual terms of the 8 rows (accumulation change,
+//               reactions, wells)
+//   [72, 180)   12 mobility-weighted carried quantities lambda_a * xi_{e,a}
+//   [180, 207)  specific weights gamma_w, gamma_o, gamma_g
+//   [207, 216)  bulk thermal conductivity K_T
+constexpr int PL_LOCAL = 0;
+constexpr int PL_MOB = 72;
+constexpr int PL_GAM = 180;
+constexpr int PL_KT = 207;
+constexpr int PL = 216;
+constexpr int NMOB = 12;
+// carried-quantity slot of (phase, row), -1 if the row's species is absent
+// from the phase.  Phases: 0 water, 1 oil, 2 gas.
+__host__ __device__ constexpr int mob_slot(int a, int e) {
+    return a == 0 ? (e == 0 ? 0 : e == 6 ? 1 : -1)
+         : a == 1 ? (e == 1 ? 2 : e == 2 ? 3 : e == 6 ? 4 : -1)
+                  : (e <= 5 ? 5 + e : e == 6 ? 11 : -1);
+}
+
+// Value and one directional derivative.  The property pass runs eight lanes
+// per cell; lane k carries d/du_k, so a cell's full 8-gradient is spread over
+// its eight lanes and every lane computes the same values (the branch taken
+// therefore agrees across the lanes of a cell).
+struct G1 {
+    double v, d;
+};
+__device__ __forceinline__ G1 gconst(double x) { return G1{x, 0.0}; }
+__device__ __forceinline__ G1 operator+(G1 a, G1 b) { return G1{a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ G1 operator-(G1 a, G1 b) { return G1{a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ G1 operator-(G1 a) { return G1{-a.v, -a.d}; }
+__device__ __forceinline__ G1 operator*(G1 a, G1 b) { return G1{a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ G1 operator*(double s, G1 a) { return G1{s * a.v, s * a.d}; }
+__device__ __forceinline__ G1 operator*(G1 a, double s) { return G1{s * a.v, s * a.d}; }
+__device__ __forceinline__ G1 operator+(G1 a, double s) { return G1{a.v + s, a.d}; }
+__device__ __forceinline__ G1 operator+(double s, G1 a) { return G1{a.v + s, a.d}; }
+__device__ __forceinline__ G1 operator-(G1 a, double s) { return G1{a.v - s, a.d}; }
+__device__ __forceinline__ G1 operator-(double s, G1 a) { return G1{s - a.v, -a.d}; }
+__device__ __forceinline__ G1 operator/(G1 a, G1 b) {
+    const double q = a.v / b.v;
+    return G1{q, (a.d - q * b.d) / b.v};
+}
+__device__ __forceinline__ G1 operator/(G1 a, double s) { return G1{a.v / s, a.d / s}; }
+__device__ __forceinline__ G1 operator/(double s, G1 b) {
+    const double q = s / b.v;
+    return G1{q, -q * b.d / b.v};
+}
+__device__ __forceinline__ G1 gexp(G1 a) { const double e = exp(a.v); return G1{e, e * a.d}; }
+__device__ __forceinline__ G1 gpow(G1 a, double c) {
+    const double p = pow(a.v, c);
+    return G1{p, c * p / a.v * a.d};
+}
+
+}  // namespace isc
+
+// ---------------------------------------------------------------- context
+struct isc_ctx {
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    isc_grid g{};
+    int32_t n = 0, nnzb = 0;
+    double kvkh = 1.0;
+    isc_fluid fluid_h{};
+    isc_fluid* fluid_d = nullptr;
+    // static fields
+    double* logk = nullptr;
+    double* poro = nullptr;
+    double* trans = nullptr;        // [3][N]: +x, +y, +z face transmissibility of cell i
+    std::vector<double> logk_h, poro_h;
+    // pattern
+    int32_t *row_ptr = nullptr, *col_idx = nullptr, *diag_pos = nullptr;
+    std::vector<int32_t> row_ptr_h, col_idx_h, diag_pos_h;
+    // wells
+    std::vector<isc_well> wells;
+    std::vector<std::vector<int32_t>> well_cells;
+    int32_t npf = 0;
+    int32_t* well_slot = nullptr;   // [N] perforation index or -1
+    double* perf = nullptr;         // [npf][PERF_W]
+    std::vector<double> perf_h;
+    // hyperplane level schedule for the ILU recurrences
+    int32_t nlev = 0;
+    std::vector<int32_t> lvl_off_h;
+    int32_t* lvl_rows = nullptr;
+    // workspace
+    double* payload = nullptr;      // [N][PL]
+    double* F = nullptr;            // [N][8]
+    double* J = nullptr;            // [nnzb][64]
+    double* Dinv = nullptr;         // [N][64]
+    double* du = nullptr;           // [N][8]
+    double* rhs = nullptr;          // [N][8]
+    // Krylov
+    int32_t mmax = 30, inner_max = 0;
+    double* V = nullptr;            // [(mmax+1)][N*8]
+    double* Z = nullptr;            // [mmax][N*8] (flexible variant)
+    double* w = nullptr;            // [N*8]
+    double* tvec = nullptr;         // [N*8]
+    double* tvec2 = nullptr;        // [N*8]
+    double* partial = nullptr;      // [(mmax+2) * NPART]
+    double* small = nullptr;        // device scalars: h, givens, g, y ...
+    int32_t* flags = nullptr;       // device ints: [0] error/bad cell
+    // FP32 copies (mixed precision)
+    float* J32 = nullptr;           // [nnzb][64]
+    float* Dinv32 = nullptr;        // [N][64]
+    float* V32 = nullptr;           // [(inner+1)][N*8]
+    float* w32 = nullptr;
+    float* t32 = nullptr;
+    float* t32b = nullptr;
+    double* small32 = nullptr;
+    // host pinned scratch
+    double* hscratch = nullptr;     // 64 doubles
+    int32_t* hflags = nullptr;
+    hipEvent_t ev[8] = {};
+    std::string err;
+    // kernel-class timing (isc_profile)
+    bool prof = false;
+    double prof_ms[ISC_PROF_NCLASS] = {};
+    int32_t prof_cnt[ISC_PROF_NCLASS] = {};
+    struct Pending { int cls; hipEvent_t a, b; };
+    std::vector<Pending> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+};
+
+namespace isc {
+constexpr int PERF_W = 12;  // kind, wi, bhp, q[7], qE, q_total
+constexpr int NPART = 1024; // partial sums per reduction
+}
+
+// Profiling helpers (host).  prof_begin/prof_end bracket a kernel class on the
+// context stream; prof_drain converts finished pairs to milliseconds and must
+// only run after the stream has been synchronised.
+inline int isc_prof_begin(isc_ctx* ctx, int cls) {
+    if (!ctx->prof) return -1;
+    auto take = [&]() {
+        hipEvent_t e;
+        if (!ctx->prof_pool.empty()) { e = ctx->prof_pool.back(); ctx->prof_pool.pop_back(); }
+        else if (hipEventCreate(&e) != hipSuccess) e = nullptr;
+        return e;
+    };
+    isc_ctx::Pending p{cls, take(), take()};
+    if (!p.a || !p.b) return -1;
+    hipEventRecord(p.a, ctx->stream);
+    ctx->prof_pending.push_back(p);
+    return (int)ctx->prof_pending.size() - 1;
+}
+inline void isc_prof_end(isc_ctx* ctx, int tok) {
+    if (tok >= 0) hipEventRecord(ctx->prof_pending[tok].b, ctx->stream);
+}
+inline void isc_prof_drain(isc_ctx* ctx) {
+    for (auto& p : ctx->prof_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ctx->prof_ms[p.cls] += ms;
+            ctx->prof_cnt[p.cls] += 1;
+        }
+        ctx->prof_pool.push_back(p.a);
+        ctx->prof_pool.push_back(p.b);
+    }
+    ctx->prof_pending.clear();
+}
+
+// error helpers for host code
+#define ISC_HIP(call)                                                          \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess) {                                                \
+            ctx->err = std::string(#call) + ": " + hipGetErrorString(e_);      \
+            return ISC_ERR_HIP;                                                \
+        }                                                                      \
+    } while (0)

@@ -1,0 +1,375 @@
+#include <cmath>
+// Restarted GMRES with right preconditioning for the decoupled system.
+//
+// Orthogonalisation is classical Gram-Schmidt applied twice (CGS2): every
+// pass needs all inner products of one vector with the basis at once, which
+// is one streaming multi-dot over the basis instead of j dependent
+// reductions.  Reductions are two-stage with a fixed block count and a fixed
+// order, so results are bitwise reproducible.  The Hessenberg matrix, the
+// Givens rotations and the least-squares solution stay on the device; the
+// host reads one scalar (the residual estimate) per iteration.
+#include "common.h"
+
+namespace isc {
+
+constexpr int MAXV = 32;   // basis vectors handled by one multi-dot
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// block-level sum of nv per-thread values -> partial[k * nblk + block]
+__device__ __forceinline__ void block_store(const double* acc, int nv, double* partial, int nblk) {
+    __shared__ double red[4][MAXV];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+        if (k < nv) {
+            const double s = wave_sum(acc[k]);
+            if (lane == 0) red[w][k] = s;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nv) {
+        const int k = threadIdx.x;
+        partial[(size_t)k * nblk + blockIdx.x] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+    }
+}
+
+// partial[k] = <V_k, w>, k < nv
+template <class TV>
+__global__ void __launch_bounds__(256) multidot(int64_t len, const TV* __restrict__ V, int64_t ldv, int nv,
+                                                const TV* __restrict__ w, double* __restrict__ partial) {
+    double acc[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) acc[k] = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
+        const double wv = (double)w[t];
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k)
+            if (k < nv) acc[k] += (double)V[(size_t)k * ldv + t] * wv;
+    }
+    block_store(acc, nv, partial, gridDim.x);
+}
+
+// w <- w - sum_k h[k] V_k, then partial[k] = <V_k, w> (second CGS pass fused)
+template <class TV>
+__global__ void __launch_bounds__(256) update_multidot(int64_t len, const TV* __restrict__ V, int64_t ldv,
+                                                       int nv, const double* __restrict__ h,
+                                                       TV* __restrict__ w, double* __restrict__ partial) {
+    double acc[MAXV];
+    double hk[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) { acc[k] = 0.0; hk[k] = k < nv ? h[k] : 0.0; }
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
+        double vk[MAXV];
+        double wv = (double)w[t];
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k)
+            if (k < nv) { vk[k] = (double)V[(size_t)k * ldv + t]; wv -= hk[k] * vk[k]; }
+        w[t] = (TV)wv;
+        wv = (double)w[t];
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k)
+            if (k < nv) acc[k] += vk[k] * wv;
+    }
+    block_store(acc, nv, partial, gridDim.x);
+}
+
+// w <- w - sum_k h[k] V_k, partial[0] = ||w||^2
+template <class TV>
+__global__ void __launch_bounds__(256) update_norm(int64_t len, const TV* __restrict__ V, int64_t ldv, int nv,
+                                                   const double* __restrict__ h, TV* __restrict__ w,
+                                                   double* __restrict__ partial) {
+    double hk[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) hk[k] = k < nv ? h[k] : 0.0;
+    double acc[1] = {0.0};
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
+        double wv = (double)w[t];
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k)
+            if (k < nv) wv -= hk[k] * (double)V[(size_t)k * ldv + t];
+        const TV ws = (TV)wv;
+        w[t] = ws;
+        acc[0] += (double)ws * (double)ws;
+    }
+    block_store(acc, 1, partial, gridDim.x);
+}
+
+// out[k] = sum of partial[k][0..nblk), fixed order; one block per k
+__global__ void __launch_bounds__(256) reduce_partials(const double* __restrict__ partial, int nblk,
+                                                       double* __restrict__ out) {
+    __shared__ double red[4];
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += partial[(size_t)k * nblk + b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[k] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// y = x * s[0]  (s on the device)
+template <class TA, class TB>
+__global__ void __launch_bounds__(256) scale_copy(int64_t len, const TA* __restrict__ x, const double* __restrict__ s,
+                                                  TB* __restrict__ y) {
+    const double f = *s;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256)
+        y[t] = (TB)((double)x[t] * f);
+}
+
+// out = sum_k y[k] V_k (+ out if accumulate)
+template <class TV, class TO>
+__global__ void __launch_bounds__(256) lincomb(int64_t len, const TV* __restrict__ V, int64_t ldv, int nv,
+                                               const double* __restrict__ y, TO* __restrict__ out, int accumulate) {
+    double yk[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) yk[k] = k < nv ? y[k] : 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
+        double s = accumulate ? (double)out[t] : 0.0;
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k)
+            if (k < nv) s += yk[k] * (double)V[(size_t)k * ldv + t];
+        out[t] = (TO)s;
+    }
+}
+
+// r = b - Ax (Ax given), partial[0] = ||r||^2
+__global__ void __launch_bounds__(256) residual_norm(int64_t len, const double* __restrict__ b,
+                                                     const double* __restrict__ Ax, double* __restrict__ r,
+                                                     double* __restrict__ partial) {
+    double acc[1] = {0.0};
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
+        const double v = b[t] - Ax[t];
+        r[t] = v;
+        acc[0] += v * v;
+    }
+    block_store(acc, 1, partial, gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) axpy_kernel(int64_t len, const double* __restrict__ x, double* __restrict__ y) {
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) y[t] += x[t];
+}
+
+__global__ void __launch_bounds__(256) zero_kernel(int64_t len, double* __restrict__ y) {
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) y[t] = 0.0;
+}
+
+// Small dense state of one GMRES cycle (device, one thread):
+//   H[(m+1) x m] column-major by iteration, cs[m], sn[m], g[m+1], y[m]
+struct Hess {
+    double* H; double* cs; double* sn; double* g; double* y; double* scal;
+    int m;
+};
+// scal: [0] beta / norm input, [1] 1/h_{j+1,j}, [2] residual estimate, [3] ||b||
+
+// start a cycle: g = (beta, 0, ...), scal[1] = 1/beta from ||r||^2 in nrm2[0]
+__global__ void gmres_start(Hess hs, const double* __restrict__ nrm2) {
+    const double beta = sqrt(nrm2[0]);
+    for (int k = 0; k <= hs.m; ++k) hs.g[k] = 0.0;
+    hs.g[0] = beta;
+    hs.scal[0] = beta;
+    hs.scal[1] = beta > 0.0 ? 1.0 / beta : 0.0;
+    hs.scal[2] = beta;
+}
+
+// column j of H from the two CGS passes h1 + h2 and ||w||^2; rotations
+__global__ void gmres_column(Hess hs, int j, const double* __restrict__ h1, const double* __restrict__ h2,
+                             const double* __restrict__ nrm2) {
+    double* col = hs.H + (size_t)j * (hs.m + 1);
+    for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
+    const double hn = sqrt(nrm2[0]);
+    col[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = hs.cs[i] * a + hs.sn[i] * b;
+        col[i + 1] = -hs.sn[i] * a + hs.cs[i] * b;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double den = hypot(a, b);
+    hs.cs[j] = a / den;
+    hs.sn[j] = b / den;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    hs.g[j + 1] = -hs.sn[j] * hs.g[j];
+    hs.g[j] = hs.cs[j] * hs.g[j];
+    hs.scal[1] = hn > 0.0 ? 1.0 / hn : 0.0;
+    hs.scal[2] = fabs(hs.g[j + 1]);
+}
+
+// y = R^-1 g for the leading k x k triangle
+__global__ void gmres_solve_small(Hess hs, int k) {
+    for (int i = k - 1; i >= 0; --i) {
+        double s = hs.g[i];
+        for (int l = i + 1; l < k; ++l) s -= hs.H[(size_t)l * (hs.m + 1) + i] * hs.y[l];
+        hs.y[i] = s / hs.H[(size_t)i * (hs.m + 1) + i];
+    }
+}
+
+}  // namespace isc
+
+// ---------------------------------------------------------------- host side
+hipError_t isc_launch_bilu0_apply(isc_ctx*, const double*, const double*, const double*, double*);
+hipError_t isc_launch_spmv(isc_ctx*, const double*, const double*, double*);
+hipError_t isc_launch_bilu0_factor(isc_ctx*, const double*, double*, int32_t*);
+
+namespace isc {
+
+static int nblocks(int64_t len) {
+    int64_t b = (len + 255) / 256;
+    return (int)(b < NPART ? (b > 0 ? b : 1) : NPART);
+}
+
+// reductions: results land in ctx->small + RED_OFF
+constexpr int RED_OFF = 0;          // [0, 2*MAXV): h1, h2 ; [2*MAXV]: norm^2
+Hess hess_of(isc_ctx* ctx) {
+    Hess h;
+    const int m = ctx->mmax;
+    double* base = ctx->small + 4 * MAXV;
+    h.H = base;
+    h.cs = h.H + (size_t)(m + 1) * m;
+    h.sn = h.cs + m;
+    h.g = h.sn + m;
+    h.y = h.g + m + 1;
+    h.scal = h.y + m;
+    h.m = m;
+    return h;
+}
+
+// ||v||^2 -> dst (device)
+static void norm2_dev(isc_ctx* ctx, int64_t len, const double* v, double* dst) {
+    const int nb = nblocks(len);
+    hipLaunchKernelGGL(multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, v, (int64_t)0, 1, v,
+                       ctx->partial);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb, dst);
+}
+
+static hipError_t read_scalar(isc_ctx* ctx, const double* dsrc, double* out) {
+    hipError_t e = hipMemcpyAsync(ctx->hscratch, dsrc, sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(ctx->stream);
+    *out = ctx->hscratch[0];
+    isc_prof_drain(ctx);
+    return e;
+}
+
+}  // namespace isc
+
+// FP64 right-preconditioned GMRES(m) with BILU(0); Dinv must hold the factor.
+isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, const double* b, double* x,
+                          const isc_solve_opts* o, isc_solve_info* info) {
+    using namespace isc;
+    const int64_t len = (int64_t)ctx->n * NU;
+    const int64_t ldv = len;
+    const int m = o->restart;
+    const int nb = nblocks(len);
+    Hess hs = hess_of(ctx);
+    double* red = ctx->small + RED_OFF;
+    isc_solve_info inf{};
+    double bn2;
+    norm2_dev(ctx, len, b, red + 2 * MAXV);
+    ISC_HIP(read_scalar(ctx, red + 2 * MAXV, &bn2));
+    const double bnorm = sqrt(bn2);
+    hipLaunchKernelGGL(zero_kernel, dim3(nb), dim3(256), 0, ctx->stream, len, x);
+    if (bnorm == 0.0) {
+        if (info) *info = inf;
+        return ISC_OK;
+    }
+    if (!std::isfinite(bnorm)) {
+        ctx->err = "isc_solve: right-hand side is not finite";
+        return ISC_ERR_NONFINITE;
+    }
+    isc_status st = ISC_ERR_LINEAR_NOCONV;
+    for (int cyc = 0; cyc < o->max_restarts; ++cyc) {
+        // r = b - A x  (x = 0 on the first cycle)
+        if (cyc == 0) {
+            hipLaunchKernelGGL(multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, b, (int64_t)0, 1, b,
+                               ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
+                               red + 2 * MAXV);
+            hipLaunchKernelGGL(gmres_start, dim3(1), dim3(1), 0, ctx->stream, hs, red + 2 * MAXV);
+            hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, b,
+                               hs.scal + 1, ctx->V);
+        } else {
+            isc_launch_spmv(ctx, A, x, ctx->tvec);
+            hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, ctx->w,
+                               ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
+                               red + 2 * MAXV);
+            double rn2;
+            ISC_HIP(read_scalar(ctx, red + 2 * MAXV, &rn2));
+            inf.relres_true = sqrt(rn2) / bnorm;
+            if (sqrt(rn2) <= o->rtol * bnorm) { st = ISC_OK; break; }
+            inf.restarts = cyc;
+            hipLaunchKernelGGL(gmres_start, dim3(1), dim3(1), 0, ctx->stream, hs, red + 2 * MAXV);
+            hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w,
+                               hs.scal + 1, ctx->V);
+        }
+        int jdone = 0;
+        for (int j = 0; j < m; ++j) {
+            double* Vj = ctx->V + (size_t)j * ldv;
+            double* Vn = ctx->V + (size_t)(j + 1) * ldv;
+            int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY);
+            isc_launch_bilu0_apply(ctx, A, Dinv, Vj, ctx->tvec);
+            isc_prof_end(ctx, tk);
+            tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
+            isc_launch_spmv(ctx, A, ctx->tvec, ctx->w);
+            isc_prof_end(ctx, tk);
+            tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
+            // CGS2
+            hipLaunchKernelGGL(multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, j + 1,
+                               ctx->w, ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(j + 1), dim3(256), 0, ctx->stream, ctx->partial, nb, red);
+            hipLaunchKernelGGL(update_multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv,
+                               j + 1, red, ctx->w, ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(j + 1), dim3(256), 0, ctx->stream, ctx->partial, nb,
+                               red + MAXV);
+            hipLaunchKernelGGL(update_norm<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, j + 1,
+                               red + MAXV, ctx->w, ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
+                               red + 2 * MAXV);
+            hipLaunchKernelGGL(gmres_column, dim3(1), dim3(1), 0, ctx->stream, hs, j, red, red + MAXV,
+                               red + 2 * MAXV);
+            hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w,
+                               hs.scal + 1, Vn);
+            isc_prof_end(ctx, tk);
+            double est;
+            ISC_HIP(read_scalar(ctx, hs.scal + 2, &est));
+            inf.iters++;
+            jdone = j + 1;
+            inf.relres_est = est / bnorm;
+            if (!std::isfinite(est)) {
+                ctx->err = "isc_solve: GMRES breakdown (non-finite residual estimate)";
+                return ISC_ERR_NONFINITE;
+            }
+            if (est <= o->rtol * bnorm) break;
+        }
+        // x += M^-1 (V y)
+        hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hs, jdone);
+        hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv,
+                           jdone, hs.y, ctx->tvec2, 0);
+        {
+            const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY);
+            isc_launch_bilu0_apply(ctx, A, Dinv, ctx->tvec2, ctx->tvec);
+            isc_prof_end(ctx, tk);
+        }
+        hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->tvec, x);
+    }
+    if (st != ISC_OK) {
+        isc_launch_spmv(ctx, A, x, ctx->tvec);
+        hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, ctx->w,
+                           ctx->partial);
+        hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + 2 * MAXV);
+        double rn2;
+        ISC_HIP(read_scalar(ctx, red + 2 * MAXV, &rn2));
+        inf.relres_true = sqrt(rn2) / bnorm;
+        if (sqrt(rn2) <= o->rtol * bnorm) st = ISC_OK;
+        else ctx->err = "isc_solve: GMRES did not reach the tolerance";
+    }
+    if (info) *info = inf;
+    ISC_HIP(hipGetLastError());
+    return st;
+}

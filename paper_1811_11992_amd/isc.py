@@ -1,0 +1,268 @@
+"""Python binding of libisc (the C-ABI in include/isc.h).
+
+Argument marshalling only: every step of the Newton hot path runs in the HIP
+kernels of ``libisc.so``.  PyTorch supplies device memory and the stream.
+The library is loaded from this package directory; if it is missing the
+binding raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from . import inputs as I
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libisc.so")
+_LIB = None
+
+ISC_OK, ISC_ERR_ARG, ISC_ERR_HIP, ISC_ERR_OOM = 0, -1, -2, -3
+ISC_ERR_SINGULAR, ISC_ERR_NONFINITE, ISC_ERR_LINEAR_NOCONV, ISC_ERR_NEWTON_NOCONV = -4, -5, -6, -7
+ISC_FP64, ISC_MIXED = 0, 1
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_f64 = ctypes.c_double
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("restart", _i32), ("max_restarts", _i32), ("precision", _i32), ("inner_iters", _i32),
+                ("rtol", _f64)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", _i32), ("inner_iters_total", _i32), ("restarts", _i32), ("reserved", _i32),
+                ("relres_est", _f64), ("relres_true", _f64)]
+
+
+class NewtonOpts(ctypes.Structure):
+    _fields_ = [("lin", SolveOpts), ("tol", _f64)]
+
+
+class NewtonInfo(ctypes.Structure):
+    _fields_ = [("converged", _i32), ("bad_cell", _i32), ("res_scaled", _f64), ("lin", SolveInfo),
+                ("ms_assemble", ctypes.c_float), ("ms_decouple", ctypes.c_float),
+                ("ms_precond", ctypes.c_float), ("ms_krylov", ctypes.c_float), ("ms_update", ctypes.c_float)]
+
+
+class IscError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libisc status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1811_11992_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.isc_create.argtypes = [_vp, _vp, _vp, _f64, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(_vp)]
+        L.isc_destroy.argtypes = [_vp]
+        L.isc_set_params.argtypes = [_vp, _vp, _vp]
+        L.isc_bcsr_pattern.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i32)]
+        L.isc_assemble.argtypes = [_vp, _vp, _vp, _f64, _vp, _vp]
+        L.isc_decouple.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_i32)]
+        L.isc_solve.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]
+        L.isc_newton_step.argtypes = [_vp, _vp, _vp, _f64, ctypes.POINTER(NewtonOpts), ctypes.POINTER(NewtonInfo)]
+        L.isc_spmv.argtypes = [_vp, _vp, _vp, _vp]
+        L.isc_bilu0.argtypes = [_vp, _vp, _vp]
+        L.isc_bilu0_apply.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.isc_update.argtypes = [_vp, _vp, _vp]
+        L.isc_scaled_norm.argtypes = [_vp, _vp, _f64, ctypes.POINTER(_f64)]
+        L.isc_adjoint.argtypes = [_vp, _vp, _vp, _f64, _vp, _f64, _vp, _vp, _vp, ctypes.POINTER(SolveInfo)]
+        L.isc_profile.argtypes = [_vp, _i32, _vp, _vp]
+        L.isc_last_error.argtypes = [_vp]
+        L.isc_last_error.restype = ctypes.c_char_p
+        for name in ("isc_create", "isc_destroy", "isc_set_params", "isc_bcsr_pattern", "isc_assemble",
+                     "isc_decouple", "isc_solve", "isc_newton_step", "isc_spmv", "isc_bilu0",
+                     "isc_bilu0_apply", "isc_update", "isc_scaled_norm", "isc_adjoint", "isc_profile"):
+            getattr(L, name).restype = _i32
+        _LIB = L
+    return _LIB
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous() and t.dtype == torch.float64, (t.device, t.dtype)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def solve_opts(restart=30, max_restarts=20, precision=ISC_FP64, inner_iters=0, rtol=1e-8) -> SolveOpts:
+    return SolveOpts(restart, max_restarts, precision, inner_iters, rtol)
+
+
+class Context:
+    """One ``isc_ctx``: a grid, its physics card, rock, wells and workspace."""
+
+    def __init__(self, wl: I.Workload, fluid: I.Fluid | None = None, restart: int = 30,
+                 inner_iters: int = 0, device: str = "cuda"):
+        L = lib()
+        self.wl = wl
+        self.n = wl.ncell
+        self.device = torch.device(device)
+        self.fluid = fluid if fluid is not None else I.physics_card()
+        self._grid = wl.grid()
+        self._wells, self._keep = wl.well_structs()
+        self.logk = torch.tensor(wl.logk, dtype=torch.float64, device=self.device)
+        self.poro = torch.tensor(wl.poro, dtype=torch.float64, device=self.device)
+        self.max_opts = solve_opts(restart=restart, inner_iters=inner_iters)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        st = L.isc_create(ctypes.byref(self._grid), ctypes.byref(self.fluid), _ptr(self.logk), wl.kv_over_kh,
+                          _ptr(self.poro), ctypes.cast(self._wells, _vp), len(wl.wells),
+                          ctypes.byref(self.max_opts), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != ISC_OK:
+            raise IscError(st, "isc_create failed (see stderr)")
+        self.h = h
+        rp, ci, nn = _vp(), _vp(), _i32()
+        self._check(L.isc_bcsr_pattern(self.h, ctypes.byref(rp), ctypes.byref(ci), ctypes.byref(nn)))
+        self.nnzb = nn.value
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _LIB is not None:
+            _LIB.isc_destroy(self.h)
+            self.h = None
+
+    def _check(self, st):
+        if st != ISC_OK:
+            raise IscError(st, lib().isc_last_error(self.h).decode())
+        return st
+
+    def empty_F(self):
+        return torch.empty((self.n, 8), dtype=torch.float64, device=self.device)
+
+    def empty_J(self):
+        return torch.empty((self.nnzb, 8, 8), dtype=torch.float64, device=self.device)
+
+    # ---- C-ABI calls (same names as include/isc.h)
+    def isc_set_params(self, logk: torch.Tensor | None = None, A=None):
+        a = None if A is None else (ctypes.c_double * 4)(*[float(x) for x in A])
+        if logk is not None:
+            self.logk = logk.to(self.device, torch.float64).contiguous()
+        self._check(lib().isc_set_params(self.h, _ptr(logk if logk is None else self.logk), a))
+
+    def isc_assemble(self, u, u_old, dt, F=None, J=None):
+        F = self.empty_F() if F is None else F
+        J = self.empty_J() if J is None else J
+        self._check(lib().isc_assemble(self.h, _ptr(u), _ptr(u_old), dt, _ptr(F), _ptr(J)))
+        return F, J
+
+    def isc_decouple(self, J, F):
+        bad = _i32(-1)
+        st = lib().isc_decouple(self.h, _ptr(J), _ptr(F), ctypes.byref(bad))
+        if st == ISC_ERR_SINGULAR:
+            return st, bad.value
+        self._check(st)
+        return st, bad.value
+
+    def isc_solve(self, Jdec, b, opts: SolveOpts | None = None, x=None, check=True):
+        x = torch.empty_like(b) if x is None else x
+        info = SolveInfo()
+        st = lib().isc_solve(self.h, _ptr(Jdec), _ptr(b), _ptr(x), ctypes.byref(opts or solve_opts()),
+                             ctypes.byref(info))
+        if check:
+            self._check(st)
+        return x, info, st
+
+    def isc_newton_step(self, u, u_old, dt, tol=1e-10, lin: SolveOpts | None = None):
+        o = NewtonOpts(lin or solve_opts(), tol)
+        info = NewtonInfo()
+        st = lib().isc_newton_step(self.h, _ptr(u), _ptr(u_old), dt, ctypes.byref(o), ctypes.byref(info))
+        return st, info
+
+    def isc_spmv(self, Jdec, x, y=None):
+        y = torch.empty_like(x) if y is None else y
+        self._check(lib().isc_spmv(self.h, _ptr(Jdec), _ptr(x), _ptr(y)))
+        return y
+
+    def isc_bilu0(self, Jdec, Dinv=None):
+        Dinv = torch.empty((self.n, 8, 8), dtype=torch.float64, device=self.device) if Dinv is None else Dinv
+        self._check(lib().isc_bilu0(self.h, _ptr(Jdec), _ptr(Dinv)))
+        return Dinv
+
+    def isc_bilu0_apply(self, Jdec, Dinv, r, z=None):
+        z = torch.empty_like(r) if z is None else z
+        self._check(lib().isc_bilu0_apply(self.h, _ptr(Jdec), _ptr(Dinv), _ptr(r), _ptr(z)))
+        return z
+
+    def isc_update(self, u, du):
+        return lib().isc_update(self.h, _ptr(u), _ptr(du))
+
+    def isc_scaled_norm(self, F, dt):
+        r = _f64()
+        self._check(lib().isc_scaled_norm(self.h, _ptr(F), dt, ctypes.byref(r)))
+        return r.value
+
+    def isc_adjoint(self, u_n, u_nm1, dt_n, lam_np1, dt_np1, lam_n, g_logk, g_A):
+        info = SolveInfo()
+        a = (ctypes.c_double * 4)(*[float(x) for x in g_A])
+        st = lib().isc_adjoint(self.h, _ptr(u_n), _ptr(u_nm1), dt_n, _ptr(lam_np1), dt_np1, _ptr(lam_n),
+                               _ptr(g_logk), a, ctypes.byref(info))
+        self._check(st)
+        return [a[k] for k in range(4)], info
+
+
+PROF_CLASSES = ("spmv", "ilu_apply", "assemble", "decouple", "ilu_factor", "krylov")
+
+
+def _profile_call(ctx, enable):
+    ms = (ctypes.c_double * 8)()
+    cnt = (ctypes.c_int32 * 8)()
+    ctx._check(lib().isc_profile(ctx.h, enable, ms, cnt))
+    return {name: (ms[k], cnt[k]) for k, name in enumerate(PROF_CLASSES)}
+
+
+def isc_profile(ctx: "Context", enable: int):
+    """Start (1), stop (0) or read (-1) the library's kernel-class timers;
+    returns {class: (milliseconds, launches)}."""
+    return _profile_call(ctx, enable)
+
+
+class Simulator:
+    """Implicit-Euler time loop driving ``isc_newton_step``; on a failed step
+    the step size is halved and the step retried (at most four times)."""
+
+    def __init__(self, ctx: Context, tol=1e-10, max_newton=12, lin: SolveOpts | None = None):
+        self.ctx, self.tol, self.max_newton = ctx, tol, max_newton
+        self.lin = lin or solve_opts()
+
+    def step(self, u, dt):
+        """Advance u (in place) by one step of at most dt; returns a record."""
+        u_old = u.clone()
+        dts, cuts = dt, 0
+        rec = dict(newton=0, lin=0, inner=0, cuts=0)
+        while True:
+            ok = False
+            nit = 0
+            for nit in range(self.max_newton + 1):
+                st, info = self.ctx.isc_newton_step(u, u_old, dts, self.tol, self.lin)
+                rec["lin"] += info.lin.iters
+                rec["inner"] += info.lin.inner_iters_total
+                if st != ISC_OK:
+                    break
+                if info.converged:
+                    ok = True
+                    break
+            rec["newton"] += nit
+            rec["res"] = info.res_scaled
+            if ok:
+                rec.update(cuts=cuts, dt=dts)
+                return rec
+            u.copy_(u_old)
+            cuts += 1
+            dts *= 0.5
+            if cuts > 4:
+                raise IscError(ISC_ERR_NEWTON_NOCONV, f"Newton failed after {cuts - 1} step cuts")
+
+    def run(self, u0, dt, nsteps, history=False):
+        u = u0.clone()
+        recs, hist = [], [u.clone()] if history else None
+        for _ in range(nsteps):
+            recs.append(self.step(u, dt))
+            if history:
+                hist.append(u.clone())
+        return u, recs, hist
