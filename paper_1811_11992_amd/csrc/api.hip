@@ -21,7 +21,7 @@ isc_status isc_gmres_fp64(isc_ctx*, const double* A, const double* Dinv, const d
                           const isc_solve_opts* o, isc_solve_info* info);
 isc_status isc_solve_mixed(isc_ctx*, const double* A, const double* b, double* x, const isc_solve_opts* o,
                            isc_solve_info* info);
-isc_status isc_prepare_mixed(isc_ctx*, const double* A);
+isc_status isc_prepare_mixed_dev(isc_ctx*, const double* A, int32_t* bad_dev);
 isc_status isc_adjoint_impl(isc_ctx*, const double* u_n, const double* u_nm1, double dt_n,
                             const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
                             double* g_A_h, isc_solve_info* info_h);
@@ -455,7 +455,14 @@ isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* 
             ctx->err = "isc_solve: mixed precision needs 1 <= inner_iters <= the context's maximum";
             return ISC_ERR_ARG;
         }
-        TRY(isc_prepare_mixed(ctx, Jdec));
+        TRY(reset_flags(ctx));
+        TRY(isc_prepare_mixed_dev(ctx, Jdec, ctx->flags + FLAG_BAD));
+        int32_t bad;
+        TRY(read_flag(ctx, FLAG_BAD, &bad));
+        if (bad != INT32_MAX) {
+            ctx->err = "block ILU(0) (FP32): singular pivot block at cell " + std::to_string(bad);
+            return ISC_ERR_SINGULAR;
+        }
         return isc_solve_mixed(ctx, Jdec, b, x, o, info_h);
     }
     TRY(isc_bilu0(ctx, Jdec, ctx->Dinv));
@@ -527,7 +534,9 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
             ctx->err = "isc_newton_step: mixed precision needs 1 <= inner_iters <= the context's maximum";
             return ISC_ERR_ARG;
         }
-        TRY(isc_prepare_mixed(ctx, ctx->J));
+        tk = isc_prof_begin(ctx, ISC_PROF_ILU_FACTOR);
+        TRY(isc_prepare_mixed_dev(ctx, ctx->J, ctx->flags + FLAG_BAD));
+        isc_prof_end(ctx, tk);
     } else {
         tk = isc_prof_begin(ctx, ISC_PROF_ILU_FACTOR);
         ISC_HIP(isc_launch_bilu0_factor(ctx, ctx->J, ctx->Dinv, ctx->flags + FLAG_BAD));

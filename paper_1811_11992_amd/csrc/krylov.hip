@@ -190,8 +190,8 @@ __global__ void gmres_column(Hess hs, int j, const double* __restrict__ h1, cons
     }
     const double a = col[j], b = col[j + 1];
     const double den = hypot(a, b);
-    hs.cs[j] = a / den;
-    hs.sn[j] = b / den;
+    hs.cs[j] = den > 0.0 ? a / den : 1.0;     // exact breakdown: identity rotation
+    hs.sn[j] = den > 0.0 ? b / den : 0.0;
     col[j] = den;
     col[j + 1] = 0.0;
     hs.g[j + 1] = -hs.sn[j] * hs.g[j];
@@ -205,7 +205,8 @@ __global__ void gmres_solve_small(Hess hs, int k) {
     for (int i = k - 1; i >= 0; --i) {
         double s = hs.g[i];
         for (int l = i + 1; l < k; ++l) s -= hs.H[(size_t)l * (hs.m + 1) + i] * hs.y[l];
-        hs.y[i] = s / hs.H[(size_t)i * (hs.m + 1) + i];
+        const double d = hs.H[(size_t)i * (hs.m + 1) + i];
+        hs.y[i] = d != 0.0 ? s / d : 0.0;
     }
 }
 
@@ -225,10 +226,9 @@ static int nblocks(int64_t len) {
 
 // reductions: results land in ctx->small + RED_OFF
 constexpr int RED_OFF = 0;          // [0, 2*MAXV): h1, h2 ; [2*MAXV]: norm^2
-Hess hess_of(isc_ctx* ctx) {
+Hess hess_at(double* small, int m) {
     Hess h;
-    const int m = ctx->mmax;
-    double* base = ctx->small + 4 * MAXV;
+    double* base = small + 4 * MAXV;
     h.H = base;
     h.cs = h.H + (size_t)(m + 1) * m;
     h.sn = h.cs + m;
@@ -238,6 +238,7 @@ Hess hess_of(isc_ctx* ctx) {
     h.m = m;
     return h;
 }
+Hess hess_of(isc_ctx* ctx) { return hess_at(ctx->small, ctx->mmax); }
 
 // ||v||^2 -> dst (device)
 static void norm2_dev(isc_ctx* ctx, int64_t len, const double* v, double* dst) {
@@ -368,6 +369,179 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
         inf.relres_true = sqrt(rn2) / bnorm;
         if (sqrt(rn2) <= o->rtol * bnorm) st = ISC_OK;
         else ctx->err = "isc_solve: GMRES did not reach the tolerance";
+    }
+    if (info) *info = inf;
+    ISC_HIP(hipGetLastError());
+    return st;
+}
+
+// ---------------------------------------------------------------- precision form
+hipError_t isc_launch_bilu0_apply32(isc_ctx*, const float*, const float*, const float*, float*);
+hipError_t isc_launch_spmv32(isc_ctx*, const float*, const float*, float*);
+
+namespace isc {
+
+// w32 = (float) v, partial = ||w32||^2
+__global__ void __launch_bounds__(256) to_f32_norm(int64_t len, const double* __restrict__ v, float* __restrict__ w,
+                                                   double* __restrict__ partial) {
+    double acc[1] = {0.0};
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
+        const float f = (float)v[t];
+        w[t] = f;
+        acc[0] += (double)f * (double)f;
+    }
+    block_store(acc, 1, partial, gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) to_f64(int64_t len, const float* __restrict__ a, double* __restrict__ b) {
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256)
+        b[t] = (double)a[t];
+}
+
+// z ~= A^-1 v by m_in iterations of FP32 right-preconditioned GMRES from 0
+// (FP32 storage of the basis, the matrix and the ILU factor; FP64 reductions).
+// No host synchronisation: the iteration count is fixed.
+static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, const double* v, double* z, int m_in) {
+    const int64_t len = (int64_t)ctx->n * NU;
+    const int nb = nblocks(len);
+    Hess hi = hess_at(ctx->small32, ctx->inner_max);
+    double* red = ctx->small32 + RED_OFF;
+    float* V32 = ctx->V32;
+    hipLaunchKernelGGL(to_f32_norm, dim3(nb), dim3(256), 0, ctx->stream, len, v, ctx->w32, ctx->partial);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + 2 * MAXV);
+    hipLaunchKernelGGL(gmres_start, dim3(1), dim3(1), 0, ctx->stream, hi, red + 2 * MAXV);
+    hipLaunchKernelGGL((scale_copy<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w32, hi.scal + 1, V32);
+    for (int i = 0; i < m_in; ++i) {
+        const float* Vi = V32 + (size_t)i * len;
+        float* Vn = V32 + (size_t)(i + 1) * len;
+        isc_launch_bilu0_apply32(ctx, A32, D32, Vi, ctx->t32);
+        isc_launch_spmv32(ctx, A32, ctx->t32, ctx->w32);
+        hipLaunchKernelGGL(multidot<float>, dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, i + 1, ctx->w32,
+                           ctx->partial);
+        hipLaunchKernelGGL(reduce_partials, dim3(i + 1), dim3(256), 0, ctx->stream, ctx->partial, nb, red);
+        hipLaunchKernelGGL(update_multidot<float>, dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, i + 1, red,
+                           ctx->w32, ctx->partial);
+        hipLaunchKernelGGL(reduce_partials, dim3(i + 1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + MAXV);
+        hipLaunchKernelGGL(update_norm<float>, dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, i + 1, red + MAXV,
+                           ctx->w32, ctx->partial);
+        hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + 2 * MAXV);
+        hipLaunchKernelGGL(gmres_column, dim3(1), dim3(1), 0, ctx->stream, hi, i, red, red + MAXV, red + 2 * MAXV);
+        hipLaunchKernelGGL((scale_copy<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w32,
+                           hi.scal + 1, Vn);
+    }
+    hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hi, m_in);
+    hipLaunchKernelGGL((lincomb<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, m_in, hi.y,
+                       ctx->t32b, 0);
+    isc_launch_bilu0_apply32(ctx, A32, D32, ctx->t32b, ctx->t32);
+    hipLaunchKernelGGL(to_f64, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->t32, z);
+}
+
+}  // namespace isc
+
+// FP64 flexible GMRES(m) whose preconditioner is the FP32 inner GMRES above.
+// ctx->J32 / ctx->Dinv32 must hold the FP32 matrix and factor.
+isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, double* x, const isc_solve_opts* o,
+                           isc_solve_info* info) {
+    using namespace isc;
+    const int64_t len = (int64_t)ctx->n * NU;
+    const int64_t ldv = len;
+    const int m = o->restart;
+    const int m_in = o->inner_iters;
+    const int nb = nblocks(len);
+    Hess hs = hess_of(ctx);
+    double* red = ctx->small + RED_OFF;
+    isc_solve_info inf{};
+    double bn2;
+    norm2_dev(ctx, len, b, red + 2 * MAXV);
+    ISC_HIP(read_scalar(ctx, red + 2 * MAXV, &bn2));
+    const double bnorm = sqrt(bn2);
+    hipLaunchKernelGGL(zero_kernel, dim3(nb), dim3(256), 0, ctx->stream, len, x);
+    if (bnorm == 0.0) {
+        if (info) *info = inf;
+        return ISC_OK;
+    }
+    if (!std::isfinite(bnorm)) {
+        ctx->err = "isc_solve: right-hand side is not finite";
+        return ISC_ERR_NONFINITE;
+    }
+    isc_status st = ISC_ERR_LINEAR_NOCONV;
+    for (int cyc = 0; cyc < o->max_restarts; ++cyc) {
+        const double* r0 = b;
+        if (cyc > 0) {
+            isc_launch_spmv(ctx, A, x, ctx->tvec);
+            hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, ctx->w,
+                               ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
+                               red + 2 * MAXV);
+            double rn2;
+            ISC_HIP(read_scalar(ctx, red + 2 * MAXV, &rn2));
+            inf.relres_true = sqrt(rn2) / bnorm;
+            if (sqrt(rn2) <= o->rtol * bnorm) { st = ISC_OK; break; }
+            inf.restarts = cyc;
+            r0 = ctx->w;
+        } else {
+            hipLaunchKernelGGL(multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, b, (int64_t)0, 1, b,
+                               ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
+                               red + 2 * MAXV);
+        }
+        hipLaunchKernelGGL(gmres_start, dim3(1), dim3(1), 0, ctx->stream, hs, red + 2 * MAXV);
+        hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, r0, hs.scal + 1,
+                           ctx->V);
+        int jdone = 0;
+        for (int j = 0; j < m; ++j) {
+            double* Vj = ctx->V + (size_t)j * ldv;
+            double* Vn = ctx->V + (size_t)(j + 1) * ldv;
+            double* Zj = ctx->Z + (size_t)j * ldv;
+            int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY);
+            inner_gmres32(ctx, ctx->J32, ctx->Dinv32, Vj, Zj, m_in);
+            isc_prof_end(ctx, tk);
+            tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
+            isc_launch_spmv(ctx, A, Zj, ctx->w);
+            isc_prof_end(ctx, tk);
+            tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
+            hipLaunchKernelGGL(multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, j + 1,
+                               ctx->w, ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(j + 1), dim3(256), 0, ctx->stream, ctx->partial, nb, red);
+            hipLaunchKernelGGL(update_multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv,
+                               j + 1, red, ctx->w, ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(j + 1), dim3(256), 0, ctx->stream, ctx->partial, nb,
+                               red + MAXV);
+            hipLaunchKernelGGL(update_norm<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, j + 1,
+                               red + MAXV, ctx->w, ctx->partial);
+            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
+                               red + 2 * MAXV);
+            hipLaunchKernelGGL(gmres_column, dim3(1), dim3(1), 0, ctx->stream, hs, j, red, red + MAXV,
+                               red + 2 * MAXV);
+            hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w,
+                               hs.scal + 1, Vn);
+            isc_prof_end(ctx, tk);
+            double est;
+            ISC_HIP(read_scalar(ctx, hs.scal + 2, &est));
+            inf.iters++;
+            inf.inner_iters_total += m_in;
+            jdone = j + 1;
+            inf.relres_est = est / bnorm;
+            if (!std::isfinite(est)) {
+                ctx->err = "isc_solve: FGMRES breakdown (non-finite residual estimate)";
+                return ISC_ERR_NONFINITE;
+            }
+            if (est <= o->rtol * bnorm) break;
+        }
+        hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hs, jdone);
+        hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->Z, ldv, jdone,
+                           hs.y, x, 1);
+    }
+    if (st != ISC_OK) {
+        isc_launch_spmv(ctx, A, x, ctx->tvec);
+        hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, ctx->w,
+                           ctx->partial);
+        hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + 2 * MAXV);
+        double rn2;
+        ISC_HIP(read_scalar(ctx, red + 2 * MAXV, &rn2));
+        inf.relres_true = sqrt(rn2) / bnorm;
+        if (sqrt(rn2) <= o->rtol * bnorm) st = ISC_OK;
+        else ctx->err = "isc_solve: FGMRES did not reach the tolerance";
     }
     if (info) *info = inf;
     ISC_HIP(hipGetLastError());

@@ -260,3 +260,48 @@ def test_run_c1_matches_oracle_per_step():
         assert np.all(rel <= 1e-9), (s, rel)
         F = m.residual(ug, host(hist_g[s]), dts_g[s])
         assert m.scaled_norm(F, dts_g[s]) <= 1e-10
+
+
+# ------------------------------------------------------------ precision form
+@pytest.mark.parametrize("name,seed", [("tiny:13x7x5", 31), ("C1", 32)])
+def test_mixed_solve_reaches_fp64_tolerance(name, seed):
+    """FP32 BILU(0) + FP32 inner GMRES inside FP64 FGMRES(30): the FP64 true
+    residual still meets 1e-8 and the solution matches a tight FP64 solve."""
+    from paper_1811_11992_amd import isc
+    wl, m, u, F, J = _decoupled_case(name, seed)
+    st, Jd, Fd, _ = m.decouple(J, F)
+    b = -Fd
+    c = ctx_for(wl, inner_iters=6)
+    x, info, st = c.isc_solve(dev(Jd), dev(b), isc.solve_opts(rtol=1e-8, precision=isc.ISC_MIXED, inner_iters=6))
+    assert st == 0 and info.relres_true <= 1e-8 and info.inner_iters_total == 6 * info.iters
+    xg = host(x)
+    assert np.linalg.norm(b - m.spmv(Jd, xg)) <= 1.01e-8 * np.linalg.norm(b)
+    st, x_ref, _ = m.gmres(Jd, b, rtol=1e-13, max_restarts=60)
+    err = np.abs((xg - x_ref) / COL).max(axis=0)
+    assert np.all(err <= 1e-5 * np.abs(x_ref / COL).max()), err
+
+
+def test_mixed_newton_root_matches_fp64_oracle():
+    from paper_1811_11992_amd import isc
+    wl = I.make_workload("C1")
+    m = O.Model(wl)
+    c = ctx_for(wl, inner_iters=6)
+    lin = isc.solve_opts(precision=isc.ISC_MIXED, inner_iters=6)
+
+    def o_step(u, uo, dt, tol):
+        st, v, info = m.newton_step(u, uo, dt, tol=tol)
+        u[...] = v
+        return st, bool(info.converged)
+
+    def g_step(u, uo, dt, tol):
+        st, info = c.isc_newton_step(u, uo, dt, tol=tol, lin=lin)
+        return st, bool(info.converged)
+
+    hist_o, dts_o = _drive(o_step, lambda a: np.array(a, copy=True), wl.u0, wl.dt, 3)
+    hist_g, dts_g = _drive(g_step, lambda a: dev(a) if isinstance(a, np.ndarray) else a.clone(), wl.u0, wl.dt, 3)
+    assert dts_g == dts_o
+    for s in range(3):
+        ug = host(hist_g[s + 1])
+        rel = np.abs(ug - hist_o[s + 1]).max(axis=1) / np.maximum(np.abs(hist_o[s + 1]).max(axis=1), FLOOR)
+        assert np.all(rel <= 1e-8), (s, rel)
+        assert m.scaled_norm(m.residual(ug, host(hist_g[s]), dts_g[s]), dts_g[s]) <= 1e-10
