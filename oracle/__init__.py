@@ -208,6 +208,16 @@ class Model:
         st = lib().orc_update(self.h, _p(u), _p(np.ascontiguousarray(du, np.float64)))
         return st, u
 
+    def oil_rate(self, u):
+        return lib().orc_oil_rate(self.h, _p(np.ascontiguousarray(u, np.float64)))
+
+    def adjoint_step(self, u_n, u_nm1, dt_n, lam_np1, dt_np1, g_logk, g_A):
+        lam = np.zeros((self.n, 8))
+        lp = None if lam_np1 is None else np.ascontiguousarray(lam_np1, np.float64)
+        st = lib().orc_adjoint_step(self.h, _p(np.ascontiguousarray(u_n)), _p(np.ascontiguousarray(u_nm1)), dt_n,
+                                    _p(lp), None, dt_np1, _p(lam), _p(g_logk), _p(g_A))
+        return st, lam
+
     def newton_step(self, u, u_old, dt, tol=1e-10, restart=30, max_restarts=20, rtol=1e-8):
         u = np.array(u, dtype=np.float64, order="C")
         info = NewtonInfo()

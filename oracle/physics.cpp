@@ -322,7 +322,8 @@ static FaceGeom face_geom(const orc_model& m, int32_t lo, int32_t hi, int dir) {
  * potential; on a tie the lower cell index (lo). */
 template <class S16, class S8>
 void face_flux(const orc_model& m, const FaceGeom& G, const Props<S8>& Plo, const Props<S8>& Phi,
-               const S8& plo, const S8& phi_, const S8& Tlo, const S8& Thi, S16* flow) {
+               const S8& plo, const S8& phi_, const S8& Tlo, const S8& Thi, S16* flow,
+               bool conduction = true) {
     for (int e = 0; e < 8; ++e) flow[e] = S16(0.0);
     S16 dp = lift(plo, 0) - lift(phi_, 8);
     for (int a = 0; a < 3; ++a) {
@@ -340,6 +341,7 @@ void face_flux(const orc_model& m, const FaceGeom& G, const Props<S8>& Plo, cons
             flow[e] = flow[e] + base * lift(U.xi[a][e], off);
         }
     }
+    if (!conduction) return;
     S16 klo = lift(Plo.KT, 0), khi = lift(Phi.KT, 8);
     S16 kh = 2.0 * klo * khi / (klo + khi);
     flow[6] = flow[6] + G.area_over_h * kh * (lift(Tlo, 0) - lift(Thi, 8));
@@ -437,6 +439,76 @@ static int assemble_impl(orc_model& m, const double* u, const double* u_old, dou
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------- adjoint helpers */
+static const orc_perf* producer_at(const orc_model& m, int32_t i) {
+    for (const orc_perf& P : m.perfs)
+        if (P.cell == i && P.kind == 1) return &P;
+    return nullptr;
+}
+
+/* accumulation Jacobian dA_e/du_v at u_i and the producer's oil-phase molar
+ * rate q = WI lambda_o (p - p_wf) for p > p_wf with its gradient */
+void props_acc_grad(const orc_model& m, int32_t i, const double* u_i, double* acc_jac, double* qoil,
+                    double* qoil_grad, double* mob_o_val) {
+    D8 ui[8];
+    for (int v = 0; v < 8; ++v) ui[v] = D8::var(u_i[v], v);
+    Props<D8> P;
+    props(m.fl, m.poro[i], ui, P);
+    for (int e = 0; e < 8; ++e)
+        for (int v = 0; v < 8; ++v) acc_jac[e * 8 + v] = P.acc[e].d[v];
+    *mob_o_val = P.mob[1].v;
+    *qoil = 0.0;
+    for (int v = 0; v < 8; ++v) qoil_grad[v] = 0.0;
+    const orc_perf* W = producer_at(m, i);
+    if (W && u_i[0] > W->bhp) {
+        D8 q = W->wi * P.mob[1] * (ui[0] - W->bhp);
+        *qoil = q.v;
+        for (int v = 0; v < 8; ++v) qoil_grad[v] = q.d[v];
+    }
+}
+
+double cell_oil_rate(const orc_model& m, int32_t i, const double* u_i) {
+    const orc_perf* W = producer_at(m, i);
+    if (!W || !(u_i[0] > W->bhp)) return 0.0;
+    Props<double> P;
+    props(m.fl, m.poro[i], u_i, P);
+    return W->wi * P.mob[1] * (u_i[0] - W->bhp);
+}
+
+/* convective part of the face outflow (proportional to the transmissibility) */
+void face_conv_flux(const orc_model& m, const double* u, int32_t lo, int32_t hi, int dir, double* flow) {
+    double ul[8], uh[8];
+    for (int v = 0; v < 8; ++v) {
+        ul[v] = u[(size_t)v * m.n + lo];
+        uh[v] = u[(size_t)v * m.n + hi];
+    }
+    Props<double> Pl, Ph;
+    props(m.fl, m.poro[lo], ul, Pl);
+    props(m.fl, m.poro[hi], uh, Ph);
+    FaceGeom G = face_geom(m, lo, hi, dir);
+    face_flux<double, double>(m, G, Pl, Ph, ul[0], uh[0], ul[4], uh[4], flow, false);
+    flow[7] = 0.0;
+}
+
+void cell_rates(const orc_model& m, int32_t i, const double* u_i, double* rates) {
+    Props<double> P;
+    props(m.fl, m.poro[i], u_i, P);
+    for (int r = 0; r < 4; ++r) rates[r] = P.rate[r];
+}
+
+/* producer well terms at cell i (the amounts subtracted from the residual) */
+void well_terms(const orc_model& m, int32_t i, const double* u_i, double* W) {
+    for (int e = 0; e < 8; ++e) W[e] = 0.0;
+    const orc_perf* P = producer_at(m, i);
+    if (!P || !(u_i[0] > P->bhp)) return;
+    Props<double> Pr;
+    props(m.fl, m.poro[i], u_i, Pr);
+    for (int a = 0; a < 3; ++a) {
+        double Q = P->wi * Pr.mob[a] * (P->bhp - u_i[0]);
+        for (int e = 0; e < 7; ++e) W[e] += Q * Pr.xi[a][e];
+    }
 }
 
 }  // namespace orc
