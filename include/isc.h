@@ -190,13 +190,22 @@ isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv,
 isc_status isc_update(isc_ctx* ctx, double* u, const double* du /* [N][8] */);
 isc_status isc_scaled_norm(isc_ctx* ctx, const double* F, double dt, double* res_h);
 
-/* Discrete adjoint of one implicit step for J_obj = sum_n dt_n q_oil(u^n):
- * solves (dR^n/du^n)^T lam^n = (dj^n/du^n)^T - (dR^{n+1}/du^n)^T lam^{n+1}
- * and accumulates g_logk += -(lam^n)^T dR^n/dlnk + dj^n/dlnk and
- * g_A_h += -(lam^n)^T dR^n/dA.  lam_np1 may be NULL at the last step. */
+/* Differentiation form.  Objective J_obj = sum_n dt_n q_oil(u^n) with
+ * q_oil(u) = sum over producer perforations of WI lambda_o (p - p_wf) for
+ * p > p_wf (oil-phase molar rate, mol/s); parameters m = (ln k per cell,
+ * frequency factors A_R).  One backward step of the discrete adjoint:
+ *   (dR^n/du^n)^T lam^n = dt_n (dq_oil/du^n)^T + (V/dt_{n+1}) (dA/du(u^n))^T lam^{n+1}
+ * (A: accumulation per bulk volume; lam_np1 = NULL at the last step, then
+ * dt_np1 is ignored), solved on the decoupled system with the transposed
+ * BILU(0)-preconditioned GMRES (opts_h may be NULL: restart 30, 200 cycles,
+ * rtol 1e-12); then g_logk[N] += dt_n dq/dln k - lam^n . dR^n/dln k (device)
+ * and g_A_h[4] += -lam^n . dR^n/dA_R (host).  u_n, u_nm1: [8][N]; lam: [N][8]. */
 isc_status isc_adjoint(isc_ctx* ctx, const double* u_n, const double* u_nm1, double dt_n,
                        const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
-                       double* g_A_h, isc_solve_info* info_h);
+                       double* g_A_h, const isc_solve_opts* opts_h, isc_solve_info* info_h);
+
+/* q_oil(u) defined above, summed over all producers (host output, mol/s). */
+isc_status isc_oil_rate(isc_ctx* ctx, const double* u, double* q_h);
 
 /* Kernel-class timing with HIP events on the context's stream, for
  * profiling.  enable = 1 clears the accumulators and starts timing; every

@@ -24,7 +24,8 @@ isc_status isc_solve_mixed(isc_ctx*, const double* A, const double* b, double* x
 isc_status isc_prepare_mixed_dev(isc_ctx*, const double* A, int32_t* bad_dev);
 isc_status isc_adjoint_impl(isc_ctx*, const double* u_n, const double* u_nm1, double dt_n,
                             const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
-                            double* g_A_h, isc_solve_info* info_h);
+                            double* g_A_h, const isc_solve_opts* o, isc_solve_info* info_h);
+isc_status isc_oil_rate_impl(isc_ctx*, const double* u, double* q_h);
 
 namespace {
 
@@ -276,6 +277,12 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->partial, (size_t)32 * isc::NPART);
     ALLOC(ctx->small, (size_t)4096);
     ALLOC(ctx->flags, (size_t)16);
+    ALLOC(ctx->accJ, (size_t)n * isc::BS);
+    ALLOC(ctx->qg, nv);
+    ALLOC(ctx->qv, (size_t)n);
+    ALLOC(ctx->rates, (size_t)n * 4);
+    ALLOC(ctx->perf_cell, (size_t)std::max(npf, 1));
+    ALLOC(ctx->well_off, (size_t)nwells + 1);
     if (ctx->inner_max > 0) {
         ALLOC(ctx->Z, nv * ctx->mmax);
         ALLOC(ctx->J32, (size_t)ctx->nnzb * isc::BS);
@@ -320,6 +327,18 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         ctx->err = "host to device copy failed";
         return fail(ISC_ERR_HIP);
     }
+    {
+        std::vector<int32_t> pcell, woff(1, 0);
+        for (auto& cells : ctx->well_cells) {
+            pcell.insert(pcell.end(), cells.begin(), cells.end());
+            woff.push_back((int32_t)pcell.size());
+        }
+        if ((!pcell.empty() && !h2d(ctx->perf_cell, pcell.data(), pcell.size() * sizeof(int32_t))) ||
+            !h2d(ctx->well_off, woff.data(), woff.size() * sizeof(int32_t))) {
+            ctx->err = "host to device copy failed";
+            return fail(ISC_ERR_HIP);
+        }
+    }
     if ((s = rebuild_static(ctx)) != ISC_OK) return fail(s);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
         ctx->err = "stream synchronisation failed";
@@ -338,7 +357,8 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->J,       ctx->Dinv,  ctx->du,      ctx->rhs,    ctx->V,       ctx->Z,
                     ctx->w,       ctx->tvec,  ctx->tvec2,   ctx->partial, ctx->small,  ctx->flags,
                     ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,     ctx->t32b,
-                    ctx->small32};
+                    ctx->small32, ctx->accJ,   ctx->qg,     ctx->qv,     ctx->rates,
+                    ctx->perf_cell, ctx->well_off};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (ctx->hscratch) hipHostFree(ctx->hscratch);
@@ -582,9 +602,19 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
 }
 
 isc_status isc_adjoint(isc_ctx* ctx, const double* u_n, const double* u_nm1, double dt_n, const double* lam_np1,
-                       double dt_np1, double* lam_n, double* g_logk, double* g_A_h, isc_solve_info* info_h) {
+                       double dt_np1, double* lam_n, double* g_logk, double* g_A_h, const isc_solve_opts* opts_h,
+                       isc_solve_info* info_h) {
     TRY(check_ctx(ctx));
-    return isc_adjoint_impl(ctx, u_n, u_nm1, dt_n, lam_np1, dt_np1, lam_n, g_logk, g_A_h, info_h);
+    return isc_adjoint_impl(ctx, u_n, u_nm1, dt_n, lam_np1, dt_np1, lam_n, g_logk, g_A_h, opts_h, info_h);
+}
+
+isc_status isc_oil_rate(isc_ctx* ctx, const double* u, double* q_h) {
+    TRY(check_ctx(ctx));
+    if (!u || !q_h) {
+        ctx->err = "isc_oil_rate: invalid argument";
+        return ISC_ERR_ARG;
+    }
+    return isc_oil_rate_impl(ctx, u, q_h);
 }
 
 isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* count_h) {

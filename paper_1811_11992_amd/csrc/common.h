@@ -121,6 +121,13 @@ struct isc_ctx {
     float* t32 = nullptr;
     float* t32b = nullptr;
     double* small32 = nullptr;
+    // adjoint workspace
+    double* accJ = nullptr;         // [N][64] accumulation Jacobian
+    double* qg = nullptr;           // [N][8]  producer oil-rate gradient
+    double* qv = nullptr;           // [N]     producer oil rate
+    double* rates = nullptr;        // [N][4]  reaction rates
+    int32_t* perf_cell = nullptr;   // [npf]
+    int32_t* well_off = nullptr;    // [nwells + 1] perforation ranges
     // host pinned scratch
     double* hscratch = nullptr;     // 64 doubles
     int32_t* hflags = nullptr;
@@ -153,12 +160,12 @@ inline int isc_prof_begin(isc_ctx* ctx, int cls) {
     };
     isc_ctx::Pending p{cls, take(), take()};
     if (!p.a || !p.b) return -1;
-    hipEventRecord(p.a, ctx->stream);
+    (void)hipEventRecord(p.a, ctx->stream);
     ctx->prof_pending.push_back(p);
     return (int)ctx->prof_pending.size() - 1;
 }
 inline void isc_prof_end(isc_ctx* ctx, int tok) {
-    if (tok >= 0) hipEventRecord(ctx->prof_pending[tok].b, ctx->stream);
+    if (tok >= 0) (void)hipEventRecord(ctx->prof_pending[tok].b, ctx->stream);
 }
 inline void isc_prof_drain(isc_ctx* ctx) {
     for (auto& p : ctx->prof_pending) {

@@ -98,6 +98,8 @@ template <class S> struct Cell {
     S mx[NMOB];    // mobility times carried fraction/enthalpy, by mob_slot
     S gam[3];      // specific weights g rho M
     S KT;          // bulk thermal conductivity
+    S rate[4];     // Arrhenius rates r_R per bulk volume
+    S mob_o;       // oil mobility k_ro rho_o / mu_o
 };
 
 // Secondary variables of one cell.  u = (p, x_LO, y_O2, y_CO2, T, S_w, S_g, C_c).
@@ -210,6 +212,8 @@ template <class S> __device__ void cell_eval(const isc_fluid& f, double phi_ref,
         rr[3] = (f.Afreq[3] * xexp(-ER3 * invT)) * po2 * cc;
     }
 #pragma unroll
+    for (int r = 0; r < 4; ++r) c.rate[r] = rr[r];
+#pragma unroll
     for (int e = 0; e < 8; ++e) c.src[e] = mk<S>(0.0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -227,6 +231,7 @@ template <class S> __device__ void cell_eval(const isc_fluid& f, double phi_ref,
     {
         const S mw = krw * rho[0] / mu[0];
         const S mo = kro * rho[1] / mu[1];
+        c.mob_o = mo;
         const S mg = krg * rho[2] / mu[2];
         c.mx[mob_slot(0, 0)] = mw;
         c.mx[mob_slot(0, 6)] = mw * H[0];
@@ -314,7 +319,46 @@ __global__ void __launch_bounds__(256) props_kernel(
     put(out + PL_KT, c.KT, k);
 }
 
+// Adjoint inputs at state u, eight lanes per cell (lane k carries d/du_k):
+// accJ[i][e][k] = dA_e/du_k (accumulation per bulk volume), the producer's
+// oil-phase molar rate q = WI lambda_o (p - p_wf) for p > p_wf with dq/du_k,
+// and the reaction rates.
+__global__ void __launch_bounds__(256) accgrad_kernel(
+    int32_t n, const double* __restrict__ u, const double* __restrict__ poro, const int32_t* __restrict__ well_slot,
+    const double* __restrict__ perf, const isc_fluid* __restrict__ fl, double* __restrict__ accJ,
+    double* __restrict__ qg, double* __restrict__ qv, double* __restrict__ rates) {
+    const int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
+    const int k = threadIdx.x & 7;
+    if (i >= n) return;
+    G1 ug[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ug[q] = G1{u[(size_t)q * n + i], q == k ? 1.0 : 0.0};
+    Cell<G1> c;
+    cell_eval<G1>(*fl, poro[i], ug, c);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) accJ[(size_t)i * 64 + e * 8 + k] = c.acc[e].d;
+    G1 q = G1{0.0, 0.0};
+    const int32_t ws = well_slot[i];
+    if (ws >= 0) {
+        const double* pf = perf + (size_t)ws * PERF_W;
+        if (pf[0] == 1.0 && ug[0].v > pf[2]) q = (pf[1] * c.mob_o) * (ug[0] - pf[2]);
+    }
+    qg[(size_t)i * 8 + k] = q.d;
+    if (k == 0) {
+        qv[i] = q.v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rates[(size_t)i * 4 + r] = c.rate[r].v;
+    }
+}
+
 }  // namespace isc
+
+hipError_t isc_launch_accgrad(isc_ctx* ctx, const double* u) {
+    const int blocks = (int)(((int64_t)ctx->n * 8 + 255) / 256);
+    hipLaunchKernelGGL(isc::accgrad_kernel, dim3(blocks), dim3(256), 0, ctx->stream, ctx->n, u, ctx->poro,
+                       ctx->well_slot, ctx->perf, ctx->fluid_d, ctx->accJ, ctx->qg, ctx->qv, ctx->rates);
+    return hipGetLastError();
+}
 
 hipError_t isc_launch_props(isc_ctx* ctx, const double* u, const double* u_old, double dt) {
     const double vol = ctx->g.dx * ctx->g.dy * ctx->g.dz;

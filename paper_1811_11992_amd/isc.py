@@ -72,13 +72,16 @@ def lib():
         L.isc_bilu0_apply.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.isc_update.argtypes = [_vp, _vp, _vp]
         L.isc_scaled_norm.argtypes = [_vp, _vp, _f64, ctypes.POINTER(_f64)]
-        L.isc_adjoint.argtypes = [_vp, _vp, _vp, _f64, _vp, _f64, _vp, _vp, _vp, ctypes.POINTER(SolveInfo)]
+        L.isc_adjoint.argtypes = [_vp, _vp, _vp, _f64, _vp, _f64, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
+                                  ctypes.POINTER(SolveInfo)]
+        L.isc_oil_rate.argtypes = [_vp, _vp, ctypes.POINTER(_f64)]
         L.isc_profile.argtypes = [_vp, _i32, _vp, _vp]
         L.isc_last_error.argtypes = [_vp]
         L.isc_last_error.restype = ctypes.c_char_p
         for name in ("isc_create", "isc_destroy", "isc_set_params", "isc_bcsr_pattern", "isc_assemble",
                      "isc_decouple", "isc_solve", "isc_newton_step", "isc_spmv", "isc_bilu0",
-                     "isc_bilu0_apply", "isc_update", "isc_scaled_norm", "isc_adjoint", "isc_profile"):
+                     "isc_bilu0_apply", "isc_update", "isc_scaled_norm", "isc_adjoint", "isc_profile",
+                     "isc_oil_rate"):
             getattr(L, name).restype = _i32
         _LIB = L
     return _LIB
@@ -197,13 +200,20 @@ class Context:
         self._check(lib().isc_scaled_norm(self.h, _ptr(F), dt, ctypes.byref(r)))
         return r.value
 
-    def isc_adjoint(self, u_n, u_nm1, dt_n, lam_np1, dt_np1, lam_n, g_logk, g_A):
+    def isc_adjoint(self, u_n, u_nm1, dt_n, lam_np1, dt_np1, lam_n, g_logk, g_A, opts: SolveOpts | None = None):
+        """One backward step; g_logk (device) and the returned g_A are accumulated."""
         info = SolveInfo()
         a = (ctypes.c_double * 4)(*[float(x) for x in g_A])
+        o = opts or solve_opts(restart=30, max_restarts=200, rtol=1e-12)
         st = lib().isc_adjoint(self.h, _ptr(u_n), _ptr(u_nm1), dt_n, _ptr(lam_np1), dt_np1, _ptr(lam_n),
-                               _ptr(g_logk), a, ctypes.byref(info))
+                               _ptr(g_logk), a, ctypes.byref(o), ctypes.byref(info))
         self._check(st)
         return [a[k] for k in range(4)], info
+
+    def isc_oil_rate(self, u):
+        q = _f64()
+        self._check(lib().isc_oil_rate(self.h, _ptr(u), ctypes.byref(q)))
+        return q.value
 
 
 PROF_CLASSES = ("spmv", "ilu_apply", "assemble", "decouple", "ilu_factor", "krylov")
