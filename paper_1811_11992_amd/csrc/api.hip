@@ -228,6 +228,17 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     std::vector<int32_t> lvl_rows(n), fillp(ctx->lvl_off_h.begin(), ctx->lvl_off_h.end() - 1);
     for (int32_t i = 0; i < n; ++i) lvl_rows[fillp[i % nx + (i / nx) % ny + i / nxy]++] = i;
 
+    // chunks of at most 8 rows of one level (sync-free sweeps)
+    std::vector<int32_t> chf, chb;
+    for (int32_t s = 0; s < ctx->nlev; ++s)
+        for (int32_t o = ctx->lvl_off_h[s]; o < ctx->lvl_off_h[s + 1]; o += 8)
+            for (int32_t q = 0; q < 8; ++q) chf.push_back(o + q < ctx->lvl_off_h[s + 1] ? lvl_rows[o + q] : -1);
+    for (int32_t s = ctx->nlev - 1; s >= 0; --s)
+        for (int32_t o = ctx->lvl_off_h[s]; o < ctx->lvl_off_h[s + 1]; o += 8)
+            for (int32_t q = 0; q < 8; ++q) chb.push_back(o + q < ctx->lvl_off_h[s + 1] ? lvl_rows[o + q] : -1);
+    ctx->nchunk = (int32_t)(chf.size() / 8);
+    if (const char* e = getenv("ISC_LEVEL_SWEEPS")) ctx->syncfree = !(e[0] == '1');
+
     // wells
     int32_t npf = 0;
     for (int32_t w = 0; w < nwells; ++w) {
@@ -282,6 +293,11 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->qv, (size_t)n);
     ALLOC(ctx->rates, (size_t)n * 4);
     ALLOC(ctx->perf_cell, (size_t)std::max(npf, 1));
+    ALLOC(ctx->chunks_fwd, chf.size());
+    ALLOC(ctx->chunks_bwd, chb.size());
+    ALLOC(ctx->sweep64, (size_t)n * isc::NU);
+    ALLOC(ctx->sweep32, (size_t)n * isc::NU);
+    ALLOC(ctx->ticket, (size_t)1);
     ALLOC(ctx->well_off, (size_t)nwells + 1);
     if (ctx->inner_max > 0) {
         ALLOC(ctx->Z, nv * ctx->mmax);
@@ -316,6 +332,14 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         hipStreamSynchronize(ctx->stream) != hipSuccess) {
         ctx->err = "cannot read logk/poro (device pointers expected)";
         return fail(ISC_ERR_ARG);
+    }
+    if (isc_reset_sweep_buffers(ctx) != hipSuccess ||
+        hipMemsetAsync(ctx->ticket, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess ||
+        hipMemsetAsync(ctx->flags, 0, 16 * sizeof(int32_t), ctx->stream) != hipSuccess ||
+        !h2d(ctx->chunks_fwd, chf.data(), chf.size() * sizeof(int32_t)) ||
+        !h2d(ctx->chunks_bwd, chb.data(), chb.size() * sizeof(int32_t))) {
+        ctx->err = "initialising the sweep schedule failed";
+        return fail(ISC_ERR_HIP);
     }
     if (!h2d(ctx->fluid_d, &ctx->fluid_h, sizeof(isc_fluid)) ||
         !h2d(ctx->logk, ctx->logk_h.data(), (size_t)n * sizeof(double)) ||
@@ -358,7 +382,8 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->w,       ctx->tvec,  ctx->tvec2,   ctx->partial, ctx->small,  ctx->flags,
                     ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,     ctx->t32b,
                     ctx->small32, ctx->accJ,   ctx->qg,     ctx->qv,     ctx->rates,
-                    ctx->perf_cell, ctx->well_off};
+                    ctx->perf_cell, ctx->well_off, ctx->chunks_fwd, ctx->chunks_bwd, ctx->sweep64,
+                    ctx->sweep32, ctx->ticket};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (ctx->hscratch) hipHostFree(ctx->hscratch);
@@ -446,7 +471,7 @@ isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv,
         return ISC_ERR_ARG;
     }
     ISC_HIP(isc_launch_bilu0_apply(ctx, Jdec, Dinv, r, z));
-    return ISC_OK;
+    return isc_check_sweeps(ctx);
 }
 
 isc_status isc_spmv(isc_ctx* ctx, const double* Jdec, const double* x, double* y) {

@@ -96,6 +96,17 @@ struct isc_ctx {
     int32_t nlev = 0;
     std::vector<int32_t> lvl_off_h;
     int32_t* lvl_rows = nullptr;
+    // sync-free triangular sweeps: chunks of <= 8 rows of one level, in level
+    // order (forward) and reverse level order (backward); tickets order the
+    // workgroups
+    bool syncfree = true;
+    int32_t nchunk = 0;
+    int32_t* chunks_fwd = nullptr;
+    int32_t* chunks_bwd = nullptr;
+    double* sweep64 = nullptr;   // private forward-sweep buffers, sentinel-filled between sweeps
+    float* sweep32 = nullptr;
+    unsigned long long* ticket = nullptr;
+    unsigned long long ticket_base = 0;
     // workspace
     double* payload = nullptr;      // [N][PL]
     double* F = nullptr;            // [N][8]
@@ -178,6 +189,32 @@ inline void isc_prof_drain(isc_ctx* ctx) {
         ctx->prof_pool.push_back(p.b);
     }
     ctx->prof_pending.clear();
+}
+
+hipError_t isc_reset_sweep_buffers(isc_ctx* ctx);
+
+// Slot of ctx->flags raised when a sync-free triangular sweep gave up waiting.
+constexpr int ISC_FLAG_SWEEP = 3;
+
+// Reads (and clears) the sweep error flag; waits for the stream.
+inline isc_status isc_check_sweeps(isc_ctx* ctx) {
+    if (hipMemcpyAsync(ctx->hflags + ISC_FLAG_SWEEP, ctx->flags + ISC_FLAG_SWEEP, sizeof(int32_t),
+                       hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        ctx->err = "reading the sweep status failed";
+        return ISC_ERR_HIP;
+    }
+    if (ctx->hflags[ISC_FLAG_SWEEP] != 0) {
+        ctx->hflags[ISC_FLAG_SWEEP] = 0;
+        (void)hipMemcpyAsync(ctx->flags + ISC_FLAG_SWEEP, ctx->hflags + ISC_FLAG_SWEEP, sizeof(int32_t),
+                             hipMemcpyHostToDevice, ctx->stream);
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)isc_reset_sweep_buffers(ctx);
+        (void)hipStreamSynchronize(ctx->stream);
+        ctx->err = "triangular sweep: a row waited too long for its predecessors";
+        return ISC_ERR_HIP;
+    }
+    return ISC_OK;
 }
 
 // error helpers for host code

@@ -343,6 +343,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
             jdone = j + 1;
             inf.relres_est = est / bnorm;
             if (!std::isfinite(est)) {
+                if (isc_check_sweeps(ctx) != ISC_OK) return ISC_ERR_HIP;
                 ctx->err = "isc_solve: GMRES breakdown (non-finite residual estimate)";
                 return ISC_ERR_NONFINITE;
             }
@@ -372,6 +373,10 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
     }
     if (info) *info = inf;
     ISC_HIP(hipGetLastError());
+    {
+        const isc_status sw = isc_check_sweeps(ctx);
+        if (sw != ISC_OK) return sw;
+    }
     return st;
 }
 
@@ -523,6 +528,7 @@ isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, doubl
             jdone = j + 1;
             inf.relres_est = est / bnorm;
             if (!std::isfinite(est)) {
+                if (isc_check_sweeps(ctx) != ISC_OK) return ISC_ERR_HIP;
                 ctx->err = "isc_solve: FGMRES breakdown (non-finite residual estimate)";
                 return ISC_ERR_NONFINITE;
             }
@@ -545,5 +551,9 @@ isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, doubl
     }
     if (info) *info = inf;
     ISC_HIP(hipGetLastError());
+    {
+        const isc_status sw = isc_check_sweeps(ctx);
+        if (sw != ISC_OK) return sw;
+    }
     return st;
 }

@@ -200,7 +200,206 @@ __global__ void __launch_bounds__(256) spmv_unitdiag(int32_t n, const int32_t* _
     y[(size_t)i * NU + r] = (TV)acc;
 }
 
+// ------------------------------------------------------------ sync-free sweeps
+// One kernel per triangular sweep.  Rows are grouped in chunks of at most 8
+// rows of the same hyperplane level (one wavefront per chunk, eight lanes per
+// row), chunks are listed level by level, and each workgroup takes a ticket
+// in that order, so every row a wavefront waits for belongs to a wavefront
+// that is already running or finished.  No flags: the sweep's output buffer
+// holds a NaN sentinel before the sweep, a row's result is published with
+// device-coherent 64-/32-bit stores, and a consumer lane polls its element of
+// each predecessor with device-coherent loads until the sentinel is gone.
+// The forward sweep writes into a private buffer and sets the rows of z back
+// to the sentinel; the backward sweep reads the private buffer, restores its
+// sentinel for the next forward sweep, and writes z.  Every wait is bounded in
+// wall-clock time and stops early once any wait has timed out (error flag), so
+// a sweep always terminates.
+constexpr uint64_t SENTINEL64 = 0x7FF4DEC0DE5EED01ull;   // NaN payload no arithmetic produces
+constexpr uint32_t SENTINEL32 = 0x7FA5EED1u;
+constexpr uint64_t WAIT_TICKS = 1ull << 24;               // ~0.17 s of the 100 MHz wall clock
+
+template <class TV> struct Bits;
+template <> struct Bits<double> {
+    using U = unsigned long long;
+    static constexpr U sentinel = SENTINEL64;
+};
+template <> struct Bits<float> {
+    using U = unsigned int;
+    static constexpr U sentinel = SENTINEL32;
+};
+
+template <class TV> __device__ __forceinline__ TV from_bits(typename Bits<TV>::U u) {
+    return __builtin_bit_cast(TV, u);
+}
+template <class TV> __device__ __forceinline__ void publish(TV* p, TV v) {
+    __hip_atomic_store(reinterpret_cast<typename Bits<TV>::U*>(p), __builtin_bit_cast(typename Bits<TV>::U, v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class TV> __device__ __forceinline__ typename Bits<TV>::U peek(const TV* p) {
+    return __hip_atomic_load(reinterpret_cast<const typename Bits<TV>::U*>(p), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+// Given a first read u of *p, polls *p until it no longer holds the sentinel
+// (bounded in time); returns the value, or 0 after a timeout.
+template <class TV> __device__ __forceinline__ TV await_value(const TV* p, typename Bits<TV>::U u, int32_t* err) {
+    if (u != Bits<TV>::sentinel) return from_bits<TV>(u);
+    const uint64_t t0 = wall_clock64();
+    for (int k = 1;; ++k) {
+        __builtin_amdgcn_s_sleep(1);
+        u = peek(p);
+        if (u != Bits<TV>::sentinel) return from_bits<TV>(u);
+        if ((k & 63) == 0) {
+            if (wall_clock64() - t0 > WAIT_TICKS) {
+                atomicOr(err, 1);
+                return TV(0);
+            }
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return TV(0);
+        }
+    }
+}
+
+__device__ __forceinline__ int32_t take_ticket(unsigned long long* ticket, unsigned long long base) {
+    __shared__ int32_t s_t;
+    if (threadIdx.x == 0) s_t = (int32_t)(atomicAdd(ticket, 1ULL) - base);
+    __syncthreads();
+    return s_t;
+}
+
+// forward: v_i = D_i^-1 (r_i - sum_{k lower} A_ik v_k); v is the private
+// buffer (sentinel on entry), z_i is reset to the sentinel for the backward sweep
+template <class T, class TV>
+__global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
+    const int32_t* __restrict__ chunks, int32_t nchunk, int32_t nx, int32_t ny, const int32_t* __restrict__ row_ptr,
+    const T* __restrict__ A, const T* __restrict__ Dinv, const TV* __restrict__ rin, TV* v, TV* __restrict__ z,
+    unsigned long long* ticket, unsigned long long base, int32_t* err) {
+    const int32_t ch = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
+    if (ch >= nchunk) return;
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 7;
+    const int gbase = threadIdx.x & 56;
+    const int32_t i = chunks[(size_t)ch * 8 + (lane >> 3)];
+    const bool act = i >= 0;
+    const int32_t ii = act ? i : 0;
+    const int32_t nxy = nx * ny;
+    const int32_t ix = ii % nx, iy = (ii / nx) % ny, iz = ii / nxy;
+    const int32_t lower[3] = {iz > 0 ? ii - nxy : -1, iy > 0 ? ii - nx : -1, ix > 0 ? ii - 1 : -1};
+    // everything that does not depend on other rows is loaded first, without
+    // branches (a missing neighbour reads the row's first block and is masked)
+    double arow[3][8];
+    const int32_t b0 = row_ptr[ii];
+    int32_t blk = b0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const T* a = A + (size_t)(lower[q] >= 0 ? blk : b0) * BS + r * 8;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double x = (double)a[c];
+            arow[q][c] = lower[q] >= 0 ? x : 0.0;
+        }
+        blk += lower[q] >= 0;
+    }
+    double drow[8];
+    const T* d = Dinv + (size_t)ii * BS + r * 8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) drow[c] = (double)d[c];
+    double acc = act ? (double)rin[(size_t)ii * NU + r] : 0.0;
+    if (act) z[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
+    // first reads of the three predecessors go out together
+    typename Bits<TV>::U first[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) first[q] = (act && lower[q] >= 0) ? peek(v + (size_t)lower[q] * NU + r) : 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double xk =
+            (act && lower[q] >= 0) ? (double)await_value(v + (size_t)lower[q] * NU + r, first[q], err) : 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc -= arow[q][c] * __shfl(xk, gbase + c);
+    }
+    double out = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) out += drow[c] * __shfl(acc, gbase + c);
+    if (act) publish(v + (size_t)ii * NU + r, (TV)out);
+}
+
+// backward: z_i = v_i - D_i^-1 sum_{j upper} A_ij z_j; z holds the sentinel on
+// entry, v_i is reset to the sentinel for the next forward sweep
+template <class T, class TV>
+__global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
+    const int32_t* __restrict__ chunks, int32_t nchunk, int32_t nx, int32_t ny, int32_t nz,
+    const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ v,
+    TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
+    const int32_t ch = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
+    if (ch >= nchunk) return;
+    const int lane = threadIdx.x & 63;
+    const int r = lane & 7;
+    const int gbase = threadIdx.x & 56;
+    const int32_t i = chunks[(size_t)ch * 8 + (lane >> 3)];
+    const bool act = i >= 0;
+    const int32_t ii = act ? i : 0;
+    const int32_t nxy = nx * ny;
+    const int32_t ix = ii % nx, iy = (ii / nx) % ny, iz = ii / nxy;
+    const int32_t upper[3] = {ix + 1 < nx ? ii + 1 : -1, iy + 1 < ny ? ii + nx : -1, iz + 1 < nz ? ii + nxy : -1};
+    double arow[3][8];
+    const int32_t b0 = diag_pos[ii];
+    int32_t blk = b0 + 1;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const T* a = A + (size_t)(upper[q] >= 0 ? blk : b0) * BS + r * 8;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const double x = (double)a[c];
+            arow[q][c] = upper[q] >= 0 ? x : 0.0;
+        }
+        blk += upper[q] >= 0;
+    }
+    double drow[8];
+    const T* d = Dinv + (size_t)ii * BS + r * 8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) drow[c] = (double)d[c];
+    const double vi = act ? (double)v[(size_t)ii * NU + r] : 0.0;
+    if (act) v[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
+    double acc = 0.0;
+    typename Bits<TV>::U first[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) first[q] = (act && upper[q] >= 0) ? peek(z + (size_t)upper[q] * NU + r) : 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double xj =
+            (act && upper[q] >= 0) ? (double)await_value(z + (size_t)upper[q] * NU + r, first[q], err) : 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc += arow[q][c] * __shfl(xj, gbase + c);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) s += drow[c] * __shfl(acc, gbase + c);
+    if (act) publish(z + (size_t)ii * NU + r, (TV)(vi - s));
+}
+
+template <class U>
+__global__ void fill_bits(int64_t len, U* p, U pattern) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < len) p[k] = pattern;
+}
+
 }  // namespace isc
+
+namespace isc {
+template <class TV> TV* sweep_buffer(isc_ctx* ctx);
+template <> double* sweep_buffer<double>(isc_ctx* ctx) { return ctx->sweep64; }
+template <> float* sweep_buffer<float>(isc_ctx* ctx) { return ctx->sweep32; }
+}  // namespace isc
+
+// Fills the private sweep buffers with the sentinel (at creation and after a
+// sweep gave up, when they may hold stale values).
+hipError_t isc_reset_sweep_buffers(isc_ctx* ctx) {
+    const int64_t len = (int64_t)ctx->n * isc::NU;
+    const int nb = (int)((len + 255) / 256);
+    hipLaunchKernelGGL((isc::fill_bits<unsigned long long>), dim3(nb), dim3(256), 0, ctx->stream, len,
+                       reinterpret_cast<unsigned long long*>(ctx->sweep64), (unsigned long long)isc::SENTINEL64);
+    hipLaunchKernelGGL((isc::fill_bits<unsigned int>), dim3(nb), dim3(256), 0, ctx->stream, len,
+                       reinterpret_cast<unsigned int*>(ctx->sweep32), (unsigned int)isc::SENTINEL32);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------------ launchers
 template <class T>
@@ -216,6 +415,19 @@ hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t*
 
 template <class T, class TV>
 hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, const TV* r, TV* z) {
+    if (ctx->syncfree) {
+        TV* v = isc::sweep_buffer<TV>(ctx);
+        const int32_t nwg = (ctx->nchunk + 3) / 4;
+        hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(nwg), dim3(256), 0, ctx->stream, ctx->chunks_fwd,
+                           ctx->nchunk, ctx->g.nx, ctx->g.ny, ctx->row_ptr, A, Dinv, r, v, z, ctx->ticket,
+                           ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+        ctx->ticket_base += (unsigned long long)nwg;
+        hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV>), dim3(nwg), dim3(256), 0, ctx->stream, ctx->chunks_bwd,
+                           ctx->nchunk, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->diag_pos, A, Dinv, v, z, ctx->ticket,
+                           ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+        ctx->ticket_base += (unsigned long long)nwg;
+        return hipGetLastError();
+    }
     for (int32_t s = 0; s < ctx->nlev; ++s) {
         const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
         hipLaunchKernelGGL((isc::bilu0_fwd_level<T, TV>), dim3((cnt + 31) / 32), dim3(256), 0, ctx->stream,

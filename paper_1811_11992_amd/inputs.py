@@ -359,17 +359,29 @@ def lognormal_logk(rng, size, sigma, mean_md=500.0):
 
 
 def _air_rate(n_cells_pv: float) -> float:
-    """Total air injection: 1% of the pore volume per day at RHO_G0, mol/s."""
+    """Air injection of 1% of a pore volume per day at RHO_G0, mol/s."""
     return 0.01 * n_cells_pv * RHO_G0 / DAY
+
+
+# Pore volume one injector perforation serves: a 20 x 20 pattern element of one
+# layer.  Sizing the injection per perforation keeps the volume injected per
+# step into a perforated cell (about 0.4 of its pore volume at 0.1 day) the
+# same on every grid; sizing it on the whole reservoir would push tens of pore
+# volumes per step through the injector cells of the 2M- and 9.6M-cell grids.
+PATTERN_CELLS = 400
+
+
+def _perf_air_rate(mean_cell_pv: float, nperf: int) -> float:
+    return _air_rate(PATTERN_CELLS * mean_cell_pv) * nperf
 
 
 AIR = (0.0, 0.0, 0.0, 0.21, 0.0, 0.79, 0.0)
 
 
-def _wells_corner_columns(nx, ny, nz, pore_volume, n_inj=1):
+def _wells_corner_columns(nx, ny, nz, mean_cell_pv):
     inj = [cell_index(nx, ny, 0, 0, iz) for iz in range(nz)]
     prod = [cell_index(nx, ny, nx - 1, ny - 1, iz) for iz in range(nz)]
-    return [dict(kind=WELL_RATE_INJECTOR, cells=inj, target=_air_rate(pore_volume),
+    return [dict(kind=WELL_RATE_INJECTOR, cells=inj, target=_perf_air_rate(mean_cell_pv, len(inj)),
                  T_inj=T0, z_inj=AIR),
             dict(kind=WELL_BHP_PRODUCER, cells=prod, target=P0)]
 
@@ -423,8 +435,8 @@ def make_workload(name: str, nsteps: int | None = None) -> Workload:
         logk = np.repeat(layer, nx * ny)
         kvkh = 0.1
         poro = rng.uniform(0.25, 0.35, n)
-        pv = float(poro.sum()) * dx * dy * dz
-        wells = _wells_corner_columns(nx, ny, nz, pv)
+        cpv = float(poro.mean()) * dx * dy * dz
+        wells = _wells_corner_columns(nx, ny, nz, cpv)
         u0 = initial_state(nx, ny, nz, [0])
         steps = 50 if name == "C2" else 20
     elif name in ("C3", "C5"):
@@ -439,14 +451,14 @@ def make_workload(name: str, nsteps: int | None = None) -> Workload:
         logk = logk3.reshape(-1).copy()
         kvkh = 0.1
         poro = rng.uniform(0.25, 0.35, n)
-        pv = float(poro.sum()) * dx * dy * dz
+        cpv = float(poro.mean()) * dx * dy * dz
         if name == "C3":
-            wells = _wells_corner_columns(nx, ny, nz, pv)
+            wells = _wells_corner_columns(nx, ny, nz, cpv)
             ign = [0]
         else:
             injxy = [(100, 100), (100, 300), (300, 100), (300, 300)]
             prodxy = [(a, b) for a in (0, 200, 399) for b in (0, 200, 399)]
-            q = _air_rate(pv) / len(injxy)
+            q = _perf_air_rate(cpv, nz)
             wells = [dict(kind=WELL_RATE_INJECTOR,
                           cells=[cell_index(nx, ny, a, b, iz) for iz in range(nz)],
                           target=q, T_inj=T0, z_inj=AIR) for a, b in injxy]
