@@ -121,7 +121,7 @@ struct isc_ctx {
     double* w = nullptr;            // [N*8]
     double* tvec = nullptr;         // [N*8]
     double* tvec2 = nullptr;        // [N*8]
-    double* partial = nullptr;      // [(mmax+2) * NPART]
+    double* partial = nullptr;      // [64][NPART] block partial sums
     double* small = nullptr;        // device scalars: h, givens, g, y ...
     int32_t* flags = nullptr;       // device ints: [0] error/bad cell
     // FP32 copies (mixed precision)

@@ -1,13 +1,20 @@
 #include <cmath>
 // Restarted GMRES with right preconditioning for the decoupled system.
 //
-// Orthogonalisation is classical Gram-Schmidt applied twice (CGS2): every
-// pass needs all inner products of one vector with the basis at once, which
-// is one streaming multi-dot over the basis instead of j dependent
-// reductions.  Reductions are two-stage with a fixed block count and a fixed
-// order, so results are bitwise reproducible.  The Hessenberg matrix, the
-// Givens rotations and the least-squares solution stay on the device; the
-// host reads one scalar (the residual estimate) per iteration.
+// FP64 solver: classical Gram-Schmidt with one reorthogonalisation, the
+// reorthogonalisation delayed by one iteration (DCGS2, after Swirydowicz,
+// Langou, Ananthan, Yang and Thomas, "Low synchronization Gram-Schmidt and
+// GMRES algorithms").  The Krylov vector of step j is formed from the lagged,
+// once-projected vector u_j; the next iteration's single multi-dot pass gives
+// both the reorthogonalisation coefficients of u_j and the projections of
+// w = A M^-1 u_j, the Arnoldi relation corrects the Hessenberg column, and one
+// fused pass writes q_j and u_{j+1}.  That is two passes over the basis per
+// iteration instead of three, with CGS2's orthogonality.
+// Flexible solver (precision form): CGS2 as two fused passes plus a norm pass.
+// Reductions are two-stage with a fixed block count and a fixed order, so
+// results are bitwise reproducible.  The Hessenberg matrix, the Givens
+// rotations and the least-squares solution stay on the device; the host reads
+// one scalar (the residual estimate) per iteration.
 #include "common.h"
 
 namespace isc {
@@ -210,6 +217,180 @@ __global__ void gmres_solve_small(Hess hs, int k) {
     }
 }
 
+// ------------------------------------------------------------------ DCGS2
+// Vectors are read as double2 (lengths are multiples of 8 doubles).
+// Row layout of the dot results: r (r <= j) = <X_r, u>, MAXV + r = <X_r, w>,
+// with X_r = Q_r for r < j and X_j = u.
+__device__ __forceinline__ void block_store_dcgs(const double* a1, double au, const double* a2, double aw, int j,
+                                                 bool hw, double* partial, int nblk) {
+    __shared__ double red[4][2 * MAXV];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+        if (k < j) {
+            const double s1 = wave_sum(a1[k]);
+            if (lane == 0) red[wv][k] = s1;
+            if (hw) {
+                const double s2 = wave_sum(a2[k]);
+                if (lane == 0) red[wv][MAXV + k] = s2;
+            }
+        }
+    }
+    const double su = wave_sum(au);
+    if (lane == 0) red[wv][j] = su;
+    if (hw) {
+        const double sw = wave_sum(aw);
+        if (lane == 0) red[wv][MAXV + j] = sw;
+    }
+    __syncthreads();
+    const int nrow = hw ? 2 * (j + 1) : j + 1;
+    for (int r = threadIdx.x; r < nrow; r += 256) {
+        const int row = r <= j ? r : MAXV + (r - j - 1);
+        partial[(size_t)row * nblk + blockIdx.x] = (red[0][row] + red[1][row]) + (red[2][row] + red[3][row]);
+    }
+}
+
+// One pass: <Q_k, u>, <Q_k, w> (k < j), <u, u>, <u, w>; w may be null.
+__global__ void __launch_bounds__(256) dcgs2_dots(int64_t len2, const double2* __restrict__ Q, int64_t ldv2, int j,
+                                                  const double2* __restrict__ u, const double2* __restrict__ w,
+                                                  double* __restrict__ partial) {
+    double a1[MAXV], a2[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) { a1[k] = 0.0; a2[k] = 0.0; }
+    double au = 0.0, aw = 0.0;
+    const bool hw = w != nullptr;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len2; t += (int64_t)gridDim.x * 256) {
+        const double2 uv = u[t];
+        const double2 wv = hw ? w[t] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k) {
+            if (k < j) {
+                const double2 q = Q[(size_t)k * ldv2 + t];
+                a1[k] += q.x * uv.x + q.y * uv.y;
+                a2[k] += q.x * wv.x + q.y * wv.y;
+            }
+        }
+        au += uv.x * uv.x + uv.y * uv.y;
+        aw += uv.x * wv.x + uv.y * wv.y;
+    }
+    block_store_dcgs(a1, au, a2, aw, j, hw, partial, gridDim.x);
+}
+
+// out[row] = sum over blocks of partial[row], rows as in block_store_dcgs
+__global__ void __launch_bounds__(256) reduce_rows_dcgs(const double* __restrict__ partial, int nblk, int j,
+                                                        double* __restrict__ out) {
+    __shared__ double red[4];
+    const int r = blockIdx.x;
+    const int row = r <= j ? r : MAXV + (r - j - 1);
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) s += partial[(size_t)row * nblk + b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[row] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Device state of the delayed scheme: the unrotated Hessenberg matrix, the
+// first-pass coefficients of the pending column and (omega, zeta).
+struct Dcgs {
+    double* Hraw;    // [(m+1) x m], column-major
+    double* hprev;   // [m+1]
+    double* omz;     // [0] omega_j, [1] zeta_j
+};
+
+// Iteration j (one thread).  c holds the dots of this iteration.  Finishes
+// the reorthogonalisation of u_j (s = Q_j^T u_j, omega = ||u_j - Q_j s|| by
+// Pythagoras), completes Hessenberg column j-1 and its Givens rotation
+// (residual estimate of a j-column solution in scal[2]), then forms the
+// first-pass coefficients of A M^-1 q_j from those of w = A M^-1 u_j:
+//   zeta = q_j^T w = (u_j^T w - s^T z) / omega,  z = Q_j^T w,
+//   h    = ([z; zeta] - H_j s) / omega           (H_j: columns 0..j-1).
+// scal[4] = 1 flags omega = 0 (u_j in the span of Q_j).
+__global__ void dcgs2_step(Hess hs, Dcgs d, int j, int last, const double* __restrict__ c) {
+    const int m = hs.m;
+    const int ld = m + 1;
+    double ss = 0.0;
+    for (int k = 0; k < j; ++k) ss += c[k] * c[k];
+    const double om2 = c[j] - ss;
+    if (!isfinite(om2)) {
+        hs.scal[2] = om2;
+        hs.scal[4] = 1.0;
+        return;
+    }
+    const double om = om2 > 0.0 ? sqrt(om2) : 0.0;
+    if (j == 0) {
+        for (int k = 0; k <= m; ++k) hs.g[k] = 0.0;
+        hs.g[0] = om;
+        hs.scal[0] = om;
+        hs.scal[2] = om;
+    } else {
+        double* raw = d.Hraw + (size_t)(j - 1) * ld;
+        for (int i = 0; i < j; ++i) raw[i] = d.hprev[i] + c[i];
+        raw[j] = om;
+        for (int i = j + 1; i <= m; ++i) raw[i] = 0.0;
+        double* col = hs.H + (size_t)(j - 1) * ld;
+        for (int i = 0; i <= j; ++i) col[i] = raw[i];
+        for (int i = 0; i < j - 1; ++i) {
+            const double a = col[i], b = col[i + 1];
+            col[i] = hs.cs[i] * a + hs.sn[i] * b;
+            col[i + 1] = -hs.sn[i] * a + hs.cs[i] * b;
+        }
+        const double a = col[j - 1], b = col[j];
+        const double den = hypot(a, b);
+        hs.cs[j - 1] = den > 0.0 ? a / den : 1.0;
+        hs.sn[j - 1] = den > 0.0 ? b / den : 0.0;
+        col[j - 1] = den;
+        col[j] = 0.0;
+        hs.g[j] = -hs.sn[j - 1] * hs.g[j - 1];
+        hs.g[j - 1] = hs.cs[j - 1] * hs.g[j - 1];
+        hs.scal[2] = fabs(hs.g[j]);
+    }
+    hs.scal[4] = om > 0.0 ? 0.0 : 1.0;
+    if (last || !(om > 0.0)) return;
+    double sz = 0.0;
+    for (int k = 0; k < j; ++k) sz += c[k] * c[MAXV + k];
+    const double zeta = (c[MAXV + j] - sz) / om;
+    for (int i = 0; i <= j; ++i) {
+        double v = i < j ? c[MAXV + i] : zeta;
+        for (int k = i > 0 ? i - 1 : 0; k < j; ++k) v -= d.Hraw[(size_t)k * ld + i] * c[k];
+        d.hprev[i] = v / om;
+    }
+    d.omz[0] = om;
+    d.omz[1] = zeta;
+}
+
+// One pass: q_j = (u - Q_j s) / omega  and  u <- (w - Q_j z - zeta q_j) / omega.
+__global__ void __launch_bounds__(256) dcgs2_update(int64_t len2, double2* Q, int64_t ldv2, int j,
+                                                    const double* __restrict__ c, const double* __restrict__ omz,
+                                                    double2* u, const double2* __restrict__ w) {
+    double sk[MAXV], zk[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+        sk[k] = k < j ? c[k] : 0.0;
+        zk[k] = k < j ? c[MAXV + k] : 0.0;
+    }
+    const double rom = 1.0 / omz[0], zeta = omz[1];
+    double2* qj = Q + (size_t)j * ldv2;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len2; t += (int64_t)gridDim.x * 256) {
+        const double2 uv = u[t];
+        const double2 wv = w[t];
+        double sx = 0.0, sy = 0.0, zx = 0.0, zy = 0.0;
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k) {
+            if (k < j) {
+                const double2 q = Q[(size_t)k * ldv2 + t];
+                sx += sk[k] * q.x;
+                sy += sk[k] * q.y;
+                zx += zk[k] * q.x;
+                zy += zk[k] * q.y;
+            }
+        }
+        const double qx = (uv.x - sx) * rom, qy = (uv.y - sy) * rom;
+        qj[t] = make_double2(qx, qy);
+        u[t] = make_double2((wv.x - zx - zeta * qx) * rom, (wv.y - zy - zeta * qy) * rom);
+    }
+}
+
 }  // namespace isc
 
 // ---------------------------------------------------------------- host side
@@ -259,16 +440,41 @@ static hipError_t read_scalar(isc_ctx* ctx, const double* dsrc, double* out) {
 
 }  // namespace isc
 
+namespace isc {
+// delayed-CGS2 state lives after the Hessenberg block of ctx->small
+constexpr int DCGS_OFF = 1400;
+Dcgs dcgs_of(isc_ctx* ctx) {
+    Dcgs d;
+    const int m = ctx->mmax;
+    d.Hraw = ctx->small + DCGS_OFF;
+    d.hprev = d.Hraw + (size_t)(m + 1) * m;
+    d.omz = d.hprev + (m + 1);
+    return d;
+}
+}  // namespace isc
+
 // FP64 right-preconditioned GMRES(m) with BILU(0); Dinv must hold the factor.
+// Iteration j applies A M^-1 to the lagged vector u_j (kept in basis slot m),
+// reduces once, finishes column j-1 on the device and, while the host reads
+// the residual estimate of the j-column solution, already runs the update
+// pass that writes q_j and u_{j+1}.  A cycle that reaches m columns needs one
+// more reduction (no product) to finish column m-1.
 isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, const double* b, double* x,
                           const isc_solve_opts* o, isc_solve_info* info) {
     using namespace isc;
     const int64_t len = (int64_t)ctx->n * NU;
     const int64_t ldv = len;
+    const int64_t len2 = len / 2, ldv2 = ldv / 2;
     const int m = o->restart;
     const int nb = nblocks(len);
+    const int nb2 = nblocks(len2);
     Hess hs = hess_of(ctx);
+    Dcgs dc = dcgs_of(ctx);
     double* red = ctx->small + RED_OFF;
+    double2* Q2 = reinterpret_cast<double2*>(ctx->V);
+    double* u = ctx->V + (size_t)m * ldv;
+    double2* u2 = reinterpret_cast<double2*>(u);
+    const double2* w2 = reinterpret_cast<const double2*>(ctx->w);
     isc_solve_info inf{};
     double bn2;
     norm2_dev(ctx, len, b, red + 2 * MAXV);
@@ -284,19 +490,14 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
         return ISC_ERR_NONFINITE;
     }
     isc_status st = ISC_ERR_LINEAR_NOCONV;
+    hipEvent_t ev = ctx->ev[7];
     for (int cyc = 0; cyc < o->max_restarts; ++cyc) {
-        // r = b - A x  (x = 0 on the first cycle)
+        // u_0 = r = b - A x  (x = 0 on the first cycle)
         if (cyc == 0) {
-            hipLaunchKernelGGL(multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, b, (int64_t)0, 1, b,
-                               ctx->partial);
-            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
-                               red + 2 * MAXV);
-            hipLaunchKernelGGL(gmres_start, dim3(1), dim3(1), 0, ctx->stream, hs, red + 2 * MAXV);
-            hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, b,
-                               hs.scal + 1, ctx->V);
+            ISC_HIP(hipMemcpyAsync(u, b, (size_t)len * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         } else {
             isc_launch_spmv(ctx, A, x, ctx->tvec);
-            hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, ctx->w,
+            hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, u,
                                ctx->partial);
             hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
                                red + 2 * MAXV);
@@ -305,60 +506,64 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
             inf.relres_true = sqrt(rn2) / bnorm;
             if (sqrt(rn2) <= o->rtol * bnorm) { st = ISC_OK; break; }
             inf.restarts = cyc;
-            hipLaunchKernelGGL(gmres_start, dim3(1), dim3(1), 0, ctx->stream, hs, red + 2 * MAXV);
-            hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w,
-                               hs.scal + 1, ctx->V);
         }
-        int jdone = 0;
-        for (int j = 0; j < m; ++j) {
-            double* Vj = ctx->V + (size_t)j * ldv;
-            double* Vn = ctx->V + (size_t)(j + 1) * ldv;
-            int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY);
-            isc_launch_bilu0_apply(ctx, A, Dinv, Vj, ctx->tvec);
+        int k = m;
+        for (int j = 0; j <= m; ++j) {
+            const bool last = j == m;
+            if (!last) {
+                int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY);
+                isc_launch_bilu0_apply(ctx, A, Dinv, u, ctx->tvec);
+                isc_prof_end(ctx, tk);
+                tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
+                isc_launch_spmv(ctx, A, ctx->tvec, ctx->w);
+                isc_prof_end(ctx, tk);
+            }
+            const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
+            hipLaunchKernelGGL(dcgs2_dots, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, u2,
+                               last ? nullptr : w2, ctx->partial);
+            hipLaunchKernelGGL(reduce_rows_dcgs, dim3(last ? j + 1 : 2 * (j + 1)), dim3(256), 0, ctx->stream,
+                               ctx->partial, nb2, j, red);
+            hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hs, dc, j, last ? 1 : 0, red);
+            ISC_HIP(hipMemcpyAsync(ctx->hscratch, hs.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+            ISC_HIP(hipEventRecord(ev, ctx->stream));
+            if (!last)   // speculative: unused if the estimate below ends the cycle
+                hipLaunchKernelGGL(dcgs2_update, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, red,
+                                   dc.omz, u2, w2);
             isc_prof_end(ctx, tk);
-            tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
-            isc_launch_spmv(ctx, A, ctx->tvec, ctx->w);
-            isc_prof_end(ctx, tk);
-            tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
-            // CGS2
-            hipLaunchKernelGGL(multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, j + 1,
-                               ctx->w, ctx->partial);
-            hipLaunchKernelGGL(reduce_partials, dim3(j + 1), dim3(256), 0, ctx->stream, ctx->partial, nb, red);
-            hipLaunchKernelGGL(update_multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv,
-                               j + 1, red, ctx->w, ctx->partial);
-            hipLaunchKernelGGL(reduce_partials, dim3(j + 1), dim3(256), 0, ctx->stream, ctx->partial, nb,
-                               red + MAXV);
-            hipLaunchKernelGGL(update_norm<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, j + 1,
-                               red + MAXV, ctx->w, ctx->partial);
-            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
-                               red + 2 * MAXV);
-            hipLaunchKernelGGL(gmres_column, dim3(1), dim3(1), 0, ctx->stream, hs, j, red, red + MAXV,
-                               red + 2 * MAXV);
-            hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w,
-                               hs.scal + 1, Vn);
-            isc_prof_end(ctx, tk);
-            double est;
-            ISC_HIP(read_scalar(ctx, hs.scal + 2, &est));
-            inf.iters++;
-            jdone = j + 1;
-            inf.relres_est = est / bnorm;
+            ISC_HIP(hipEventSynchronize(ev));
+            const double est = ctx->hscratch[2];
+            const bool breakdown = ctx->hscratch[4] != 0.0;
             if (!std::isfinite(est)) {
+                (void)hipStreamSynchronize(ctx->stream);
+                isc_prof_drain(ctx);
                 if (isc_check_sweeps(ctx) != ISC_OK) return ISC_ERR_HIP;
                 ctx->err = "isc_solve: GMRES breakdown (non-finite residual estimate)";
                 return ISC_ERR_NONFINITE;
             }
-            if (est <= o->rtol * bnorm) break;
+            if (j == 0) {
+                if (breakdown) {   // u_0 = r has zero norm: nothing to do
+                    k = 0;
+                    break;
+                }
+                continue;
+            }
+            inf.iters++;
+            inf.relres_est = est / bnorm;
+            if (est <= o->rtol * bnorm || breakdown || last) {
+                k = j;
+                break;
+            }
         }
-        // x += M^-1 (V y)
-        hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hs, jdone);
-        hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv,
-                           jdone, hs.y, ctx->tvec2, 0);
-        {
+        // x += M^-1 (Q_k y)
+        if (k > 0) {
+            hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hs, k);
+            hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, k,
+                               hs.y, ctx->tvec2, 0);
             const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY);
             isc_launch_bilu0_apply(ctx, A, Dinv, ctx->tvec2, ctx->tvec);
             isc_prof_end(ctx, tk);
+            hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->tvec, x);
         }
-        hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->tvec, x);
     }
     if (st != ISC_OK) {
         isc_launch_spmv(ctx, A, x, ctx->tvec);
