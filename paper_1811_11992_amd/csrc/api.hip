@@ -228,15 +228,18 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     std::vector<int32_t> lvl_rows(n), fillp(ctx->lvl_off_h.begin(), ctx->lvl_off_h.end() - 1);
     for (int32_t i = 0; i < n; ++i) lvl_rows[fillp[i % nx + (i / nx) % ny + i / nxy]++] = i;
 
-    // chunks of at most 8 rows of one level (sync-free sweeps)
-    std::vector<int32_t> chf, chb;
-    for (int32_t s = 0; s < ctx->nlev; ++s)
-        for (int32_t o = ctx->lvl_off_h[s]; o < ctx->lvl_off_h[s + 1]; o += 8)
-            for (int32_t q = 0; q < 8; ++q) chf.push_back(o + q < ctx->lvl_off_h[s + 1] ? lvl_rows[o + q] : -1);
-    for (int32_t s = ctx->nlev - 1; s >= 0; --s)
-        for (int32_t o = ctx->lvl_off_h[s]; o < ctx->lvl_off_h[s + 1]; o += 8)
-            for (int32_t q = 0; q < 8; ++q) chb.push_back(o + q < ctx->lvl_off_h[s + 1] ? lvl_rows[o + q] : -1);
-    ctx->nchunk = (int32_t)(chf.size() / 8);
+    // 2x2x2 bricks by brick level (sync-free sweeps), ascending brick index inside a level
+    const int32_t nbx = (nx + 1) / 2, nby = (ny + 1) / 2, nbz = (nz + 1) / 2;
+    ctx->nbrick = nbx * nby * nbz;
+    std::vector<int32_t> chf((size_t)ctx->nbrick), chb;
+    {
+        const int32_t nbl = nbx + nby + nbz - 2;
+        std::vector<int32_t> off(nbl + 2, 0);
+        for (int32_t b = 0; b < ctx->nbrick; ++b) off[b % nbx + (b / nbx) % nby + b / (nbx * nby) + 1]++;
+        for (int32_t s = 0; s <= nbl; ++s) off[s + 1] += off[s];
+        for (int32_t b = 0; b < ctx->nbrick; ++b) chf[off[b % nbx + (b / nbx) % nby + b / (nbx * nby)]++] = b;
+        chb.assign(chf.rbegin(), chf.rend());
+    }
     if (const char* e = getenv("ISC_LEVEL_SWEEPS")) ctx->syncfree = !(e[0] == '1');
 
     // wells
@@ -293,8 +296,8 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->qv, (size_t)n);
     ALLOC(ctx->rates, (size_t)n * 4);
     ALLOC(ctx->perf_cell, (size_t)std::max(npf, 1));
-    ALLOC(ctx->chunks_fwd, chf.size());
-    ALLOC(ctx->chunks_bwd, chb.size());
+    ALLOC(ctx->bricks_fwd, chf.size());
+    ALLOC(ctx->bricks_bwd, chb.size());
     ALLOC(ctx->sweep64, (size_t)n * isc::NU);
     ALLOC(ctx->sweep32, (size_t)n * isc::NU);
     ALLOC(ctx->ticket, (size_t)1);
@@ -336,8 +339,8 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     if (isc_reset_sweep_buffers(ctx) != hipSuccess ||
         hipMemsetAsync(ctx->ticket, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->flags, 0, 16 * sizeof(int32_t), ctx->stream) != hipSuccess ||
-        !h2d(ctx->chunks_fwd, chf.data(), chf.size() * sizeof(int32_t)) ||
-        !h2d(ctx->chunks_bwd, chb.data(), chb.size() * sizeof(int32_t))) {
+        !h2d(ctx->bricks_fwd, chf.data(), chf.size() * sizeof(int32_t)) ||
+        !h2d(ctx->bricks_bwd, chb.data(), chb.size() * sizeof(int32_t))) {
         ctx->err = "initialising the sweep schedule failed";
         return fail(ISC_ERR_HIP);
     }
@@ -382,7 +385,7 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->w,       ctx->tvec,  ctx->tvec2,   ctx->partial, ctx->small,  ctx->flags,
                     ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,     ctx->t32b,
                     ctx->small32, ctx->accJ,   ctx->qg,     ctx->qv,     ctx->rates,
-                    ctx->perf_cell, ctx->well_off, ctx->chunks_fwd, ctx->chunks_bwd, ctx->sweep64,
+                    ctx->perf_cell, ctx->well_off, ctx->bricks_fwd, ctx->bricks_bwd, ctx->sweep64,
                     ctx->sweep32, ctx->ticket};
     for (void* p : ptrs)
         if (p) hipFree(p);

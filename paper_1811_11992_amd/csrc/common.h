@@ -96,13 +96,12 @@ struct isc_ctx {
     int32_t nlev = 0;
     std::vector<int32_t> lvl_off_h;
     int32_t* lvl_rows = nullptr;
-    // sync-free triangular sweeps: chunks of <= 8 rows of one level, in level
-    // order (forward) and reverse level order (backward); tickets order the
-    // workgroups
+    // sync-free triangular sweeps: 2x2x2 bricks listed by ascending (forward)
+    // and descending (backward) brick level; tickets order the workgroups
     bool syncfree = true;
-    int32_t nchunk = 0;
-    int32_t* chunks_fwd = nullptr;
-    int32_t* chunks_bwd = nullptr;
+    int32_t nbrick = 0;
+    int32_t* bricks_fwd = nullptr;
+    int32_t* bricks_bwd = nullptr;
     double* sweep64 = nullptr;   // private forward-sweep buffers, sentinel-filled between sweeps
     float* sweep32 = nullptr;
     unsigned long long* ticket = nullptr;

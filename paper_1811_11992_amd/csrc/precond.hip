@@ -201,22 +201,27 @@ __global__ void __launch_bounds__(256) spmv_unitdiag(int32_t n, const int32_t* _
 }
 
 // ------------------------------------------------------------ sync-free sweeps
-// One kernel per triangular sweep.  Rows are grouped in chunks of at most 8
-// rows of the same hyperplane level (one wavefront per chunk, eight lanes per
-// row), chunks are listed level by level, and each workgroup takes a ticket
-// in that order, so every row a wavefront waits for belongs to a wavefront
-// that is already running or finished.  No flags: the sweep's output buffer
-// holds a NaN sentinel before the sweep, a row's result is published with
-// device-coherent 64-/32-bit stores, and a consumer lane polls its element of
-// each predecessor with device-coherent loads until the sentinel is gone.
-// The forward sweep writes into a private buffer and sets the rows of z back
-// to the sentinel; the backward sweep reads the private buffer, restores its
-// sentinel for the next forward sweep, and writes z.  Every wait is bounded in
-// wall-clock time and stops early once any wait has timed out (error flag), so
-// a sweep always terminates.
+// One kernel per triangular sweep.  The grid is cut into 2x2x2 bricks (one
+// wavefront each), the bricks are listed by brick level bx + by + bz, and each
+// workgroup takes a ticket in that order, so every brick a wavefront waits for
+// belongs to a wavefront that is already running or finished.  No flags: the
+// sweep's output buffer holds a NaN sentinel before the sweep, a row's result
+// is published with device-coherent 64-/32-bit stores, and a consumer lane
+// polls its element of each predecessor with device-coherent loads until the
+// sentinel is gone.  The forward sweep writes into a private buffer and sets
+// the rows of z back to the sentinel; the backward sweep reads the private
+// buffer, restores its sentinel for the next forward sweep, and writes z.
+// Every wait is bounded in wall-clock time and stops early once any wait has
+// timed out (error flag), so a sweep always terminates.
 constexpr uint64_t SENTINEL64 = 0x7FF4DEC0DE5EED01ull;   // NaN payload no arithmetic produces
 constexpr uint32_t SENTINEL32 = 0x7FA5EED1u;
 constexpr uint64_t WAIT_TICKS = 1ull << 24;               // ~0.17 s of the 100 MHz wall clock
+#ifndef ISC_SWEEP_SLEEP
+#define ISC_SWEEP_SLEEP 1      // s_sleep argument between polls (units of 64 clocks)
+#endif
+#ifndef ISC_SWEEP_LDS
+#define ISC_SWEEP_LDS 0        // dynamic LDS per workgroup: caps resident sweep workgroups per CU
+#endif
 
 template <class TV> struct Bits;
 template <> struct Bits<double> {
@@ -245,7 +250,7 @@ template <class TV> __device__ __forceinline__ TV await_value(const TV* p, typen
     if (u != Bits<TV>::sentinel) return from_bits<TV>(u);
     const uint64_t t0 = wall_clock64();
     for (int k = 1;; ++k) {
-        __builtin_amdgcn_s_sleep(1);
+        __builtin_amdgcn_s_sleep(ISC_SWEEP_SLEEP);
         u = peek(p);
         if (u != Bits<TV>::sentinel) return from_bits<TV>(u);
         if ((k & 63) == 0) {
@@ -265,24 +270,50 @@ __device__ __forceinline__ int32_t take_ticket(unsigned long long* ticket, unsig
     return s_t;
 }
 
+// Bricks: a wavefront owns a 2x2x2 brick of cells (lane = 8 * g + r, brick
+// cell g = dx + 2 dy + 4 dz, block row r).  A brick depends only on the
+// bricks below it in x, y and z, so the chain of waits is bx + by + bz long
+// instead of ix + iy + iz.  Inside the brick the cells are finished in four
+// steps (dx + dy + dz = 0..3), taking in-brick predecessors from the lanes
+// that computed them; each cell still subtracts its neighbours in the order
+// z-, y-, x- (forward) and x+, y+, z+ (backward), as the level launches do.
+struct BrickCell {
+    int32_t i;      // row, or -1 outside the grid
+    int32_t ii;     // row clamped to 0
+    int g, r, gbase, step;
+};
+__device__ __forceinline__ BrickCell brick_cell(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny,
+                                                int32_t nz) {
+    BrickCell bc;
+    const int lane = threadIdx.x & 63;
+    bc.g = lane >> 3;
+    bc.r = lane & 7;
+    bc.gbase = threadIdx.x & 56;
+    const int32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int dx = bc.g & 1, dy = (bc.g >> 1) & 1, dz = bc.g >> 2;
+    const int32_t ix = 2 * bx + dx, iy = 2 * by + dy, iz = 2 * bz + dz;
+    bc.step = dx + dy + dz;
+    bc.i = (ix < nx && iy < ny && iz < nz) ? ix + nx * (iy + ny * iz) : -1;
+    bc.ii = bc.i >= 0 ? bc.i : 0;
+    return bc;
+}
+
 // forward: v_i = D_i^-1 (r_i - sum_{k lower} A_ik v_k); v is the private
 // buffer (sentinel on entry), z_i is reset to the sentinel for the backward sweep
 template <class T, class TV>
-__global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
-    const int32_t* __restrict__ chunks, int32_t nchunk, int32_t nx, int32_t ny, const int32_t* __restrict__ row_ptr,
-    const T* __restrict__ A, const T* __restrict__ Dinv, const TV* __restrict__ rin, TV* v, TV* __restrict__ z,
-    unsigned long long* ticket, unsigned long long base, int32_t* err) {
-    const int32_t ch = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
-    if (ch >= nchunk) return;
-    const int lane = threadIdx.x & 63;
-    const int r = lane & 7;
-    const int gbase = threadIdx.x & 56;
-    const int32_t i = chunks[(size_t)ch * 8 + (lane >> 3)];
-    const bool act = i >= 0;
-    const int32_t ii = act ? i : 0;
+__device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+                                          const int32_t* __restrict__ row_ptr, const T* __restrict__ A,
+                                          const T* __restrict__ Dinv, const TV* __restrict__ rin, TV* v,
+                                          TV* __restrict__ z, int32_t* err) {
+    const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
+    const int r = bc.r, gbase = bc.gbase;
+    const bool act = bc.i >= 0;
+    const int32_t ii = bc.ii;
     const int32_t nxy = nx * ny;
     const int32_t ix = ii % nx, iy = (ii / nx) % ny, iz = ii / nxy;
     const int32_t lower[3] = {iz > 0 ? ii - nxy : -1, iy > 0 ? ii - nx : -1, ix > 0 ? ii - 1 : -1};
+    // in-brick predecessor (brick cell index) or -1
+    const int inb[3] = {(bc.g & 4) ? bc.g - 4 : -1, (bc.g & 2) ? bc.g - 2 : -1, (bc.g & 1) ? bc.g - 1 : -1};
     // everything that does not depend on other rows is loaded first, without
     // branches (a missing neighbour reads the row's first block and is masked)
     double arow[3][8];
@@ -302,43 +333,52 @@ __global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
     const T* d = Dinv + (size_t)ii * BS + r * 8;
 #pragma unroll
     for (int c = 0; c < 8; ++c) drow[c] = (double)d[c];
-    double acc = act ? (double)rin[(size_t)ii * NU + r] : 0.0;
+    const double rv = act ? (double)rin[(size_t)ii * NU + r] : 0.0;
     if (act) z[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
-    // first reads of the three predecessors go out together
+    // predecessors in other bricks: first reads go out together, then wait
+    bool ext[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) ext[q] = act && lower[q] >= 0 && inb[q] < 0;
     typename Bits<TV>::U first[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) first[q] = (act && lower[q] >= 0) ? peek(v + (size_t)lower[q] * NU + r) : 0;
+    for (int q = 0; q < 3; ++q) first[q] = ext[q] ? peek(v + (size_t)lower[q] * NU + r) : 0;
+    double xg[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const double xk =
-            (act && lower[q] >= 0) ? (double)await_value(v + (size_t)lower[q] * NU + r, first[q], err) : 0.0;
+    for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(v + (size_t)lower[q] * NU + r, first[q], err) : 0.0;
+    double vout = 0.0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc -= arow[q][c] * __shfl(xk, gbase + c);
+    for (int s = 0; s < 4; ++s) {
+        double acc = rv;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            // element r of neighbour q: from its lane if it is in this brick
+            const double xin = __shfl(vout, (inb[q] >= 0 ? inb[q] : bc.g) * 8 + r);
+            const double xq = lower[q] < 0 ? 0.0 : (inb[q] >= 0 ? xin : xg[q]);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc -= arow[q][c] * __shfl(xq, gbase + c);
+        }
+        double out = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) out += drow[c] * __shfl(acc, gbase + c);
+        if (bc.step == s) vout = out;
     }
-    double out = 0.0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) out += drow[c] * __shfl(acc, gbase + c);
-    if (act) publish(v + (size_t)ii * NU + r, (TV)out);
+    if (act) publish(v + (size_t)ii * NU + r, (TV)vout);
 }
 
 // backward: z_i = v_i - D_i^-1 sum_{j upper} A_ij z_j; z holds the sentinel on
 // entry, v_i is reset to the sentinel for the next forward sweep
 template <class T, class TV>
-__global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
-    const int32_t* __restrict__ chunks, int32_t nchunk, int32_t nx, int32_t ny, int32_t nz,
-    const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ v,
-    TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
-    const int32_t ch = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
-    if (ch >= nchunk) return;
-    const int lane = threadIdx.x & 63;
-    const int r = lane & 7;
-    const int gbase = threadIdx.x & 56;
-    const int32_t i = chunks[(size_t)ch * 8 + (lane >> 3)];
-    const bool act = i >= 0;
-    const int32_t ii = act ? i : 0;
+__device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+                                          const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
+                                          const T* __restrict__ Dinv, TV* __restrict__ v, TV* z, int32_t* err) {
+    const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
+    const int r = bc.r, gbase = bc.gbase;
+    const bool act = bc.i >= 0;
+    const int32_t ii = bc.ii;
     const int32_t nxy = nx * ny;
     const int32_t ix = ii % nx, iy = (ii / nx) % ny, iz = ii / nxy;
     const int32_t upper[3] = {ix + 1 < nx ? ii + 1 : -1, iy + 1 < ny ? ii + nx : -1, iz + 1 < nz ? ii + nxy : -1};
+    const int inb[3] = {(bc.g & 1) ? -1 : bc.g + 1, (bc.g & 2) ? -1 : bc.g + 2, (bc.g & 4) ? -1 : bc.g + 4};
     double arow[3][8];
     const int32_t b0 = diag_pos[ii];
     int32_t blk = b0 + 1;
@@ -358,21 +398,54 @@ __global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
     for (int c = 0; c < 8; ++c) drow[c] = (double)d[c];
     const double vi = act ? (double)v[(size_t)ii * NU + r] : 0.0;
     if (act) v[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
-    double acc = 0.0;
+    bool ext[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) ext[q] = act && upper[q] >= 0 && inb[q] < 0;
     typename Bits<TV>::U first[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) first[q] = (act && upper[q] >= 0) ? peek(z + (size_t)upper[q] * NU + r) : 0;
+    for (int q = 0; q < 3; ++q) first[q] = ext[q] ? peek(z + (size_t)upper[q] * NU + r) : 0;
+    double xg[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const double xj =
-            (act && upper[q] >= 0) ? (double)await_value(z + (size_t)upper[q] * NU + r, first[q], err) : 0.0;
+    for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(z + (size_t)upper[q] * NU + r, first[q], err) : 0.0;
+    double zout = 0.0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc += arow[q][c] * __shfl(xj, gbase + c);
+    for (int s = 0; s < 4; ++s) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double xin = __shfl(zout, (inb[q] >= 0 ? inb[q] : bc.g) * 8 + r);
+            const double xq = upper[q] < 0 ? 0.0 : (inb[q] >= 0 ? xin : xg[q]);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc += arow[q][c] * __shfl(xq, gbase + c);
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) t += drow[c] * __shfl(acc, gbase + c);
+        if (3 - bc.step == s) zout = vi - t;
     }
-    double s = 0.0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) s += drow[c] * __shfl(acc, gbase + c);
-    if (act) publish(z + (size_t)ii * NU + r, (TV)(vi - s));
+    if (act) publish(z + (size_t)ii * NU + r, (TV)zout);
+}
+
+// A workgroup takes one ticket; wavefront w handles brick list entry 4 t + w.
+template <class T, class TV>
+__global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
+    const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+    const int32_t* __restrict__ row_ptr, const T* __restrict__ A, const T* __restrict__ Dinv,
+    const TV* __restrict__ rin, TV* v, TV* __restrict__ z, unsigned long long* ticket, unsigned long long base,
+    int32_t* err) {
+    const int32_t k = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
+    if (k >= nbrick) return;
+    fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, row_ptr, A, Dinv, rin, v, z, err);
+}
+
+template <class T, class TV>
+__global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
+    const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+    const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ v,
+    TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
+    const int32_t k = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
+    if (k >= nbrick) return;
+    bwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, v, z, err);
 }
 
 template <class U>
@@ -417,14 +490,15 @@ template <class T, class TV>
 hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, const TV* r, TV* z) {
     if (ctx->syncfree) {
         TV* v = isc::sweep_buffer<TV>(ctx);
-        const int32_t nwg = (ctx->nchunk + 3) / 4;
-        hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(nwg), dim3(256), 0, ctx->stream, ctx->chunks_fwd,
-                           ctx->nchunk, ctx->g.nx, ctx->g.ny, ctx->row_ptr, A, Dinv, r, v, z, ctx->ticket,
-                           ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+        const int32_t nwg = (ctx->nbrick + 3) / 4;
+        const int32_t nbx = (ctx->g.nx + 1) / 2, nby = (ctx->g.ny + 1) / 2;
+        hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(nwg), dim3(256), ISC_SWEEP_LDS, ctx->stream,
+                           ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr, A,
+                           Dinv, r, v, z, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
         ctx->ticket_base += (unsigned long long)nwg;
-        hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV>), dim3(nwg), dim3(256), 0, ctx->stream, ctx->chunks_bwd,
-                           ctx->nchunk, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->diag_pos, A, Dinv, v, z, ctx->ticket,
-                           ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+        hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV>), dim3(nwg), dim3(256), ISC_SWEEP_LDS, ctx->stream,
+                           ctx->bricks_bwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->diag_pos, A,
+                           Dinv, v, z, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
         ctx->ticket_base += (unsigned long long)nwg;
         return hipGetLastError();
     }
