@@ -5,12 +5,19 @@ GMRES(30) to 1e-8 -> safeguarded update) on one MI355X.
 A step is one Newton iteration that solves; when Newton has converged the
 next timestep starts (the converged-check assembly is inside the timed
 region, counted as no step).  Inputs are resident in HBM before timing.
+The JSON line's value is the chosen precision on the chosen workload;
+unless --no-forms, it also carries the other precision on the same workload
+(precision form: FP32 BILU(0) and inner SpMV inside FP64 FGMRES) and the
+cost of the differentiation form (forward and backward ms per step of the
+adjoint of cumulative oil production on the 60x60x10 grid).
 
     python bench.py [--steps K] [--warmup W] [--workload C3] [--precision fp64|mixed]
 """
 from __future__ import annotations
 
 import argparse
+import gc
+import hashlib
 import json
 import os
 import sys
@@ -32,25 +39,59 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--inner", type=int, default=6, help="FP32 inner iterations (mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the other precision and the adjoint-cost legs")
     ap.add_argument("--cpu-layers", type=int, default=4, help="layers of the workload in the oracle sample")
     return ap.parse_args()
 
 
-def algorithmic_bytes(n, nnzb, prec="fp64"):
-    """Bytes each kernel class must move per launch (SURVEY-style counts:
-    neighbour vector blocks assumed cache hits)."""
-    b = 8 if prec == "fp64" else 4
-    off = (nnzb - n) * 64 * b               # off-diagonal blocks of the decoupled matrix
-    vec = n * 8 * 8                         # one FP64 block vector
+def algorithmic_bytes(n, nnzb):
+    """Bytes each kernel class must move per launch (every matrix block and
+    vector element once; a neighbour's vector block re-read by another row is
+    counted as a cache hit)."""
+    off64 = (nnzb - n) * 64 * 8             # off-diagonal blocks of the decoupled matrix, FP64
+    vec64 = n * 8 * 8                       # one FP64 block vector
     return {
         # y = A x: off-diagonal blocks + x + y
-        "spmv": off + 2 * vec,
+        "spmv": off64 + 2 * vec64,
         # forward + backward sweep: all off-diagonal blocks once, D^-1 twice,
         # r read, v write, v read, z write
-        "ilu_apply": off + 2 * n * 64 * 8 + 4 * vec,
+        "ilu_apply": off64 + 2 * n * 64 * 8 + 4 * vec64,
+        # the same in FP32 storage (precision form)
+        "ilu_apply32": (off64 + 2 * n * 64 * 8 + 4 * vec64) // 2,
+        "spmv32": (off64 + 2 * vec64) // 2,
         # u, u_old, porosity, 3 transmissibilities in; F and J out
-        "assemble": 2 * vec + n * 8 * 4 + vec + nnzb * 64 * 8,
+        "assemble": 2 * vec64 + n * 8 * 4 + vec64 + nnzb * 64 * 8,
     }
+
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "bilu0_sweeps_200x200x50_fp64_traffic.md")
+
+
+def sweep_source_hash():
+    h = hashlib.sha256()
+    for f in ("precond.hip", "common.h"):
+        with open(os.path.join(HERE, "paper_1811_11992_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, or None when
+    it covers another kernel or workload or the sweep source has changed
+    since the counters were taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            for line in fh:
+                if line.startswith("traffic_record:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if (rec["kernel"] == kernel and rec["workload"] == workload
+                            and rec["source_sha256"] == sweep_source_hash()):
+                        return rec["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
 
 
 class Driver:
@@ -117,48 +158,103 @@ def cpu_baseline(wl, layers):
             "status": int(st)}
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (the hot path is single-GPU; see DESIGN.md for how it "
-              f"would shard); got --gpus {a.gpus}", file=sys.stderr)
-        sys.exit(2)
+def run_newton(wl, precision, inner, warmup, steps):
+    """Times `steps` solving Newton iterations; returns (rate, seconds, driver, profile)."""
     import torch
-    from paper_1811_11992_amd import inputs as I
     from paper_1811_11992_amd import isc
-
-    wl = I.make_workload(a.workload)
-    mixed = a.precision == "mixed"
-    ctx = isc.Context(wl, restart=30, inner_iters=a.inner if mixed else 0)
+    mixed = precision == "mixed"
+    ctx = isc.Context(wl, restart=30, inner_iters=inner if mixed else 0)
     lin = isc.solve_opts(restart=30, max_restarts=20, rtol=1e-8,
-                         precision=isc.ISC_MIXED if mixed else isc.ISC_FP64, inner_iters=a.inner if mixed else 0)
+                         precision=isc.ISC_MIXED if mixed else isc.ISC_FP64, inner_iters=inner if mixed else 0)
     drv = Driver(ctx, wl, lin)
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         drv.newton_iteration()
     torch.cuda.synchronize()
     ni0, lin0, inner0 = drv.ni, drv.lin_its, drv.inner_its
     isc.isc_profile(ctx, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(steps):
         drv.newton_iteration()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     prof = isc.isc_profile(ctx, 0)
-    n = wl.ncell
-    value = n * a.steps / el
-    lin_per_ni = (drv.lin_its - lin0) / max(1, drv.ni - ni0)
+    stats = {"gmres_its_per_newton": round((drv.lin_its - lin0) / max(1, drv.ni - ni0), 2),
+             "inner_its_per_newton": round((drv.inner_its - inner0) / max(1, drv.ni - ni0), 2),
+             "timesteps_completed": drv.steps_done, "step_cuts": drv.cuts, "nnzb": ctx.nnzb}
+    del drv, ctx
+    gc.collect()
+    torch.cuda.synchronize()
+    return wl.ncell * steps / el, el, stats, prof
 
-    nbytes = algorithmic_bytes(n, ctx.nnzb)
-    classes = {}
-    for k, (ms, cnt) in prof.items():
-        rec = {"ms": round(ms, 3), "launches": cnt}
-        if k in nbytes and cnt > 0 and ms > 0:
-            rec["GB_s"] = round(nbytes[k] * cnt / (ms * 1e-3) / 1e9, 1)
-        classes[k] = rec
-    dom = max((k for k in nbytes if prof[k][1] > 0), key=lambda k: prof[k][0])
+
+def adjoint_cost(name="C4", nsteps=20, every=5):
+    """Differentiation form: one forward run (checkpoints every `every` steps)
+    and its backward pass (segment recomputation + one adjoint solve per
+    step) of cumulative oil production on `name`; times per step."""
+    import torch
+    from paper_1811_11992_amd import inputs as I
+    from paper_1811_11992_amd import isc
+    from paper_1811_11992_amd.adjoint import OilProduction, log_frequency_factors
+    wl = I.make_workload(name)
+    fl = I.physics_card()
+    ctx = isc.Context(wl, fluid=fl)
+    u0 = torch.tensor(wl.u0, dtype=torch.float64, device="cuda")
+    logk = torch.tensor(wl.logk, dtype=torch.float64, device="cuda").requires_grad_(True)
+    lnA = log_frequency_factors(fl).requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = OilProduction.apply(logk, lnA, ctx, u0, wl.dt, nsteps, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ok = bool(torch.isfinite(logk.grad).all()) and bool(torch.isfinite(lnA.grad).all())
+    del ctx
+    gc.collect()
+    return {"workload": f"{name}: {wl.nx}x{wl.ny}x{wl.nz}, {nsteps} steps, checkpoints every {every}",
+            "forward_ms_per_step": round((t1 - t0) / nsteps * 1e3, 2),
+            "backward_ms_per_step": round((t2 - t1) / nsteps * 1e3, 2),
+            "backward_over_forward": round((t2 - t1) / (t1 - t0), 3),
+            "gradient_finite": ok}
+
+
+def roofline(prof, nbytes, workload):
+    dom = max((k for k in nbytes if prof.get(k, (0, 0))[1] > 0), key=lambda k: prof[k][0])
     ms, cnt = prof[dom]
     achieved = nbytes[dom] / (ms / cnt * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, workload),
+            "bytes_per_launch": nbytes[dom], "avg_launch_ms": round(ms / cnt, 4)}
+
+
+def classes_of(prof, nbytes):
+    out = {}
+    for k, (ms, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        rec = {"ms": round(ms, 3), "launches": cnt}
+        if k in nbytes and ms > 0:
+            rec["GB_s"] = round(nbytes[k] * cnt / (ms * 1e-3) / 1e9, 1)
+        out[k] = rec
+    return out
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only: the hot path is built and measured on a single MI355X "
+              f"(how it would shard is described in the design notes); got --gpus {a.gpus}", file=sys.stderr)
+        sys.exit(2)
+    from paper_1811_11992_amd import inputs as I
+
+    wl = I.make_workload(a.workload)
+    n = wl.ncell
+    value, el, stats, prof = run_newton(wl, a.precision, a.inner, a.warmup, a.steps)
+    nbytes = algorithmic_bytes(n, stats["nnzb"])
+    mixed = a.precision == "mixed"
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": el / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -168,13 +264,20 @@ def main():
                                + ("FP32 BILU(0) + inner SpMV in FP64 FGMRES(30)" if mixed
                                   else "FP64 BILU(0)-GMRES(30)") + " to 1e-8, Newton 1e-10",
                    "cells": n, "precision": a.precision, "newton_its_timed": a.steps,
-                   "gmres_its_per_newton": round(lin_per_ni, 2), "timesteps_completed": drv.steps_done,
-                   "step_cuts": drv.cuts},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": nbytes[dom], "avg_launch_ms": round(ms / cnt, 4)},
-        "kernel_classes": classes,
+                   **{k: v for k, v in stats.items() if k != "nnzb"}},
+        "roofline": roofline(prof, nbytes, wl.name),
+        "kernel_classes": classes_of(prof, nbytes),
     }
+    if not a.no_forms:
+        other = "fp64" if mixed else "mixed"
+        v2, el2, st2, prof2 = run_newton(wl, other, a.inner, a.warmup, a.steps)
+        out["precision_forms"] = {
+            other: {"value": v2, "ms_per_step": el2 / a.steps * 1e3,
+                    **{k: v for k, v in st2.items() if k != "nnzb"},
+                    "roofline": roofline(prof2, nbytes, wl.name), "kernel_classes": classes_of(prof2, nbytes)},
+            "mixed_over_fp64": (v2 / value) if not mixed else (value / v2),
+        }
+        out["adjoint"] = adjoint_cost()
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_layers)
     print(json.dumps(out), flush=True)

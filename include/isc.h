@@ -196,9 +196,10 @@ isc_status isc_scaled_norm(isc_ctx* ctx, const double* F, double dt, double* res
  * frequency factors A_R).  One backward step of the discrete adjoint:
  *   (dR^n/du^n)^T lam^n = dt_n (dq_oil/du^n)^T + (V/dt_{n+1}) (dA/du(u^n))^T lam^{n+1}
  * (A: accumulation per bulk volume; lam_np1 = NULL at the last step, then
- * dt_np1 is ignored), solved on the decoupled system with the transposed
- * BILU(0)-preconditioned GMRES (opts_h may be NULL: restart 30, 200 cycles,
- * rtol 1e-12); then g_logk[N] += dt_n dq/dln k - lam^n . dR^n/dln k (device)
+ * dt_np1 is ignored), solved by transposing J in place (the 7-point pattern is
+ * symmetric), decoupling J^T by its own diagonal blocks and running the
+ * BILU(0)-preconditioned GMRES on it (opts_h may be NULL: restart 30, 200
+ * cycles, rtol 1e-12); then g_logk[N] += dt_n dq/dln k - lam^n . dR^n/dln k (device)
  * and g_A_h[4] += -lam^n . dR^n/dA_R (host).  u_n, u_nm1: [8][N]; lam: [N][8]. */
 isc_status isc_adjoint(isc_ctx* ctx, const double* u_n, const double* u_nm1, double dt_n,
                        const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
@@ -212,11 +213,13 @@ isc_status isc_oil_rate(isc_ctx* ctx, const double* u, double* q_h);
  * launch of a class inside the calls above is then bracketed by an event
  * pair; enable = 0 stops.  Always returns the accumulated milliseconds and
  * launch counts (host arrays of ISC_PROF_NCLASS, may be NULL).  Classes:
- * 0 SpMV, 1 BILU(0) apply (one forward plus one backward sweep, all levels),
- * 2 assembly (property pass + face assembly), 3 decoupling, 4 BILU(0) factor
- * (all levels), 5 Krylov vector work (orthogonalisation, updates, norms). */
+ * 0 SpMV, 1 BILU(0) apply (one forward plus one backward sweep), 2 assembly
+ * (property pass + face assembly), 3 decoupling, 4 BILU(0) factor (all
+ * levels), 5 Krylov vector work (orthogonalisation, updates, norms, in both
+ * precisions), 6 FP32 BILU(0) apply and 7 FP32 SpMV (the inner solver of the
+ * precision form). */
 enum { ISC_PROF_SPMV = 0, ISC_PROF_ILU_APPLY, ISC_PROF_ASSEMBLE, ISC_PROF_DECOUPLE, ISC_PROF_ILU_FACTOR,
-       ISC_PROF_KRYLOV, ISC_PROF_NCLASS = 8 };
+       ISC_PROF_KRYLOV, ISC_PROF_ILU_APPLY32, ISC_PROF_SPMV32, ISC_PROF_NCLASS = 8 };
 isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* count_h);
 
 const char* isc_last_error(const isc_ctx* ctx);

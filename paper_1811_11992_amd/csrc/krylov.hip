@@ -624,8 +624,13 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
     for (int i = 0; i < m_in; ++i) {
         const float* Vi = V32 + (size_t)i * len;
         float* Vn = V32 + (size_t)(i + 1) * len;
+        int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY32);
         isc_launch_bilu0_apply32(ctx, A32, D32, Vi, ctx->t32);
+        isc_prof_end(ctx, tk);
+        tk = isc_prof_begin(ctx, ISC_PROF_SPMV32);
         isc_launch_spmv32(ctx, A32, ctx->t32, ctx->w32);
+        isc_prof_end(ctx, tk);
+        tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
         hipLaunchKernelGGL(multidot<float>, dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, i + 1, ctx->w32,
                            ctx->partial);
         hipLaunchKernelGGL(reduce_partials, dim3(i + 1), dim3(256), 0, ctx->stream, ctx->partial, nb, red);
@@ -638,11 +643,14 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
         hipLaunchKernelGGL(gmres_column, dim3(1), dim3(1), 0, ctx->stream, hi, i, red, red + MAXV, red + 2 * MAXV);
         hipLaunchKernelGGL((scale_copy<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w32,
                            hi.scal + 1, Vn);
+        isc_prof_end(ctx, tk);
     }
     hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hi, m_in);
     hipLaunchKernelGGL((lincomb<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, m_in, hi.y,
                        ctx->t32b, 0);
+    const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY32);
     isc_launch_bilu0_apply32(ctx, A32, D32, ctx->t32b, ctx->t32);
+    isc_prof_end(ctx, tk);
     hipLaunchKernelGGL(to_f64, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->t32, z);
 }
 
@@ -703,10 +711,8 @@ isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, doubl
             double* Vj = ctx->V + (size_t)j * ldv;
             double* Vn = ctx->V + (size_t)(j + 1) * ldv;
             double* Zj = ctx->Z + (size_t)j * ldv;
-            int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY);
             inner_gmres32(ctx, ctx->J32, ctx->Dinv32, Vj, Zj, m_in);
-            isc_prof_end(ctx, tk);
-            tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
+            int tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
             isc_launch_spmv(ctx, A, Zj, ctx->w);
             isc_prof_end(ctx, tk);
             tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);

@@ -6,13 +6,16 @@
 // diagonal blocks: M = (D + L) D^-1 (D + U) with L, U the strict lower and
 // upper block parts of A and
 //     D_i = I - sum_{k lower neighbour of i} A_ik D_k^-1 A_ki.
-// The factor, forward and backward recurrences are scheduled by hyperplanes
-// ix + iy + iz = s (all rows of a hyperplane are independent); the result is
-// the natural-order factorisation exactly.
+// The factor is scheduled by hyperplanes ix + iy + iz = s (all rows of a
+// hyperplane are independent), one launch each; the triangular sweeps of the
+// apply run as one launch each over 2x2x2 bricks (below), with one launch per
+// hyperplane kept as the reference schedule.  Every schedule gives the
+// natural-order factorisation exactly.
 //
 // Mappings: factor - one wavefront per row, lane (r, c) with LDS-staged 8x8
-// products and a column-per-lane Gauss-Jordan inverse; apply and SpMV - eight
-// lanes per block row, lane r owns output row r.
+// products and a column-per-lane Gauss-Jordan inverse; apply - one wavefront
+// per brick, eight lanes per cell; SpMV - eight lanes per block row, lane r
+// owns output row r.
 #include "common.h"
 
 namespace isc {

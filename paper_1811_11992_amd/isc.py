@@ -216,7 +216,7 @@ class Context:
         return q.value
 
 
-PROF_CLASSES = ("spmv", "ilu_apply", "assemble", "decouple", "ilu_factor", "krylov")
+PROF_CLASSES = ("spmv", "ilu_apply", "assemble", "decouple", "ilu_factor", "krylov", "ilu_apply32", "spmv32")
 
 
 def _profile_call(ctx, enable):

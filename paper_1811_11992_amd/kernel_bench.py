@@ -1,0 +1,60 @@
+"""Times the linear-algebra kernels of one Newton iteration on a workload.
+
+    python -m paper_1811_11992_amd.kernel_bench [--workload C3] [--reps 20]
+
+Builds the decoupled Jacobian at the workload's initial state (assemble,
+decouple, BILU(0) factor through the C-ABI), then times ``isc_bilu0_apply``
+and ``isc_spmv`` on a random right-hand side, and runs a plain 128 MB-class
+device copy of one vector as the reference kernel for hardware counters (a
+copy moves a known number of bytes).  Prints one JSON line.  Used to take
+per-kernel traffic counters without the rest of the solver in the trace.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import torch
+
+from . import inputs as I
+from . import isc
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--reps", type=int, default=20)
+    a = ap.parse_args(argv)
+    wl = I.make_workload(a.workload)
+    c = isc.Context(wl)
+    u = torch.tensor(wl.u0, dtype=torch.float64, device="cuda")
+    F, J = c.isc_assemble(u, u, wl.dt)
+    c.isc_decouple(J, F)
+    D = c.isc_bilu0(J)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    r = torch.randn((c.n, 8), dtype=torch.float64, device="cuda", generator=g)
+    z = torch.empty_like(r)
+    y = torch.empty_like(r)
+    for _ in range(3):
+        c.isc_bilu0_apply(J, D, r, z)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        for _ in range(a.reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / a.reps * 1e3
+
+    t_apply = timed(lambda: c.isc_bilu0_apply(J, D, r, z))
+    t_spmv = timed(lambda: c.isc_spmv(J, r, y))
+    t_copy = timed(lambda: y.copy_(r))
+    vec_bytes = r.numel() * r.element_size()
+    print(json.dumps({"workload": wl.name, "cells": c.n, "reps": a.reps, "bilu0_apply_ms": round(t_apply, 4),
+                      "spmv_ms": round(t_spmv, 4), "copy_ms": round(t_copy, 4), "copy_bytes_each_way": vec_bytes,
+                      "apply_finite": bool(torch.isfinite(z).all())}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
