@@ -154,7 +154,10 @@ struct isc_ctx {
 
 namespace isc {
 constexpr int PERF_W = 12;  // kind, wi, bhp, q[7], qE, q_total
-constexpr int NPART = 1024; // partial sums per reduction
+#ifndef ISC_NPART
+#define ISC_NPART 4096
+#endif
+constexpr int NPART = ISC_NPART;  // partial sums per reduction (block count of the reducing kernels)
 }
 
 // Profiling helpers (host).  prof_begin/prof_end bracket a kernel class on the

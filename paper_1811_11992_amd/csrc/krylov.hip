@@ -221,62 +221,60 @@ __global__ void gmres_solve_small(Hess hs, int k) {
 // Vectors are read as double2 (lengths are multiples of 8 doubles).
 // Row layout of the dot results: r (r <= j) = <X_r, u>, MAXV + r = <X_r, w>,
 // with X_r = Q_r for r < j and X_j = u.
-__device__ __forceinline__ void block_store_dcgs(const double* a1, double au, const double* a2, double aw, int j,
-                                                 bool hw, double* partial, int nblk) {
-    __shared__ double red[4][2 * MAXV];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int k = 0; k < MAXV; ++k) {
-        if (k < j) {
-            const double s1 = wave_sum(a1[k]);
-            if (lane == 0) red[wv][k] = s1;
-            if (hw) {
-                const double s2 = wave_sum(a2[k]);
-                if (lane == 0) red[wv][MAXV + k] = s2;
-            }
-        }
-    }
-    const double su = wave_sum(au);
-    if (lane == 0) red[wv][j] = su;
-    if (hw) {
-        const double sw = wave_sum(aw);
-        if (lane == 0) red[wv][MAXV + j] = sw;
-    }
-    __syncthreads();
-    const int nrow = hw ? 2 * (j + 1) : j + 1;
-    for (int r = threadIdx.x; r < nrow; r += 256) {
-        const int row = r <= j ? r : MAXV + (r - j - 1);
-        partial[(size_t)row * nblk + blockIdx.x] = (red[0][row] + red[1][row]) + (red[2][row] + red[3][row]);
-    }
-}
-
 // One pass: <Q_k, u>, <Q_k, w> (k < j), <u, u>, <u, w>; w may be null.
+// Wavefront wv of a block accumulates the basis vectors k = wv, wv + 4, ...
+// (at most 8 of them, so few registers) over the block's elements; the four
+// wavefronts read the same u and w, which the cache serves after the first.
 __global__ void __launch_bounds__(256) dcgs2_dots(int64_t len2, const double2* __restrict__ Q, int64_t ldv2, int j,
                                                   const double2* __restrict__ u, const double2* __restrict__ w,
                                                   double* __restrict__ partial) {
-    double a1[MAXV], a2[MAXV];
+    constexpr int PER = MAXV / 4;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double a1[PER], a2[PER];
 #pragma unroll
-    for (int k = 0; k < MAXV; ++k) { a1[k] = 0.0; a2[k] = 0.0; }
+    for (int m = 0; m < PER; ++m) { a1[m] = 0.0; a2[m] = 0.0; }
     double au = 0.0, aw = 0.0;
     const bool hw = w != nullptr;
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len2; t += (int64_t)gridDim.x * 256) {
+    for (int64_t t = (int64_t)blockIdx.x * 64 + lane; t < len2; t += (int64_t)gridDim.x * 64) {
         const double2 uv = u[t];
-        const double2 wv = hw ? w[t] : make_double2(0.0, 0.0);
+        const double2 wx = hw ? w[t] : make_double2(0.0, 0.0);
 #pragma unroll
-        for (int k = 0; k < MAXV; ++k) {
+        for (int m = 0; m < PER; ++m) {
+            const int k = wv + 4 * m;
             if (k < j) {
                 const double2 q = Q[(size_t)k * ldv2 + t];
-                a1[k] += q.x * uv.x + q.y * uv.y;
-                a2[k] += q.x * wv.x + q.y * wv.y;
+                a1[m] += q.x * uv.x + q.y * uv.y;
+                a2[m] += q.x * wx.x + q.y * wx.y;
             }
         }
-        au += uv.x * uv.x + uv.y * uv.y;
-        aw += uv.x * wv.x + uv.y * wv.y;
+        if (wv == 0) {
+            au += uv.x * uv.x + uv.y * uv.y;
+            aw += uv.x * wx.x + uv.y * wx.y;
+        }
     }
-    block_store_dcgs(a1, au, a2, aw, j, hw, partial, gridDim.x);
+    const int nblk = gridDim.x;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+        const int k = wv + 4 * m;
+        if (k < j) {
+            const double s1 = wave_sum(a1[m]);
+            const double s2 = wave_sum(a2[m]);
+            if (lane == 0) {
+                partial[(size_t)k * nblk + blockIdx.x] = s1;
+                if (hw) partial[(size_t)(MAXV + k) * nblk + blockIdx.x] = s2;
+            }
+        }
+    }
+    if (wv == 0) {
+        const double su = wave_sum(au), sw = wave_sum(aw);
+        if (lane == 0) {
+            partial[(size_t)j * nblk + blockIdx.x] = su;
+            if (hw) partial[(size_t)(MAXV + j) * nblk + blockIdx.x] = sw;
+        }
+    }
 }
 
-// out[row] = sum over blocks of partial[row], rows as in block_store_dcgs
+// out[row] = sum over blocks of partial[row] (row layout above)
 __global__ void __launch_bounds__(256) reduce_rows_dcgs(const double* __restrict__ partial, int nblk, int j,
                                                         double* __restrict__ out) {
     __shared__ double red[4];

@@ -301,6 +301,30 @@ __device__ __forceinline__ BrickCell brick_cell(int32_t b, int32_t nbx, int32_t 
     return bc;
 }
 
+// In-brick exchange through a per-wavefront LDS scratch: LDS operations of
+// one wavefront complete in issue order, so a fence at wavefront scope is
+// enough between a lane's write and another lane's read.
+struct alignas(16) BrickLds {
+    double v[64];        // [cell][row]: results of the previous cell steps
+    double acc[64];      // [cell][row]: accumulators before the D^-1 product
+    double ext[3][64];   // [neighbour][cell][row]: values from other bricks (0 if none)
+};
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// the eight doubles at x (LDS, 16-byte aligned)
+__device__ __forceinline__ void lds_row8(const double* x, double* out8) {
+    const double2* p = reinterpret_cast<const double2*>(x);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double2 t = p[k];
+        out8[2 * k] = t.x;
+        out8[2 * k + 1] = t.y;
+    }
+}
+
 // forward: v_i = D_i^-1 (r_i - sum_{k lower} A_ik v_k); v is the private
 // buffer (sentinel on entry), z_i is reset to the sentinel for the backward sweep
 template <class T, class TV>
@@ -348,22 +372,37 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     double xg[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(v + (size_t)lower[q] * NU + r, first[q], err) : 0.0;
+    __shared__ BrickLds lds_all[4];
+    BrickLds& L = lds_all[threadIdx.x >> 6];
+    const int me = bc.g * 8 + r;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) L.ext[q][me] = xg[q];
+    // neighbour q's row block: in this brick (results so far) or outside (ext)
+    const double* src[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) src[q] = (lower[q] >= 0 && inb[q] >= 0) ? &L.v[inb[q] * 8] : &L.ext[q][bc.g * 8];
     double vout = 0.0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+        L.v[me] = vout;
+        wave_lds_sync();
         double acc = rv;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            // element r of neighbour q: from its lane if it is in this brick
-            const double xin = __shfl(vout, (inb[q] >= 0 ? inb[q] : bc.g) * 8 + r);
-            const double xq = lower[q] < 0 ? 0.0 : (inb[q] >= 0 ? xin : xg[q]);
+            double x[8];
+            lds_row8(src[q], x);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc -= arow[q][c] * __shfl(xq, gbase + c);
+            for (int c = 0; c < 8; ++c) acc -= arow[q][c] * x[c];
         }
+        L.acc[me] = acc;
+        wave_lds_sync();
+        double a8[8];
+        lds_row8(&L.acc[bc.g * 8], a8);
         double out = 0.0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) out += drow[c] * __shfl(acc, gbase + c);
+        for (int c = 0; c < 8; ++c) out += drow[c] * a8[c];
         if (bc.step == s) vout = out;
+        wave_lds_sync();
     }
     if (act) publish(v + (size_t)ii * NU + r, (TV)vout);
 }
@@ -410,21 +449,36 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     double xg[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(z + (size_t)upper[q] * NU + r, first[q], err) : 0.0;
+    __shared__ BrickLds lds_all[4];
+    BrickLds& L = lds_all[threadIdx.x >> 6];
+    const int me = bc.g * 8 + r;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) L.ext[q][me] = xg[q];
+    const double* src[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) src[q] = (upper[q] >= 0 && inb[q] >= 0) ? &L.v[inb[q] * 8] : &L.ext[q][bc.g * 8];
     double zout = 0.0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+        L.v[me] = zout;
+        wave_lds_sync();
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const double xin = __shfl(zout, (inb[q] >= 0 ? inb[q] : bc.g) * 8 + r);
-            const double xq = upper[q] < 0 ? 0.0 : (inb[q] >= 0 ? xin : xg[q]);
+            double x[8];
+            lds_row8(src[q], x);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc += arow[q][c] * __shfl(xq, gbase + c);
+            for (int c = 0; c < 8; ++c) acc += arow[q][c] * x[c];
         }
+        L.acc[me] = acc;
+        wave_lds_sync();
+        double a8[8];
+        lds_row8(&L.acc[bc.g * 8], a8);
         double t = 0.0;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) t += drow[c] * __shfl(acc, gbase + c);
+        for (int c = 0; c < 8; ++c) t += drow[c] * a8[c];
         if (3 - bc.step == s) zout = vi - t;
+        wave_lds_sync();
     }
     if (act) publish(z + (size_t)ii * NU + r, (TV)zout);
 }
