@@ -225,8 +225,9 @@ __global__ void gmres_solve_small(Hess hs, int k) {
 // Wavefront wv of a block accumulates the basis vectors k = wv, wv + 4, ...
 // (at most 8 of them, so few registers) over the block's elements; the four
 // wavefronts read the same u and w, which the cache serves after the first.
-__global__ void __launch_bounds__(256) dcgs2_dots(int64_t len2, const double2* __restrict__ Q, int64_t ldv2, int j,
-                                                  const double2* __restrict__ u, const double2* __restrict__ w,
+template <class V2>
+__global__ void __launch_bounds__(256) dcgs2_dots(int64_t len2, const V2* __restrict__ Q, int64_t ldv2, int j,
+                                                  const V2* __restrict__ u, const V2* __restrict__ w,
                                                   double* __restrict__ partial) {
     constexpr int PER = MAXV / 4;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -236,20 +237,27 @@ __global__ void __launch_bounds__(256) dcgs2_dots(int64_t len2, const double2* _
     double au = 0.0, aw = 0.0;
     const bool hw = w != nullptr;
     for (int64_t t = (int64_t)blockIdx.x * 64 + lane; t < len2; t += (int64_t)gridDim.x * 64) {
-        const double2 uv = u[t];
-        const double2 wx = hw ? w[t] : make_double2(0.0, 0.0);
+        const V2 uvr = u[t];
+        const double ux = (double)uvr.x, uy = (double)uvr.y;
+        double wxx = 0.0, wxy = 0.0;
+        if (hw) {
+            const V2 wr = w[t];
+            wxx = (double)wr.x;
+            wxy = (double)wr.y;
+        }
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
             const int k = wv + 4 * m;
             if (k < j) {
-                const double2 q = Q[(size_t)k * ldv2 + t];
-                a1[m] += q.x * uv.x + q.y * uv.y;
-                a2[m] += q.x * wx.x + q.y * wx.y;
+                const V2 q = Q[(size_t)k * ldv2 + t];
+                const double qx = (double)q.x, qy = (double)q.y;
+                a1[m] += qx * ux + qy * uy;
+                a2[m] += qx * wxx + qy * wxy;
             }
         }
         if (wv == 0) {
-            au += uv.x * uv.x + uv.y * uv.y;
-            aw += uv.x * wx.x + uv.y * wx.y;
+            au += ux * ux + uy * uy;
+            aw += ux * wxx + uy * wxy;
         }
     }
     const int nblk = gridDim.x;
@@ -344,7 +352,13 @@ __global__ void dcgs2_step(Hess hs, Dcgs d, int j, int last, const double* __res
         hs.scal[2] = fabs(hs.g[j]);
     }
     hs.scal[4] = om > 0.0 ? 0.0 : 1.0;
-    if (last || !(om > 0.0)) return;
+    if (last) return;
+    if (!(om > 0.0)) {   // u_j lies in the span of Q_j: q_j = u_{j+1} = 0 from here on
+        for (int i = 0; i <= j; ++i) d.hprev[i] = 0.0;
+        d.omz[0] = 0.0;
+        d.omz[1] = 0.0;
+        return;
+    }
     double sz = 0.0;
     for (int k = 0; k < j; ++k) sz += c[k] * c[MAXV + k];
     const double zeta = (c[MAXV + j] - sz) / om;
@@ -357,35 +371,42 @@ __global__ void dcgs2_step(Hess hs, Dcgs d, int j, int last, const double* __res
     d.omz[1] = zeta;
 }
 
-// One pass: q_j = (u - Q_j s) / omega  and  u <- (w - Q_j z - zeta q_j) / omega.
-__global__ void __launch_bounds__(256) dcgs2_update(int64_t len2, double2* Q, int64_t ldv2, int j,
+// One pass: q_j = (u - Q_j s) / omega  and  u <- (w - Q_j z - zeta q_j) / omega
+// (omega = 0, a breakdown, leaves q_j = u = 0).
+template <class V2>
+__global__ void __launch_bounds__(256) dcgs2_update(int64_t len2, V2* Q, int64_t ldv2, int j,
                                                     const double* __restrict__ c, const double* __restrict__ omz,
-                                                    double2* u, const double2* __restrict__ w) {
+                                                    V2* u, const V2* __restrict__ w) {
     double sk[MAXV], zk[MAXV];
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) {
         sk[k] = k < j ? c[k] : 0.0;
         zk[k] = k < j ? c[MAXV + k] : 0.0;
     }
-    const double rom = 1.0 / omz[0], zeta = omz[1];
-    double2* qj = Q + (size_t)j * ldv2;
+    const double rom = omz[0] > 0.0 ? 1.0 / omz[0] : 0.0, zeta = omz[1];
+    V2* qj = Q + (size_t)j * ldv2;
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len2; t += (int64_t)gridDim.x * 256) {
-        const double2 uv = u[t];
-        const double2 wv = w[t];
+        const V2 uv = u[t];
+        const V2 wv = w[t];
         double sx = 0.0, sy = 0.0, zx = 0.0, zy = 0.0;
 #pragma unroll
         for (int k = 0; k < MAXV; ++k) {
             if (k < j) {
-                const double2 q = Q[(size_t)k * ldv2 + t];
-                sx += sk[k] * q.x;
-                sy += sk[k] * q.y;
-                zx += zk[k] * q.x;
-                zy += zk[k] * q.y;
+                const V2 q = Q[(size_t)k * ldv2 + t];
+                sx += sk[k] * (double)q.x;
+                sy += sk[k] * (double)q.y;
+                zx += zk[k] * (double)q.x;
+                zy += zk[k] * (double)q.y;
             }
         }
-        const double qx = (uv.x - sx) * rom, qy = (uv.y - sy) * rom;
-        qj[t] = make_double2(qx, qy);
-        u[t] = make_double2((wv.x - zx - zeta * qx) * rom, (wv.y - zy - zeta * qy) * rom);
+        const double qx = ((double)uv.x - sx) * rom, qy = ((double)uv.y - sy) * rom;
+        V2 qo, uo;
+        qo.x = qx;
+        qo.y = qy;
+        uo.x = ((double)wv.x - zx - zeta * qx) * rom;
+        uo.y = ((double)wv.y - zy - zeta * qy) * rom;
+        qj[t] = qo;
+        u[t] = uo;
     }
 }
 
@@ -441,10 +462,9 @@ static hipError_t read_scalar(isc_ctx* ctx, const double* dsrc, double* out) {
 namespace isc {
 // delayed-CGS2 state lives after the Hessenberg block of ctx->small
 constexpr int DCGS_OFF = 1400;
-Dcgs dcgs_of(isc_ctx* ctx) {
+Dcgs dcgs_at(double* small, int m) {
     Dcgs d;
-    const int m = ctx->mmax;
-    d.Hraw = ctx->small + DCGS_OFF;
+    d.Hraw = small + DCGS_OFF;
     d.hprev = d.Hraw + (size_t)(m + 1) * m;
     d.omz = d.hprev + (m + 1);
     return d;
@@ -467,7 +487,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
     const int nb = nblocks(len);
     const int nb2 = nblocks(len2);
     Hess hs = hess_of(ctx);
-    Dcgs dc = dcgs_of(ctx);
+    Dcgs dc = dcgs_at(ctx->small, ctx->mmax);
     double* red = ctx->small + RED_OFF;
     double2* Q2 = reinterpret_cast<double2*>(ctx->V);
     double* u = ctx->V + (size_t)m * ldv;
@@ -517,7 +537,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
                 isc_prof_end(ctx, tk);
             }
             const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
-            hipLaunchKernelGGL(dcgs2_dots, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, u2,
+            hipLaunchKernelGGL(dcgs2_dots<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, u2,
                                last ? nullptr : w2, ctx->partial);
             hipLaunchKernelGGL(reduce_rows_dcgs, dim3(last ? j + 1 : 2 * (j + 1)), dim3(256), 0, ctx->stream,
                                ctx->partial, nb2, j, red);
@@ -525,7 +545,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
             ISC_HIP(hipMemcpyAsync(ctx->hscratch, hs.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
             ISC_HIP(hipEventRecord(ev, ctx->stream));
             if (!last)   // speculative: unused if the estimate below ends the cycle
-                hipLaunchKernelGGL(dcgs2_update, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, red,
+                hipLaunchKernelGGL(dcgs2_update<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, red,
                                    dc.omz, u2, w2);
             isc_prof_end(ctx, tk);
             ISC_HIP(hipEventSynchronize(ev));
@@ -589,62 +609,58 @@ hipError_t isc_launch_spmv32(isc_ctx*, const float*, const float*, float*);
 
 namespace isc {
 
-// w32 = (float) v, partial = ||w32||^2
-__global__ void __launch_bounds__(256) to_f32_norm(int64_t len, const double* __restrict__ v, float* __restrict__ w,
-                                                   double* __restrict__ partial) {
-    double acc[1] = {0.0};
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
-        const float f = (float)v[t];
-        w[t] = f;
-        acc[0] += (double)f * (double)f;
-    }
-    block_store(acc, 1, partial, gridDim.x);
-}
-
 __global__ void __launch_bounds__(256) to_f64(int64_t len, const float* __restrict__ a, double* __restrict__ b) {
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256)
         b[t] = (double)a[t];
 }
 
+__global__ void __launch_bounds__(256) narrow_f32(int64_t len, const double* __restrict__ a, float* __restrict__ b) {
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256)
+        b[t] = (float)a[t];
+}
+
 // z ~= A^-1 v by m_in iterations of FP32 right-preconditioned GMRES from 0
-// (FP32 storage of the basis, the matrix and the ILU factor; FP64 reductions).
-// No host synchronisation: the iteration count is fixed.
+// (FP32 storage of the basis, the matrix and the ILU factor; FP64 reductions
+// and small dense work), orthogonalised by the same delayed CGS2 as the FP64
+// solver.  No host synchronisation: the iteration count is fixed, and a
+// breakdown leaves zero vectors and zero Hessenberg columns, which the
+// triangular solve skips.
 static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, const double* v, double* z, int m_in) {
     const int64_t len = (int64_t)ctx->n * NU;
+    const int64_t len2 = len / 2;
     const int nb = nblocks(len);
+    const int nb2 = nblocks(len2);
     Hess hi = hess_at(ctx->small32, ctx->inner_max);
+    Dcgs di = dcgs_at(ctx->small32, ctx->inner_max);
     double* red = ctx->small32 + RED_OFF;
-    float* V32 = ctx->V32;
-    hipLaunchKernelGGL(to_f32_norm, dim3(nb), dim3(256), 0, ctx->stream, len, v, ctx->w32, ctx->partial);
-    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + 2 * MAXV);
-    hipLaunchKernelGGL(gmres_start, dim3(1), dim3(1), 0, ctx->stream, hi, red + 2 * MAXV);
-    hipLaunchKernelGGL((scale_copy<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w32, hi.scal + 1, V32);
-    for (int i = 0; i < m_in; ++i) {
-        const float* Vi = V32 + (size_t)i * len;
-        float* Vn = V32 + (size_t)(i + 1) * len;
-        int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY32);
-        isc_launch_bilu0_apply32(ctx, A32, D32, Vi, ctx->t32);
-        isc_prof_end(ctx, tk);
-        tk = isc_prof_begin(ctx, ISC_PROF_SPMV32);
-        isc_launch_spmv32(ctx, A32, ctx->t32, ctx->w32);
-        isc_prof_end(ctx, tk);
-        tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
-        hipLaunchKernelGGL(multidot<float>, dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, i + 1, ctx->w32,
-                           ctx->partial);
-        hipLaunchKernelGGL(reduce_partials, dim3(i + 1), dim3(256), 0, ctx->stream, ctx->partial, nb, red);
-        hipLaunchKernelGGL(update_multidot<float>, dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, i + 1, red,
-                           ctx->w32, ctx->partial);
-        hipLaunchKernelGGL(reduce_partials, dim3(i + 1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + MAXV);
-        hipLaunchKernelGGL(update_norm<float>, dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, i + 1, red + MAXV,
-                           ctx->w32, ctx->partial);
-        hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + 2 * MAXV);
-        hipLaunchKernelGGL(gmres_column, dim3(1), dim3(1), 0, ctx->stream, hi, i, red, red + MAXV, red + 2 * MAXV);
-        hipLaunchKernelGGL((scale_copy<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w32,
-                           hi.scal + 1, Vn);
+    float2* Q2 = reinterpret_cast<float2*>(ctx->V32);
+    float* u = ctx->V32 + (size_t)m_in * len;
+    float2* u2 = reinterpret_cast<float2*>(u);
+    const float2* w2 = reinterpret_cast<const float2*>(ctx->w32);
+    hipLaunchKernelGGL(narrow_f32, dim3(nb), dim3(256), 0, ctx->stream, len, v, u);
+    for (int j = 0; j <= m_in; ++j) {
+        const bool last = j == m_in;
+        if (!last) {
+            int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY32);
+            isc_launch_bilu0_apply32(ctx, A32, D32, u, ctx->t32);
+            isc_prof_end(ctx, tk);
+            tk = isc_prof_begin(ctx, ISC_PROF_SPMV32);
+            isc_launch_spmv32(ctx, A32, ctx->t32, ctx->w32);
+            isc_prof_end(ctx, tk);
+        }
+        const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
+        hipLaunchKernelGGL(dcgs2_dots<float2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, len2, j, u2,
+                           last ? nullptr : w2, ctx->partial);
+        hipLaunchKernelGGL(reduce_rows_dcgs, dim3(last ? j + 1 : 2 * (j + 1)), dim3(256), 0, ctx->stream,
+                           ctx->partial, nb2, j, red);
+        hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hi, di, j, last ? 1 : 0, red);
+        if (!last)
+            hipLaunchKernelGGL(dcgs2_update<float2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, len2, j, red,
+                               di.omz, u2, w2);
         isc_prof_end(ctx, tk);
     }
     hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hi, m_in);
-    hipLaunchKernelGGL((lincomb<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, V32, len, m_in, hi.y,
+    hipLaunchKernelGGL((lincomb<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V32, len, m_in, hi.y,
                        ctx->t32b, 0);
     const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY32);
     isc_launch_bilu0_apply32(ctx, A32, D32, ctx->t32b, ctx->t32);
