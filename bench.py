@@ -54,11 +54,12 @@ def algorithmic_bytes(n, nnzb):
     return {
         # y = A x: off-diagonal blocks + x + y
         "spmv": off64 + 2 * vec64,
-        # forward + backward sweep: all off-diagonal blocks once, D^-1 twice,
-        # r read, v write, v read, z write
-        "ilu_apply": off64 + 2 * n * 64 * 8 + 4 * vec64,
+        # forward + backward sweep of M = (I + L D^-1)(D + U): every
+        # off-diagonal block once (L D^-1 forward, U backward), D^-1 once,
+        # r read, y write, y read, z write
+        "ilu_apply": off64 + n * 64 * 8 + 4 * vec64,
         # the same in FP32 storage (precision form)
-        "ilu_apply32": (off64 + 2 * n * 64 * 8 + 4 * vec64) // 2,
+        "ilu_apply32": (off64 + n * 64 * 8 + 4 * vec64) // 2,
         "spmv32": (off64 + 2 * vec64) // 2,
         # u, u_old, porosity, 3 transmissibilities in; F and J out
         "assemble": 2 * vec64 + n * 8 * 4 + vec64 + nnzb * 64 * 8,

@@ -13,6 +13,7 @@ hipError_t isc_launch_assemble(isc_ctx*, const double* u, double* F, double* J);
 hipError_t isc_launch_decouple(isc_ctx*, double* J, double* F, int32_t* bad_dev);
 hipError_t isc_launch_bilu0_factor(isc_ctx*, const double* A, double* Dinv, int32_t* bad);
 hipError_t isc_launch_bilu0_apply(isc_ctx*, const double* A, const double* Dinv, const double* r, double* z);
+hipError_t isc_launch_form_ltilde(isc_ctx*, const double* A, const double* Dinv);
 hipError_t isc_launch_spmv(isc_ctx*, const double* A, const double* x, double* y);
 hipError_t isc_launch_update(isc_ctx*, double* u, const double* du, int32_t* flag_dev);
 hipError_t isc_launch_scaled_norm(isc_ctx*, const double* F, double dt, double* out_dev);
@@ -299,6 +300,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->bricks_fwd, chf.size());
     ALLOC(ctx->bricks_bwd, chb.size());
     ALLOC(ctx->sweep64, (size_t)n * isc::NU);
+    ALLOC(ctx->Lt, (size_t)n * 3 * isc::BS);
     ALLOC(ctx->sweep32, (size_t)n * isc::NU);
     ALLOC(ctx->ticket, (size_t)1);
     ALLOC(ctx->well_off, (size_t)nwells + 1);
@@ -306,6 +308,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         ALLOC(ctx->Z, nv * ctx->mmax);
         ALLOC(ctx->J32, (size_t)ctx->nnzb * isc::BS);
         ALLOC(ctx->Dinv32, (size_t)n * isc::BS);
+        ALLOC(ctx->Lt32, (size_t)n * 3 * isc::BS);
         ALLOC(ctx->V32, nv * (ctx->inner_max + 1));
         ALLOC(ctx->w32, nv);
         ALLOC(ctx->t32, nv);
@@ -386,7 +389,7 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,     ctx->t32b,
                     ctx->small32, ctx->accJ,   ctx->qg,     ctx->qv,     ctx->rates,
                     ctx->perf_cell, ctx->well_off, ctx->bricks_fwd, ctx->bricks_bwd, ctx->sweep64,
-                    ctx->sweep32, ctx->ticket};
+                    ctx->sweep32, ctx->ticket, ctx->Lt, ctx->Lt32};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (ctx->hscratch) hipHostFree(ctx->hscratch);
@@ -473,6 +476,7 @@ isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv,
         ctx->err = "isc_bilu0_apply: r and z must not alias";
         return ISC_ERR_ARG;
     }
+    ISC_HIP(isc_launch_form_ltilde(ctx, Jdec, Dinv));
     ISC_HIP(isc_launch_bilu0_apply(ctx, Jdec, Dinv, r, z));
     return isc_check_sweeps(ctx);
 }

@@ -6,6 +6,11 @@
 // diagonal blocks: M = (D + L) D^-1 (D + U) with L, U the strict lower and
 // upper block parts of A and
 //     D_i = I - sum_{k lower neighbour of i} A_ik D_k^-1 A_ki.
+// The factor keeps D_i^-1 and the products Lt_ik = A_ik D_k^-1 it forms on the
+// way, and the apply uses M = (I + Lt)(D + U):
+//     forward   y_i = r_i - sum_{k lower} Lt_ik y_k
+//     backward  z_i = D_i^-1 (y_i - sum_{j upper} A_ij z_j),
+// which reads seven blocks per row instead of eight (D^-1 once).
 // The factor is scheduled by hyperplanes ix + iy + iz = s (all rows of a
 // hyperplane are independent), one launch each; the triangular sweeps of the
 // apply run as one launch each over 2x2x2 bricks (below), with one launch per
@@ -35,7 +40,7 @@ template <class T>
 __global__ void __launch_bounds__(256) bilu0_factor_level(
     const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-    T* __restrict__ Dinv, int32_t* __restrict__ bad) {
+    T* __restrict__ Dinv, T* __restrict__ Lt, int32_t* __restrict__ bad) {
     __shared__ double sm[4][4][64];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -66,6 +71,7 @@ __global__ void __launch_bounds__(256) bilu0_factor_level(
 #pragma unroll
         for (int j = 0; j < 8; ++j) p += sA[r * 8 + j] * sK[j * 8 + c];
         sP[lane] = p;
+        Lt[((size_t)i * 3 + q) * BS + lane] = (T)p;
         __builtin_amdgcn_wave_barrier();
         double q2 = 0.0;
 #pragma unroll
@@ -115,39 +121,66 @@ __global__ void __launch_bounds__(256) bilu0_factor_level(
     }
 }
 
-// Forward sweep of one level: v_i = D_i^-1 (r_i - sum_{k lower} A_ik v_k).
+// Lt_ik = A_ik D_k^-1 for every lower neighbour k of i, from a given factor
+// (the factor kernel forms them itself; this serves an apply with a factor
+// computed elsewhere).  One wavefront per row, lane (r, c).
+template <class T>
+__global__ void __launch_bounds__(256) form_ltilde(int32_t n, int32_t nx, int32_t ny, const int32_t* __restrict__ row_ptr,
+                                                   const T* __restrict__ A, const T* __restrict__ Dinv,
+                                                   T* __restrict__ Lt) {
+    __shared__ double sm[4][2][64];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int32_t i = (int32_t)blockIdx.x * 4 + w;
+    if (i >= n) return;
+    const int r = lane >> 3, c = lane & 7;
+    double* sA = sm[w][0];
+    double* sK = sm[w][1];
+    const int32_t nxy = nx * ny;
+    const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    const int32_t lower[3] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1};
+    int32_t blk = row_ptr[i];
+    for (int q = 0; q < 3; ++q) {
+        const int32_t k = lower[q];
+        if (k < 0) continue;
+        sA[lane] = (double)A[(size_t)blk * BS + lane];
+        sK[lane] = (double)Dinv[(size_t)k * BS + lane];
+        ++blk;
+        __builtin_amdgcn_wave_barrier();
+        double p = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) p += sA[r * 8 + j] * sK[j * 8 + c];
+        Lt[((size_t)i * 3 + q) * BS + lane] = (T)p;
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Forward sweep of one level: y_i = r_i - sum_{k lower} Lt_ik y_k.
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_fwd_level(
-    const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, const int32_t* __restrict__ row_ptr,
-    const T* __restrict__ A, const T* __restrict__ Dinv, const TV* rin, TV* v) {
+    const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, const T* __restrict__ Lt,
+    const TV* rin, TV* y) {
     const int32_t t = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
     const int r = threadIdx.x & 7;
-    const int gbase = threadIdx.x & 56;   // first lane of this row's group in the wavefront
     if (t >= cnt) return;
     const int32_t i = rows[t];
     const int32_t nxy = nx * ny;
     const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
     double acc = (double)rin[(size_t)i * NU + r];
-    int32_t blk = row_ptr[i];
     const int32_t lower[3] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1};
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         const int32_t k = lower[q];
         if (k < 0) continue;
-        const T* a = A + (size_t)blk * BS + r * 8;
-        const TV* x = v + (size_t)k * NU;
+        const T* a = Lt + ((size_t)i * 3 + q) * BS + r * 8;
+        const TV* x = y + (size_t)k * NU;
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc -= (double)a[c] * (double)x[c];
-        ++blk;
     }
-    const T* d = Dinv + (size_t)i * BS + r * 8;
-    double out = 0.0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) out += (double)d[c] * __shfl(acc, gbase + c);
-    v[(size_t)i * NU + r] = (TV)out;
+    y[(size_t)i * NU + r] = (TV)acc;
 }
 
-// Backward sweep of one level (in place over v): z_i = v_i - D_i^-1 sum_{j upper} A_ij z_j.
+// Backward sweep of one level (in place over y): z_i = D_i^-1 (y_i - sum_{j upper} A_ij z_j).
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_bwd_level(
     const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, int32_t nz,
@@ -160,7 +193,7 @@ __global__ void __launch_bounds__(256) bilu0_bwd_level(
     const int32_t i = rows[t];
     const int32_t nxy = nx * ny;
     const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
-    double acc = 0.0;
+    double acc = (double)z[(size_t)i * NU + r];
     int32_t blk = diag_pos[i] + 1;
     const int32_t upper[3] = {ix + 1 < nx ? i + 1 : -1, iy + 1 < ny ? i + nx : -1,
                               iz + 1 < nz ? i + nxy : -1};
@@ -171,14 +204,14 @@ __global__ void __launch_bounds__(256) bilu0_bwd_level(
         const T* a = A + (size_t)blk * BS + r * 8;
         const TV* x = z + (size_t)j * NU;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc += (double)a[c] * (double)x[c];
+        for (int c = 0; c < 8; ++c) acc -= (double)a[c] * (double)x[c];
         ++blk;
     }
     const T* d = Dinv + (size_t)i * BS + r * 8;
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) s += (double)d[c] * __shfl(acc, gbase + c);
-    z[(size_t)i * NU + r] = (TV)((double)z[(size_t)i * NU + r] - s);
+    z[(size_t)i * NU + r] = (TV)s;
 }
 
 // y = A x for the decoupled matrix (unit diagonal blocks are not read).
@@ -325,15 +358,14 @@ __device__ __forceinline__ void lds_row8(const double* x, double* out8) {
     }
 }
 
-// forward: v_i = D_i^-1 (r_i - sum_{k lower} A_ik v_k); v is the private
-// buffer (sentinel on entry), z_i is reset to the sentinel for the backward sweep
+// forward: y_i = r_i - sum_{k lower} Lt_ik y_k; y is the private buffer
+// (sentinel on entry), z_i is reset to the sentinel for the backward sweep
 template <class T, class TV>
 __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-                                          const int32_t* __restrict__ row_ptr, const T* __restrict__ A,
-                                          const T* __restrict__ Dinv, const TV* __restrict__ rin, TV* v,
+                                          const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y,
                                           TV* __restrict__ z, int32_t* err) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
-    const int r = bc.r, gbase = bc.gbase;
+    const int r = bc.r;
     const bool act = bc.i >= 0;
     const int32_t ii = bc.ii;
     const int32_t nxy = nx * ny;
@@ -342,24 +374,17 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     // in-brick predecessor (brick cell index) or -1
     const int inb[3] = {(bc.g & 4) ? bc.g - 4 : -1, (bc.g & 2) ? bc.g - 2 : -1, (bc.g & 1) ? bc.g - 1 : -1};
     // everything that does not depend on other rows is loaded first, without
-    // branches (a missing neighbour reads the row's first block and is masked)
+    // branches (the slot of a missing neighbour is read and masked)
     double arow[3][8];
-    const int32_t b0 = row_ptr[ii];
-    int32_t blk = b0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const T* a = A + (size_t)(lower[q] >= 0 ? blk : b0) * BS + r * 8;
+        const T* a = Lt + ((size_t)ii * 3 + q) * BS + r * 8;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const double x = (double)a[c];
             arow[q][c] = lower[q] >= 0 ? x : 0.0;
         }
-        blk += lower[q] >= 0;
     }
-    double drow[8];
-    const T* d = Dinv + (size_t)ii * BS + r * 8;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) drow[c] = (double)d[c];
     const double rv = act ? (double)rin[(size_t)ii * NU + r] : 0.0;
     if (act) z[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
     // predecessors in other bricks: first reads go out together, then wait
@@ -368,10 +393,10 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     for (int q = 0; q < 3; ++q) ext[q] = act && lower[q] >= 0 && inb[q] < 0;
     typename Bits<TV>::U first[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) first[q] = ext[q] ? peek(v + (size_t)lower[q] * NU + r) : 0;
+    for (int q = 0; q < 3; ++q) first[q] = ext[q] ? peek(y + (size_t)lower[q] * NU + r) : 0;
     double xg[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(v + (size_t)lower[q] * NU + r, first[q], err) : 0.0;
+    for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(y + (size_t)lower[q] * NU + r, first[q], err) : 0.0;
     __shared__ BrickLds lds_all[4];
     BrickLds& L = lds_all[threadIdx.x >> 6];
     const int me = bc.g * 8 + r;
@@ -381,10 +406,10 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     const double* src[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) src[q] = (lower[q] >= 0 && inb[q] >= 0) ? &L.v[inb[q] * 8] : &L.ext[q][bc.g * 8];
-    double vout = 0.0;
+    double yout = 0.0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        L.v[me] = vout;
+        L.v[me] = yout;
         wave_lds_sync();
         double acc = rv;
 #pragma unroll
@@ -394,27 +419,20 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
 #pragma unroll
             for (int c = 0; c < 8; ++c) acc -= arow[q][c] * x[c];
         }
-        L.acc[me] = acc;
-        wave_lds_sync();
-        double a8[8];
-        lds_row8(&L.acc[bc.g * 8], a8);
-        double out = 0.0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) out += drow[c] * a8[c];
-        if (bc.step == s) vout = out;
+        if (bc.step == s) yout = acc;
         wave_lds_sync();
     }
-    if (act) publish(v + (size_t)ii * NU + r, (TV)vout);
+    if (act) publish(y + (size_t)ii * NU + r, (TV)yout);
 }
 
-// backward: z_i = v_i - D_i^-1 sum_{j upper} A_ij z_j; z holds the sentinel on
-// entry, v_i is reset to the sentinel for the next forward sweep
+// backward: z_i = D_i^-1 (y_i - sum_{j upper} A_ij z_j); z holds the sentinel on
+// entry, y_i is reset to the sentinel for the next forward sweep
 template <class T, class TV>
 __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
                                           const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-                                          const T* __restrict__ Dinv, TV* __restrict__ v, TV* z, int32_t* err) {
+                                          const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, int32_t* err) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
-    const int r = bc.r, gbase = bc.gbase;
+    const int r = bc.r;
     const bool act = bc.i >= 0;
     const int32_t ii = bc.ii;
     const int32_t nxy = nx * ny;
@@ -438,8 +456,8 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     const T* d = Dinv + (size_t)ii * BS + r * 8;
 #pragma unroll
     for (int c = 0; c < 8; ++c) drow[c] = (double)d[c];
-    const double vi = act ? (double)v[(size_t)ii * NU + r] : 0.0;
-    if (act) v[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
+    const double yi = act ? (double)y[(size_t)ii * NU + r] : 0.0;
+    if (act) y[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
     bool ext[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) ext[q] = act && upper[q] >= 0 && inb[q] < 0;
@@ -462,13 +480,13 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     for (int s = 0; s < 4; ++s) {
         L.v[me] = zout;
         wave_lds_sync();
-        double acc = 0.0;
+        double acc = yi;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             double x[8];
             lds_row8(src[q], x);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc += arow[q][c] * x[c];
+            for (int c = 0; c < 8; ++c) acc -= arow[q][c] * x[c];
         }
         L.acc[me] = acc;
         wave_lds_sync();
@@ -477,7 +495,7 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
         double t = 0.0;
 #pragma unroll
         for (int c = 0; c < 8; ++c) t += drow[c] * a8[c];
-        if (3 - bc.step == s) zout = vi - t;
+        if (3 - bc.step == s) zout = t;
         wave_lds_sync();
     }
     if (act) publish(z + (size_t)ii * NU + r, (TV)zout);
@@ -487,22 +505,21 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-    const int32_t* __restrict__ row_ptr, const T* __restrict__ A, const T* __restrict__ Dinv,
-    const TV* __restrict__ rin, TV* v, TV* __restrict__ z, unsigned long long* ticket, unsigned long long base,
-    int32_t* err) {
+    const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y, TV* __restrict__ z, unsigned long long* ticket,
+    unsigned long long base, int32_t* err) {
     const int32_t k = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
     if (k >= nbrick) return;
-    fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, row_ptr, A, Dinv, rin, v, z, err);
+    fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, Lt, rin, y, z, err);
 }
 
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-    const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ v,
+    const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ y,
     TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
     const int32_t k = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
     if (k >= nbrick) return;
-    bwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, v, z, err);
+    bwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, err);
 }
 
 template <class U>
@@ -517,6 +534,10 @@ namespace isc {
 template <class TV> TV* sweep_buffer(isc_ctx* ctx);
 template <> double* sweep_buffer<double>(isc_ctx* ctx) { return ctx->sweep64; }
 template <> float* sweep_buffer<float>(isc_ctx* ctx) { return ctx->sweep32; }
+// the Lt = L D^-1 blocks of the last factor in each precision
+template <class T> T* lt_buffer(isc_ctx* ctx);
+template <> double* lt_buffer<double>(isc_ctx* ctx) { return ctx->Lt; }
+template <> float* lt_buffer<float>(isc_ctx* ctx) { return ctx->Lt32; }
 }  // namespace isc
 
 // Fills the private sweep buffers with the sentinel (at creation and after a
@@ -538,7 +559,7 @@ hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t*
         const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
         hipLaunchKernelGGL(isc::bilu0_factor_level<T>, dim3((cnt + 3) / 4), dim3(256), 0, ctx->stream,
                            ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
-                           ctx->diag_pos, A, Dinv, bad_dev);
+                           ctx->diag_pos, A, Dinv, isc::lt_buffer<T>(ctx), bad_dev);
     }
     return hipGetLastError();
 }
@@ -550,8 +571,9 @@ hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, con
         const int32_t nwg = (ctx->nbrick + 3) / 4;
         const int32_t nbx = (ctx->g.nx + 1) / 2, nby = (ctx->g.ny + 1) / 2;
         hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(nwg), dim3(256), ISC_SWEEP_LDS, ctx->stream,
-                           ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr, A,
-                           Dinv, r, v, z, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+                           ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
+                           (const T*)isc::lt_buffer<T>(ctx), r, v, z, ctx->ticket, ctx->ticket_base,
+                           ctx->flags + ISC_FLAG_SWEEP);
         ctx->ticket_base += (unsigned long long)nwg;
         hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV>), dim3(nwg), dim3(256), ISC_SWEEP_LDS, ctx->stream,
                            ctx->bricks_bwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->diag_pos, A,
@@ -562,7 +584,7 @@ hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, con
     for (int32_t s = 0; s < ctx->nlev; ++s) {
         const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
         hipLaunchKernelGGL((isc::bilu0_fwd_level<T, TV>), dim3((cnt + 31) / 32), dim3(256), 0, ctx->stream,
-                           ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, ctx->row_ptr, A, Dinv, r, z);
+                           ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, (const T*)isc::lt_buffer<T>(ctx), r, z);
     }
     for (int32_t s = ctx->nlev - 1; s >= 0; --s) {
         const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
@@ -586,6 +608,12 @@ hipError_t isc_launch_bilu0_factor(isc_ctx* ctx, const double* A, double* Dinv, 
 }
 hipError_t isc_launch_bilu0_factor32(isc_ctx* ctx, const float* A, float* Dinv, int32_t* bad) {
     return isc_launch_bilu0_factor_t<float>(ctx, A, Dinv, bad);
+}
+// Lt of the context from a factor computed elsewhere (FP64).
+hipError_t isc_launch_form_ltilde(isc_ctx* ctx, const double* A, const double* Dinv) {
+    hipLaunchKernelGGL(isc::form_ltilde<double>, dim3((ctx->n + 3) / 4), dim3(256), 0, ctx->stream, ctx->n,
+                       ctx->g.nx, ctx->g.ny, ctx->row_ptr, A, Dinv, ctx->Lt);
+    return hipGetLastError();
 }
 hipError_t isc_launch_bilu0_apply(isc_ctx* ctx, const double* A, const double* Dinv, const double* r, double* z) {
     return isc_launch_bilu0_apply_t<double, double>(ctx, A, Dinv, r, z);
