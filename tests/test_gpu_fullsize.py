@@ -167,3 +167,48 @@ def test_fullsize_decouple_bilu_and_solve(c3):
     mfull = O.Model(wl)
     r = b.cpu().numpy() - mfull.spmv(Jdh, x.cpu().numpy())
     assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(b.cpu().numpy())
+
+
+def _timestep(ctx, wl, precision, inner):
+    """One implicit step from the initial state in parity mode (Newton to
+    1e-10, then one more iteration); returns the state and the Newton count."""
+    from paper_1811_11992_amd import isc
+    lin = isc.solve_opts(restart=30, max_restarts=20, rtol=1e-8, precision=precision, inner_iters=inner)
+    u = dev(wl.u0)
+    uo = u.clone()
+    for k in range(14):
+        st, info = ctx.isc_newton_step(u, uo, wl.dt, 1e-10, lin)
+        assert st == 0, (precision, k, st)
+        if info.converged:
+            break
+    assert info.converged, (precision, info.res_scaled)
+    st, info = ctx.isc_newton_step(u, uo, wl.dt, 0.0, lin)
+    assert st == 0
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), k
+
+
+def test_fullsize_newton_step_fp64_and_mixed_reach_the_oracle_root():
+    """A whole implicit step of the 2M-cell workload in FP64 and in the
+    precision form: both converge without a step cut, their states agree to
+    1e-8 (per variable, floors 1 Pa / 1 K / 1 / C_cmax), and the oracle's
+    scaled residual rows at the FP64 root, recomputed on 3x3x3 windows around
+    sampled cells, are <= 1e-10."""
+    from paper_1811_11992_amd import isc
+    wl = I.make_workload("C3")
+    ctx = isc.Context(wl, restart=30, inner_iters=6)
+    u64, k64 = _timestep(ctx, wl, isc.ISC_FP64, 0)
+    umx, kmx = _timestep(ctx, wl, isc.ISC_MIXED, 6)
+    fl = I.physics_card()
+    floors = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, fl.Ccmax])
+    rel = np.abs(umx - u64).max(axis=1) / np.maximum(np.abs(u64).max(axis=1), floors)
+    assert np.all(rel <= 1e-8), rel
+    V = wl.dx * wl.dy * wl.dz
+    for c in _samples(wl):
+        sub, cells, local = _window(wl, c)
+        m = O.Model(sub, fl)
+        F = m.residual(u64[:, cells], wl.u0[:, cells], wl.dt)[local]
+        sm = V * wl.poro[c] * fl.rho_ref[0] / wl.dt
+        se = V * (1.0 - wl.poro[c]) * fl.cp_rock / wl.dt
+        scaled = np.abs(F) / np.where(np.arange(8) == 6, se, sm)
+        assert scaled.max() <= 1e-10, (c, scaled)
