@@ -115,8 +115,10 @@ typedef struct {
 } isc_solve_opts;
 
 typedef struct {
-    int32_t iters;               /* outer Krylov iterations */
-    int32_t inner_iters_total;   /* ISC_MIXED: inner iterations */
+    int32_t iters;               /* outer Krylov iterations (columns of the solutions formed) */
+    int32_t inner_iters_total;   /* ISC_MIXED: inner iterations executed, including the one
+                                    preconditioner application per cycle whose residual test
+                                    ended the cycle (its column is not used) */
     int32_t restarts;
     int32_t reserved;
     double relres_est;           /* Arnoldi residual estimate / ||b|| */

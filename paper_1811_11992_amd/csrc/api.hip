@@ -289,8 +289,8 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->w, nv);
     ALLOC(ctx->tvec, nv);
     ALLOC(ctx->tvec2, nv);
-    ALLOC(ctx->partial, (size_t)64 * isc::NPART);
-    ALLOC(ctx->small, (size_t)4096);
+    ALLOC(ctx->partial, (size_t)65 * isc::NPART);   // 64 rows of dot partials + one norm row
+    ALLOC(ctx->small, (size_t)4096 + 32 * 32);   // scalars, Hessenberg, delayed-CGS2 state; Rs past 4096
     ALLOC(ctx->flags, (size_t)16);
     ALLOC(ctx->accJ, (size_t)n * isc::BS);
     ALLOC(ctx->qg, nv);

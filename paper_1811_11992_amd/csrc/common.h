@@ -122,8 +122,8 @@ struct isc_ctx {
     double* w = nullptr;            // [N*8]
     double* tvec = nullptr;         // [N*8]
     double* tvec2 = nullptr;        // [N*8]
-    double* partial = nullptr;      // [64][NPART] block partial sums
-    double* small = nullptr;        // device scalars: h, givens, g, y ...
+    double* partial = nullptr;      // [65][NPART] block partial sums
+    double* small = nullptr;        // device scalars: reductions, Hessenberg, Givens, g, y, delayed-CGS2 state
     int32_t* flags = nullptr;       // device ints: [0] error/bad cell
     // FP32 copies (mixed precision)
     float* J32 = nullptr;           // [nnzb][64]

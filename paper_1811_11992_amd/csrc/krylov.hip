@@ -9,8 +9,9 @@
 // both the reorthogonalisation coefficients of u_j and the projections of
 // w = A M^-1 u_j, the Arnoldi relation corrects the Hessenberg column, and one
 // fused pass writes q_j and u_{j+1}.  That is two passes over the basis per
-// iteration instead of three, with CGS2's orthogonality.
-// Flexible solver (precision form): CGS2 as two fused passes plus a norm pass.
+// iteration instead of three, with CGS2's orthogonality.  The flexible outer
+// solver of the precision form and its fixed-length FP32 inner solver use the
+// same iteration.
 // Reductions are two-stage with a fixed block count and a fixed order, so
 // results are bitwise reproducible.  The Hessenberg matrix, the Givens
 // rotations and the least-squares solution stay on the device; the host reads
@@ -61,51 +62,6 @@ __global__ void __launch_bounds__(256) multidot(int64_t len, const TV* __restric
     block_store(acc, nv, partial, gridDim.x);
 }
 
-// w <- w - sum_k h[k] V_k, then partial[k] = <V_k, w> (second CGS pass fused)
-template <class TV>
-__global__ void __launch_bounds__(256) update_multidot(int64_t len, const TV* __restrict__ V, int64_t ldv,
-                                                       int nv, const double* __restrict__ h,
-                                                       TV* __restrict__ w, double* __restrict__ partial) {
-    double acc[MAXV];
-    double hk[MAXV];
-#pragma unroll
-    for (int k = 0; k < MAXV; ++k) { acc[k] = 0.0; hk[k] = k < nv ? h[k] : 0.0; }
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
-        double vk[MAXV];
-        double wv = (double)w[t];
-#pragma unroll
-        for (int k = 0; k < MAXV; ++k)
-            if (k < nv) { vk[k] = (double)V[(size_t)k * ldv + t]; wv -= hk[k] * vk[k]; }
-        w[t] = (TV)wv;
-        wv = (double)w[t];
-#pragma unroll
-        for (int k = 0; k < MAXV; ++k)
-            if (k < nv) acc[k] += vk[k] * wv;
-    }
-    block_store(acc, nv, partial, gridDim.x);
-}
-
-// w <- w - sum_k h[k] V_k, partial[0] = ||w||^2
-template <class TV>
-__global__ void __launch_bounds__(256) update_norm(int64_t len, const TV* __restrict__ V, int64_t ldv, int nv,
-                                                   const double* __restrict__ h, TV* __restrict__ w,
-                                                   double* __restrict__ partial) {
-    double hk[MAXV];
-#pragma unroll
-    for (int k = 0; k < MAXV; ++k) hk[k] = k < nv ? h[k] : 0.0;
-    double acc[1] = {0.0};
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) {
-        double wv = (double)w[t];
-#pragma unroll
-        for (int k = 0; k < MAXV; ++k)
-            if (k < nv) wv -= hk[k] * (double)V[(size_t)k * ldv + t];
-        const TV ws = (TV)wv;
-        w[t] = ws;
-        acc[0] += (double)ws * (double)ws;
-    }
-    block_store(acc, 1, partial, gridDim.x);
-}
-
 // out[k] = sum of partial[k][0..nblk), fixed order; one block per k
 __global__ void __launch_bounds__(256) reduce_partials(const double* __restrict__ partial, int nblk,
                                                        double* __restrict__ out) {
@@ -117,15 +73,6 @@ __global__ void __launch_bounds__(256) reduce_partials(const double* __restrict_
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
     if (threadIdx.x == 0) out[k] = (red[0] + red[1]) + (red[2] + red[3]);
-}
-
-// y = x * s[0]  (s on the device)
-template <class TA, class TB>
-__global__ void __launch_bounds__(256) scale_copy(int64_t len, const TA* __restrict__ x, const double* __restrict__ s,
-                                                  TB* __restrict__ y) {
-    const double f = *s;
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256)
-        y[t] = (TB)((double)x[t] * f);
 }
 
 // out = sum_k y[k] V_k (+ out if accumulate)
@@ -171,41 +118,7 @@ struct Hess {
     double* H; double* cs; double* sn; double* g; double* y; double* scal;
     int m;
 };
-// scal: [0] beta / norm input, [1] 1/h_{j+1,j}, [2] residual estimate, [3] ||b||
-
-// start a cycle: g = (beta, 0, ...), scal[1] = 1/beta from ||r||^2 in nrm2[0]
-__global__ void gmres_start(Hess hs, const double* __restrict__ nrm2) {
-    const double beta = sqrt(nrm2[0]);
-    for (int k = 0; k <= hs.m; ++k) hs.g[k] = 0.0;
-    hs.g[0] = beta;
-    hs.scal[0] = beta;
-    hs.scal[1] = beta > 0.0 ? 1.0 / beta : 0.0;
-    hs.scal[2] = beta;
-}
-
-// column j of H from the two CGS passes h1 + h2 and ||w||^2; rotations
-__global__ void gmres_column(Hess hs, int j, const double* __restrict__ h1, const double* __restrict__ h2,
-                             const double* __restrict__ nrm2) {
-    double* col = hs.H + (size_t)j * (hs.m + 1);
-    for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-    const double hn = sqrt(nrm2[0]);
-    col[j + 1] = hn;
-    for (int i = 0; i < j; ++i) {
-        const double a = col[i], b = col[i + 1];
-        col[i] = hs.cs[i] * a + hs.sn[i] * b;
-        col[i + 1] = -hs.sn[i] * a + hs.cs[i] * b;
-    }
-    const double a = col[j], b = col[j + 1];
-    const double den = hypot(a, b);
-    hs.cs[j] = den > 0.0 ? a / den : 1.0;     // exact breakdown: identity rotation
-    hs.sn[j] = den > 0.0 ? b / den : 0.0;
-    col[j] = den;
-    col[j + 1] = 0.0;
-    hs.g[j + 1] = -hs.sn[j] * hs.g[j];
-    hs.g[j] = hs.cs[j] * hs.g[j];
-    hs.scal[1] = hn > 0.0 ? 1.0 / hn : 0.0;
-    hs.scal[2] = fabs(hs.g[j + 1]);
-}
+// scal: [0] beta, [2] residual estimate of the current column count, [4] breakdown flag
 
 // y = R^-1 g for the leading k x k triangle
 __global__ void gmres_solve_small(Hess hs, int k) {
@@ -302,6 +215,7 @@ struct Dcgs {
     double* Hraw;    // [(m+1) x m], column-major
     double* hprev;   // [m+1]
     double* omz;     // [0] omega_j, [1] zeta_j
+    double* Rs;      // flexible variant only (else null): [m x (m+1)], column j = (s_j, omega_j)
 };
 
 // Iteration j (one thread).  c holds the dots of this iteration.  Finishes
@@ -324,6 +238,10 @@ __global__ void dcgs2_step(Hess hs, Dcgs d, int j, int last, const double* __res
         return;
     }
     const double om = om2 > 0.0 ? sqrt(om2) : 0.0;
+    if (d.Rs && j < m) {   // u_j = omega_j q_j + Q_j s_j
+        for (int i = 0; i < j; ++i) d.Rs[(size_t)j * ld + i] = c[i];
+        d.Rs[(size_t)j * ld + j] = om;
+    }
     if (j == 0) {
         for (int k = 0; k <= m; ++k) hs.g[k] = 0.0;
         hs.g[0] = om;
@@ -371,12 +289,44 @@ __global__ void dcgs2_step(Hess hs, Dcgs d, int j, int last, const double* __res
     d.omz[1] = zeta;
 }
 
+// Residual estimate a j-column solution would have, taking column j-1 as
+// (hprev, ||u_j||): the reorthogonalisation coefficients s_j of u_j are left
+// out (they are of the order of rounding), so no preconditioner application
+// is needed to decide whether the cycle has converged.  State is not changed;
+// the estimate goes to scal[5].
+__global__ void dcgs2_probe(Hess hs, Dcgs d, int j, const double* __restrict__ nrm2) {
+    double col[MAXV + 1];
+    for (int i = 0; i < j; ++i) col[i] = d.hprev[i];
+    col[j] = sqrt(fmax(nrm2[0], 0.0));
+    for (int i = 0; i < j - 1; ++i) {
+        const double a = col[i], b = col[i + 1];
+        col[i] = hs.cs[i] * a + hs.sn[i] * b;
+        col[i + 1] = -hs.sn[i] * a + hs.cs[i] * b;
+    }
+    const double den = hypot(col[j - 1], col[j]);
+    const double sn = den > 0.0 ? col[j] / den : 0.0;
+    hs.scal[5] = fabs(sn * hs.g[j - 1]);
+}
+
+// Flexible variant: the stored vectors are zt_j = P(u_j) = omega_j z_j +
+// Z_j s_j, i.e. Zt = Z Rs with Rs upper triangular, so Z y = Zt (Rs^-1 y);
+// y (k entries, from gmres_solve_small) is replaced by Rs^-1 y.
+__global__ void dcgs2_solve_rs(Hess hs, Dcgs d, int k) {
+    const int ld = hs.m + 1;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = hs.y[i];
+        for (int j = i + 1; j < k; ++j) s -= d.Rs[(size_t)j * ld + i] * hs.y[j];
+        const double dd = d.Rs[(size_t)i * ld + i];
+        hs.y[i] = dd != 0.0 ? s / dd : 0.0;
+    }
+}
+
 // One pass: q_j = (u - Q_j s) / omega  and  u <- (w - Q_j z - zeta q_j) / omega
 // (omega = 0, a breakdown, leaves q_j = u = 0).
 template <class V2>
 __global__ void __launch_bounds__(256) dcgs2_update(int64_t len2, V2* Q, int64_t ldv2, int j,
                                                     const double* __restrict__ c, const double* __restrict__ omz,
-                                                    V2* u, const V2* __restrict__ w) {
+                                                    V2* u, const V2* __restrict__ w, double* __restrict__ nrm_partial) {
     double sk[MAXV], zk[MAXV];
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) {
@@ -385,6 +335,7 @@ __global__ void __launch_bounds__(256) dcgs2_update(int64_t len2, V2* Q, int64_t
     }
     const double rom = omz[0] > 0.0 ? 1.0 / omz[0] : 0.0, zeta = omz[1];
     V2* qj = Q + (size_t)j * ldv2;
+    double nacc[1] = {0.0};
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len2; t += (int64_t)gridDim.x * 256) {
         const V2 uv = u[t];
         const V2 wv = w[t];
@@ -407,7 +358,9 @@ __global__ void __launch_bounds__(256) dcgs2_update(int64_t len2, V2* Q, int64_t
         uo.y = ((double)wv.y - zy - zeta * qy) * rom;
         qj[t] = qo;
         u[t] = uo;
+        nacc[0] += (double)uo.x * (double)uo.x + (double)uo.y * (double)uo.y;
     }
+    if (nrm_partial) block_store(nacc, 1, nrm_partial, gridDim.x);   // ||u_{j+1}||^2 per block
 }
 
 }  // namespace isc
@@ -462,11 +415,13 @@ static hipError_t read_scalar(isc_ctx* ctx, const double* dsrc, double* out) {
 namespace isc {
 // delayed-CGS2 state lives after the Hessenberg block of ctx->small
 constexpr int DCGS_OFF = 1400;
+constexpr int RS_OFF = 4096;     // Rs of the flexible solver: (m+1)^2 doubles past the first 4096
 Dcgs dcgs_at(double* small, int m) {
     Dcgs d;
     d.Hraw = small + DCGS_OFF;
     d.hprev = d.Hraw + (size_t)(m + 1) * m;
     d.omz = d.hprev + (m + 1);
+    d.Rs = nullptr;
     return d;
 }
 }  // namespace isc
@@ -546,7 +501,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
             ISC_HIP(hipEventRecord(ev, ctx->stream));
             if (!last)   // speculative: unused if the estimate below ends the cycle
                 hipLaunchKernelGGL(dcgs2_update<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, red,
-                                   dc.omz, u2, w2);
+                                   dc.omz, u2, w2, (double*)nullptr);
             isc_prof_end(ctx, tk);
             ISC_HIP(hipEventSynchronize(ev));
             const double est = ctx->hscratch[2];
@@ -656,7 +611,7 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
         hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hi, di, j, last ? 1 : 0, red);
         if (!last)
             hipLaunchKernelGGL(dcgs2_update<float2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, len2, j, red,
-                               di.omz, u2, w2);
+                               di.omz, u2, w2, (double*)nullptr);
         isc_prof_end(ctx, tk);
     }
     hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hi, m_in);
@@ -670,18 +625,32 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
 
 }  // namespace isc
 
-// FP64 flexible GMRES(m) whose preconditioner is the FP32 inner GMRES above.
+// FP64 flexible GMRES(m) whose preconditioner is the FP32 inner GMRES above,
+// with the same delayed CGS2 as the FP64 solver.  Iteration j stores
+// zt_j = P(u_j) for the lagged vector u_j; since u_j = omega_j q_j + Q_j s_j,
+// zt_j = omega_j z_j + Z_j s_j for the vectors z_j that satisfy the flexible
+// Arnoldi relation A Z = Q H, so the update x += Z y is done as
+// x += Zt (Rs^-1 y) with the small triangular Rs of the (s_j, omega_j).
 // ctx->J32 / ctx->Dinv32 must hold the FP32 matrix and factor.
 isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, double* x, const isc_solve_opts* o,
                            isc_solve_info* info) {
     using namespace isc;
     const int64_t len = (int64_t)ctx->n * NU;
     const int64_t ldv = len;
+    const int64_t len2 = len / 2, ldv2 = ldv / 2;
     const int m = o->restart;
     const int m_in = o->inner_iters;
     const int nb = nblocks(len);
+    const int nb2 = nblocks(len2);
+    const int nb2u = nb2;   // blocks of the update pass (its norm partials)
     Hess hs = hess_of(ctx);
+    Dcgs dc = dcgs_at(ctx->small, ctx->mmax);
+    dc.Rs = ctx->small + RS_OFF;
     double* red = ctx->small + RED_OFF;
+    double2* Q2 = reinterpret_cast<double2*>(ctx->V);
+    double* u = ctx->V + (size_t)m * ldv;
+    double2* u2 = reinterpret_cast<double2*>(u);
+    const double2* w2 = reinterpret_cast<const double2*>(ctx->w);
     isc_solve_info inf{};
     double bn2;
     norm2_dev(ctx, len, b, red + 2 * MAXV);
@@ -697,11 +666,14 @@ isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, doubl
         return ISC_ERR_NONFINITE;
     }
     isc_status st = ISC_ERR_LINEAR_NOCONV;
+    hipEvent_t ev = ctx->ev[7];
     for (int cyc = 0; cyc < o->max_restarts; ++cyc) {
-        const double* r0 = b;
-        if (cyc > 0) {
+        // u_0 = r = b - A x  (x = 0 on the first cycle)
+        if (cyc == 0) {
+            ISC_HIP(hipMemcpyAsync(u, b, (size_t)len * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+        } else {
             isc_launch_spmv(ctx, A, x, ctx->tvec);
-            hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, ctx->w,
+            hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, u,
                                ctx->partial);
             hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
                                red + 2 * MAXV);
@@ -710,58 +682,69 @@ isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, doubl
             inf.relres_true = sqrt(rn2) / bnorm;
             if (sqrt(rn2) <= o->rtol * bnorm) { st = ISC_OK; break; }
             inf.restarts = cyc;
-            r0 = ctx->w;
-        } else {
-            hipLaunchKernelGGL(multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, b, (int64_t)0, 1, b,
-                               ctx->partial);
-            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
-                               red + 2 * MAXV);
         }
-        hipLaunchKernelGGL(gmres_start, dim3(1), dim3(1), 0, ctx->stream, hs, red + 2 * MAXV);
-        hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, r0, hs.scal + 1,
-                           ctx->V);
-        int jdone = 0;
-        for (int j = 0; j < m; ++j) {
-            double* Vj = ctx->V + (size_t)j * ldv;
-            double* Vn = ctx->V + (size_t)(j + 1) * ldv;
-            double* Zj = ctx->Z + (size_t)j * ldv;
-            inner_gmres32(ctx, ctx->J32, ctx->Dinv32, Vj, Zj, m_in);
-            int tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
-            isc_launch_spmv(ctx, A, Zj, ctx->w);
+        int k = m;
+        for (int j = 0; j <= m; ++j) {
+            bool last = j == m;
+            if (!last && j > 0) {
+                // probe: does the cycle converge with j columns?  (||u_j||^2 from the update pass)
+                hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial + (size_t)2 * MAXV * NPART,
+                                   nb2u, red + 2 * MAXV + 1);
+                hipLaunchKernelGGL(dcgs2_probe, dim3(1), dim3(1), 0, ctx->stream, hs, dc, j, red + 2 * MAXV + 1);
+                double probe;
+                ISC_HIP(read_scalar(ctx, hs.scal + 5, &probe));
+                if (probe <= o->rtol * bnorm) last = true;   // finish the cycle without another P application
+            }
+            if (!last) {
+                double* Zj = ctx->Z + (size_t)j * ldv;
+                inner_gmres32(ctx, ctx->J32, ctx->Dinv32, u, Zj, m_in);
+                const int tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
+                isc_launch_spmv(ctx, A, Zj, ctx->w);
+                isc_prof_end(ctx, tk);
+            }
+            const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
+            hipLaunchKernelGGL(dcgs2_dots<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, u2,
+                               last ? nullptr : w2, ctx->partial);
+            hipLaunchKernelGGL(reduce_rows_dcgs, dim3(last ? j + 1 : 2 * (j + 1)), dim3(256), 0, ctx->stream,
+                               ctx->partial, nb2, j, red);
+            hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hs, dc, j, last ? 1 : 0, red);
+            ISC_HIP(hipMemcpyAsync(ctx->hscratch, hs.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+            ISC_HIP(hipEventRecord(ev, ctx->stream));
+            if (!last)   // speculative: unused if the estimate below ends the cycle
+                hipLaunchKernelGGL(dcgs2_update<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j,
+                                   red, dc.omz, u2, w2, ctx->partial + (size_t)2 * MAXV * NPART);
             isc_prof_end(ctx, tk);
-            tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
-            hipLaunchKernelGGL(multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, j + 1,
-                               ctx->w, ctx->partial);
-            hipLaunchKernelGGL(reduce_partials, dim3(j + 1), dim3(256), 0, ctx->stream, ctx->partial, nb, red);
-            hipLaunchKernelGGL(update_multidot<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv,
-                               j + 1, red, ctx->w, ctx->partial);
-            hipLaunchKernelGGL(reduce_partials, dim3(j + 1), dim3(256), 0, ctx->stream, ctx->partial, nb,
-                               red + MAXV);
-            hipLaunchKernelGGL(update_norm<double>, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, j + 1,
-                               red + MAXV, ctx->w, ctx->partial);
-            hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
-                               red + 2 * MAXV);
-            hipLaunchKernelGGL(gmres_column, dim3(1), dim3(1), 0, ctx->stream, hs, j, red, red + MAXV,
-                               red + 2 * MAXV);
-            hipLaunchKernelGGL((scale_copy<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->w,
-                               hs.scal + 1, Vn);
-            isc_prof_end(ctx, tk);
-            double est;
-            ISC_HIP(read_scalar(ctx, hs.scal + 2, &est));
-            inf.iters++;
-            inf.inner_iters_total += m_in;
-            jdone = j + 1;
-            inf.relres_est = est / bnorm;
+            ISC_HIP(hipEventSynchronize(ev));
+            const double est = ctx->hscratch[2];
+            const bool breakdown = ctx->hscratch[4] != 0.0;
             if (!std::isfinite(est)) {
+                (void)hipStreamSynchronize(ctx->stream);
+                isc_prof_drain(ctx);
                 if (isc_check_sweeps(ctx) != ISC_OK) return ISC_ERR_HIP;
                 ctx->err = "isc_solve: FGMRES breakdown (non-finite residual estimate)";
                 return ISC_ERR_NONFINITE;
             }
-            if (est <= o->rtol * bnorm) break;
+            if (!last) inf.inner_iters_total += m_in;
+            if (j == 0) {
+                if (breakdown) {
+                    k = 0;
+                    break;
+                }
+                continue;
+            }
+            inf.iters++;
+            inf.relres_est = est / bnorm;
+            if (est <= o->rtol * bnorm || breakdown || last) {
+                k = j;
+                break;
+            }
         }
-        hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hs, jdone);
-        hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->Z, ldv, jdone,
-                           hs.y, x, 1);
+        if (k > 0) {   // x += Zt (Rs^-1 R^-1 g)
+            hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hs, k);
+            hipLaunchKernelGGL(dcgs2_solve_rs, dim3(1), dim3(1), 0, ctx->stream, hs, dc, k);
+            hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->Z, ldv, k,
+                               hs.y, x, 1);
+        }
     }
     if (st != ISC_OK) {
         isc_launch_spmv(ctx, A, x, ctx->tvec);

@@ -296,7 +296,10 @@ def test_mixed_solve_reaches_fp64_tolerance(name, seed):
     b = -Fd
     c = ctx_for(wl, inner_iters=6)
     x, info, st = c.isc_solve(dev(Jd), dev(b), isc.solve_opts(rtol=1e-8, precision=isc.ISC_MIXED, inner_iters=6))
-    assert st == 0 and info.relres_true <= 1e-8 and info.inner_iters_total == 6 * info.iters
+    assert st == 0 and info.relres_true <= 1e-8
+    # one inner solve per column, plus at most one per cycle whose residual test ended the cycle
+    assert info.inner_iters_total % 6 == 0
+    assert 6 * info.iters <= info.inner_iters_total <= 6 * (info.iters + info.restarts + 1)
     xg = host(x)
     assert np.linalg.norm(b - m.spmv(Jd, xg)) <= 1.01e-8 * np.linalg.norm(b)
     st, x_ref, _ = m.gmres(Jd, b, rtol=1e-13, max_restarts=60)
