@@ -229,8 +229,9 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     std::vector<int32_t> lvl_rows(n), fillp(ctx->lvl_off_h.begin(), ctx->lvl_off_h.end() - 1);
     for (int32_t i = 0; i < n; ++i) lvl_rows[fillp[i % nx + (i / nx) % ny + i / nxy]++] = i;
 
-    // 2x2x2 bricks by brick level (sync-free sweeps), ascending brick index inside a level
-    const int32_t nbx = (nx + 1) / 2, nby = (ny + 1) / 2, nbz = (nz + 1) / 2;
+    // bricks by brick level (sync-free sweeps), ascending brick index inside a level
+    const int32_t nbx = (nx + isc::BRICK_X - 1) / isc::BRICK_X, nby = (ny + isc::BRICK_Y - 1) / isc::BRICK_Y,
+                  nbz = (nz + isc::BRICK_Z - 1) / isc::BRICK_Z;
     ctx->nbrick = nbx * nby * nbz;
     std::vector<int32_t> chf((size_t)ctx->nbrick), chb;
     {

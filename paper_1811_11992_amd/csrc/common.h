@@ -12,6 +12,8 @@ namespace isc {
 
 constexpr int NU = 8;        // unknowns per cell
 constexpr int BS = 64;       // 8x8 block
+// cells of one brick of the sync-free triangular sweeps (one 256-thread workgroup)
+constexpr int BRICK_X = 4, BRICK_Y = 4, BRICK_Z = 2;
 // Per-cell property payload written by the property pass and read by the
 // face-flux assembly (doubles, value followed by the 8 partial derivatives):
 //   [0, 72)     local residual terms of the 8 rows (accumulation change,
@@ -96,8 +98,8 @@ struct isc_ctx {
     int32_t nlev = 0;
     std::vector<int32_t> lvl_off_h;
     int32_t* lvl_rows = nullptr;
-    // sync-free triangular sweeps: 2x2x2 bricks listed by ascending (forward)
-    // and descending (backward) brick level; tickets order the workgroups
+    // sync-free triangular sweeps: bricks listed by ascending (forward) and
+    // descending (backward) brick level; tickets order the workgroups
     bool syncfree = true;
     int32_t nbrick = 0;
     int32_t* bricks_fwd = nullptr;

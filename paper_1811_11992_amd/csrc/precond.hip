@@ -306,41 +306,49 @@ __device__ __forceinline__ int32_t take_ticket(unsigned long long* ticket, unsig
     return s_t;
 }
 
-// Bricks: a wavefront owns a 2x2x2 brick of cells (lane = 8 * g + r, brick
-// cell g = dx + 2 dy + 4 dz, block row r).  A brick depends only on the
-// bricks below it in x, y and z, so the chain of waits is bx + by + bz long
-// instead of ix + iy + iz.  Inside the brick the cells are finished in four
-// steps (dx + dy + dz = 0..3), taking in-brick predecessors from the lanes
-// that computed them; each cell still subtracts its neighbours in the order
-// z-, y-, x- (forward) and x+, y+, z+ (backward), as the level launches do.
+// Bricks: a workgroup owns a BRICK_X x BRICK_Y x BRICK_Z brick of cells
+// (thread = 8 * g + r, brick cell g = dx + BRICK_X (dy + BRICK_Y dz), block
+// row r; the eight rows of a cell share one wavefront).  A brick depends only
+// on the bricks below it in x, y and z, so the chain of waits is
+// bx + by + bz long (123 on the 200x200x50 grid) instead of ix + iy + iz (448).
+// Inside the brick the cells are finished in BRICK_STEPS steps
+// (dx + dy + dz = 0, 1, ...), taking in-brick predecessors from LDS; each cell
+// still subtracts its neighbours in the order z-, y-, x- (forward) and x+,
+// y+, z+ (backward), as the level launches do.
+constexpr int BRICK_CELLS = BRICK_X * BRICK_Y * BRICK_Z;
+constexpr int BRICK_STEPS = BRICK_X + BRICK_Y + BRICK_Z - 2;
+static_assert(BRICK_CELLS * 8 == 256, "one brick per 256-thread workgroup");
+
 struct BrickCell {
     int32_t i;      // row, or -1 outside the grid
     int32_t ii;     // row clamped to 0
-    int g, r, gbase, step;
+    int g, r, step, dx, dy, dz;
 };
 __device__ __forceinline__ BrickCell brick_cell(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny,
                                                 int32_t nz) {
     BrickCell bc;
-    const int lane = threadIdx.x & 63;
-    bc.g = lane >> 3;
-    bc.r = lane & 7;
-    bc.gbase = threadIdx.x & 56;
+    bc.g = threadIdx.x >> 3;
+    bc.r = threadIdx.x & 7;
     const int32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
-    const int dx = bc.g & 1, dy = (bc.g >> 1) & 1, dz = bc.g >> 2;
-    const int32_t ix = 2 * bx + dx, iy = 2 * by + dy, iz = 2 * bz + dz;
-    bc.step = dx + dy + dz;
+    bc.dx = bc.g % BRICK_X;
+    bc.dy = (bc.g / BRICK_X) % BRICK_Y;
+    bc.dz = bc.g / (BRICK_X * BRICK_Y);
+    const int32_t ix = BRICK_X * bx + bc.dx, iy = BRICK_Y * by + bc.dy, iz = BRICK_Z * bz + bc.dz;
+    bc.step = bc.dx + bc.dy + bc.dz;
     bc.i = (ix < nx && iy < ny && iz < nz) ? ix + nx * (iy + ny * iz) : -1;
     bc.ii = bc.i >= 0 ? bc.i : 0;
     return bc;
 }
 
-// In-brick exchange through a per-wavefront LDS scratch: LDS operations of
-// one wavefront complete in issue order, so a fence at wavefront scope is
-// enough between a lane's write and another lane's read.
+// In-brick exchange through LDS: results of the previous steps (double
+// buffered, one block barrier per step), accumulators before the D^-1 product
+// (exchanged inside a wavefront: LDS operations of one wavefront complete in
+// issue order, so a wavefront-scope fence is enough), and the values taken
+// from other bricks.
 struct alignas(16) BrickLds {
-    double v[64];        // [cell][row]: results of the previous cell steps
-    double acc[64];      // [cell][row]: accumulators before the D^-1 product
-    double ext[3][64];   // [neighbour][cell][row]: values from other bricks (0 if none)
+    double v[2][BRICK_CELLS * 8];
+    double acc[BRICK_CELLS * 8];
+    double ext[3][BRICK_CELLS * 8];
 };
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -372,7 +380,8 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     const int32_t ix = ii % nx, iy = (ii / nx) % ny, iz = ii / nxy;
     const int32_t lower[3] = {iz > 0 ? ii - nxy : -1, iy > 0 ? ii - nx : -1, ix > 0 ? ii - 1 : -1};
     // in-brick predecessor (brick cell index) or -1
-    const int inb[3] = {(bc.g & 4) ? bc.g - 4 : -1, (bc.g & 2) ? bc.g - 2 : -1, (bc.g & 1) ? bc.g - 1 : -1};
+    const int inb[3] = {bc.dz > 0 ? bc.g - BRICK_X * BRICK_Y : -1, bc.dy > 0 ? bc.g - BRICK_X : -1,
+                        bc.dx > 0 ? bc.g - 1 : -1};
     // everything that does not depend on other rows is loaded first, without
     // branches (the slot of a missing neighbour is read and masked)
     double arow[3][8];
@@ -397,30 +406,25 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     double xg[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(y + (size_t)lower[q] * NU + r, first[q], err) : 0.0;
-    __shared__ BrickLds lds_all[4];
-    BrickLds& L = lds_all[threadIdx.x >> 6];
+    __shared__ BrickLds L;
     const int me = bc.g * 8 + r;
 #pragma unroll
     for (int q = 0; q < 3; ++q) L.ext[q][me] = xg[q];
-    // neighbour q's row block: in this brick (results so far) or outside (ext)
-    const double* src[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) src[q] = (lower[q] >= 0 && inb[q] >= 0) ? &L.v[inb[q] * 8] : &L.ext[q][bc.g * 8];
     double yout = 0.0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        L.v[me] = yout;
-        wave_lds_sync();
+    for (int s = 0; s < BRICK_STEPS; ++s) {
+        const int buf = s & 1;
+        L.v[buf][me] = yout;
+        __syncthreads();
         double acc = rv;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
+            const double* src = (lower[q] >= 0 && inb[q] >= 0) ? &L.v[buf][inb[q] * 8] : &L.ext[q][bc.g * 8];
             double x[8];
-            lds_row8(src[q], x);
+            lds_row8(src, x);
 #pragma unroll
             for (int c = 0; c < 8; ++c) acc -= arow[q][c] * x[c];
         }
         if (bc.step == s) yout = acc;
-        wave_lds_sync();
     }
     if (act) publish(y + (size_t)ii * NU + r, (TV)yout);
 }
@@ -438,7 +442,8 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     const int32_t nxy = nx * ny;
     const int32_t ix = ii % nx, iy = (ii / nx) % ny, iz = ii / nxy;
     const int32_t upper[3] = {ix + 1 < nx ? ii + 1 : -1, iy + 1 < ny ? ii + nx : -1, iz + 1 < nz ? ii + nxy : -1};
-    const int inb[3] = {(bc.g & 1) ? -1 : bc.g + 1, (bc.g & 2) ? -1 : bc.g + 2, (bc.g & 4) ? -1 : bc.g + 4};
+    const int inb[3] = {bc.dx < BRICK_X - 1 ? bc.g + 1 : -1, bc.dy < BRICK_Y - 1 ? bc.g + BRICK_X : -1,
+                        bc.dz < BRICK_Z - 1 ? bc.g + BRICK_X * BRICK_Y : -1};
     double arow[3][8];
     const int32_t b0 = diag_pos[ii];
     int32_t blk = b0 + 1;
@@ -467,24 +472,22 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     double xg[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(z + (size_t)upper[q] * NU + r, first[q], err) : 0.0;
-    __shared__ BrickLds lds_all[4];
-    BrickLds& L = lds_all[threadIdx.x >> 6];
+    __shared__ BrickLds L;
     const int me = bc.g * 8 + r;
 #pragma unroll
     for (int q = 0; q < 3; ++q) L.ext[q][me] = xg[q];
-    const double* src[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) src[q] = (upper[q] >= 0 && inb[q] >= 0) ? &L.v[inb[q] * 8] : &L.ext[q][bc.g * 8];
+    const int mystep = BRICK_STEPS - 1 - bc.step;
     double zout = 0.0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        L.v[me] = zout;
-        wave_lds_sync();
+    for (int s = 0; s < BRICK_STEPS; ++s) {
+        const int buf = s & 1;
+        L.v[buf][me] = zout;
+        __syncthreads();
         double acc = yi;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
+            const double* src = (upper[q] >= 0 && inb[q] >= 0) ? &L.v[buf][inb[q] * 8] : &L.ext[q][bc.g * 8];
             double x[8];
-            lds_row8(src[q], x);
+            lds_row8(src, x);
 #pragma unroll
             for (int c = 0; c < 8; ++c) acc -= arow[q][c] * x[c];
         }
@@ -495,19 +498,19 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
         double t = 0.0;
 #pragma unroll
         for (int c = 0; c < 8; ++c) t += drow[c] * a8[c];
-        if (3 - bc.step == s) zout = t;
+        if (mystep == s) zout = t;
         wave_lds_sync();
     }
     if (act) publish(z + (size_t)ii * NU + r, (TV)zout);
 }
 
-// A workgroup takes one ticket; wavefront w handles brick list entry 4 t + w.
+// One workgroup per brick; workgroups take tickets in brick-list order.
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y, TV* __restrict__ z, unsigned long long* ticket,
     unsigned long long base, int32_t* err) {
-    const int32_t k = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
+    const int32_t k = take_ticket(ticket, base);
     if (k >= nbrick) return;
     fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, Lt, rin, y, z, err);
 }
@@ -517,7 +520,7 @@ __global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ y,
     TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
-    const int32_t k = take_ticket(ticket, base) * 4 + (int32_t)(threadIdx.x >> 6);
+    const int32_t k = take_ticket(ticket, base);
     if (k >= nbrick) return;
     bwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, err);
 }
@@ -568,8 +571,9 @@ template <class T, class TV>
 hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, const TV* r, TV* z) {
     if (ctx->syncfree) {
         TV* v = isc::sweep_buffer<TV>(ctx);
-        const int32_t nwg = (ctx->nbrick + 3) / 4;
-        const int32_t nbx = (ctx->g.nx + 1) / 2, nby = (ctx->g.ny + 1) / 2;
+        const int32_t nwg = ctx->nbrick;   // one workgroup per brick
+        const int32_t nbx = (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X;
+        const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
         hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(nwg), dim3(256), ISC_SWEEP_LDS, ctx->stream,
                            ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
                            (const T*)isc::lt_buffer<T>(ctx), r, v, z, ctx->ticket, ctx->ticket_base,
