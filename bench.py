@@ -61,6 +61,10 @@ def algorithmic_bytes(n, nnzb):
         # the same in FP32 storage (precision form)
         "ilu_apply32": (off64 + n * 64 * 8 + 4 * vec64) // 2,
         "spmv32": (off64 + 2 * vec64) // 2,
+        # the GMRES iteration's w = A M^-1 u: BILU(0) apply and SpMV in one pass
+        # (the SpMV reads z as the backward sweep produces it)
+        "ilu_spmv": (off64 + n * 64 * 8 + 4 * vec64) + (off64 + 2 * vec64),
+        "ilu_spmv32": ((off64 + n * 64 * 8 + 4 * vec64) + (off64 + 2 * vec64)) // 2,
         # u, u_old, porosity, 3 transmissibilities in; F and J out
         "assemble": 2 * vec64 + n * 8 * 4 + vec64 + nnzb * 64 * 8,
     }

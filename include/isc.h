@@ -189,6 +189,12 @@ isc_status isc_spmv(isc_ctx* ctx, const double* Jdec, const double* x, double* y
 isc_status isc_bilu0(isc_ctx* ctx, const double* Jdec, double* Dinv /* [N][8][8] */);
 isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv, const double* r,
                            double* z);
+/* z = M^-1 r and w = Jdec z in one call (the preconditioned operator of the
+ * GMRES iteration): the backward sweep of the BILU(0) apply and the SpMV run as
+ * one launch, each SpMV brick scheduled after the sweep of its neighbours.
+ * r, z, w: [N][8], pairwise distinct. */
+isc_status isc_bilu0_apply_spmv(isc_ctx* ctx, const double* Jdec, const double* Dinv, const double* r,
+                                double* z, double* w);
 isc_status isc_update(isc_ctx* ctx, double* u, const double* du /* [N][8] */);
 isc_status isc_scaled_norm(isc_ctx* ctx, const double* F, double dt, double* res_h);
 
@@ -219,9 +225,11 @@ isc_status isc_oil_rate(isc_ctx* ctx, const double* u, double* q_h);
  * (property pass + face assembly), 3 decoupling, 4 BILU(0) factor (all
  * levels), 5 Krylov vector work (orthogonalisation, updates, norms, in both
  * precisions), 6 FP32 BILU(0) apply and 7 FP32 SpMV (the inner solver of the
- * precision form). */
+ * precision form), 8 BILU(0) apply fused with the SpMV (z = M^-1 r, w = A z;
+ * the FP64 GMRES iteration), 9 reserved. */
 enum { ISC_PROF_SPMV = 0, ISC_PROF_ILU_APPLY, ISC_PROF_ASSEMBLE, ISC_PROF_DECOUPLE, ISC_PROF_ILU_FACTOR,
-       ISC_PROF_KRYLOV, ISC_PROF_ILU_APPLY32, ISC_PROF_SPMV32, ISC_PROF_NCLASS = 8 };
+       ISC_PROF_KRYLOV, ISC_PROF_ILU_APPLY32, ISC_PROF_SPMV32, ISC_PROF_ILU_SPMV, ISC_PROF_ILU_SPMV32,
+       ISC_PROF_NCLASS = 10 };
 isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* count_h);
 
 const char* isc_last_error(const isc_ctx* ctx);

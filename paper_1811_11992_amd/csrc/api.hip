@@ -14,6 +14,8 @@ hipError_t isc_launch_decouple(isc_ctx*, double* J, double* F, int32_t* bad_dev)
 hipError_t isc_launch_bilu0_factor(isc_ctx*, const double* A, double* Dinv, int32_t* bad);
 hipError_t isc_launch_bilu0_apply(isc_ctx*, const double* A, const double* Dinv, const double* r, double* z);
 hipError_t isc_launch_form_ltilde(isc_ctx*, const double* A, const double* Dinv);
+hipError_t isc_launch_bilu0_apply_spmv(isc_ctx*, const double* A, const double* Dinv, const double* r, double* z,
+                                       double* w);
 hipError_t isc_launch_spmv(isc_ctx*, const double* A, const double* x, double* y);
 hipError_t isc_launch_update(isc_ctx*, double* u, const double* du, int32_t* flag_dev);
 hipError_t isc_launch_scaled_norm(isc_ctx*, const double* F, double dt, double* out_dev);
@@ -27,6 +29,10 @@ isc_status isc_adjoint_impl(isc_ctx*, const double* u_n, const double* u_nm1, do
                             const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
                             double* g_A_h, const isc_solve_opts* o, isc_solve_info* info_h);
 isc_status isc_oil_rate_impl(isc_ctx*, const double* u, double* q_h);
+
+#ifndef ISC_SPMV_LAG
+#define ISC_SPMV_LAG 0   // brick levels between the sweep front and the SpMV bricks of the fused kernel
+#endif
 
 namespace {
 
@@ -233,7 +239,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     const int32_t nbx = (nx + isc::BRICK_X - 1) / isc::BRICK_X, nby = (ny + isc::BRICK_Y - 1) / isc::BRICK_Y,
                   nbz = (nz + isc::BRICK_Z - 1) / isc::BRICK_Z;
     ctx->nbrick = nbx * nby * nbz;
-    std::vector<int32_t> chf((size_t)ctx->nbrick), chb;
+    std::vector<int32_t> chf((size_t)ctx->nbrick), chb, items;
     {
         const int32_t nbl = nbx + nby + nbz - 2;
         std::vector<int32_t> off(nbl + 2, 0);
@@ -241,6 +247,22 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         for (int32_t s = 0; s <= nbl; ++s) off[s + 1] += off[s];
         for (int32_t b = 0; b < ctx->nbrick; ++b) chf[off[b % nbx + (b / nbx) % nby + b / (nbx * nby)]++] = b;
         chb.assign(chf.rbegin(), chf.rend());
+        // fused backward sweep + SpMV: after the backward bricks of level L come the
+        // SpMV bricks of level L + 1 + ISC_SPMV_LAG (their neighbours are at levels
+        // L + ISC_SPMV_LAG .. L + 2 + ISC_SPMV_LAG, all swept before them); the lag
+        // keeps SpMV bricks from waiting on the sweep front
+        auto level_of = [&](int32_t b) { return b % nbx + (b / nbx) % nby + b / (nbx * nby); };
+        std::vector<std::vector<int32_t>> by_level(nbl);
+        for (int32_t b : chb) by_level[level_of(b)].push_back(b);
+        items.reserve((size_t)2 * ctx->nbrick);
+        int32_t next_spmv = nbl - 1;   // highest level whose SpMV bricks are not listed yet
+        for (int32_t L = nbl - 1; L >= 0; --L) {
+            for (int32_t b : by_level[L]) items.push_back(b);
+            for (; next_spmv >= 0 && next_spmv >= L + 1 + ISC_SPMV_LAG; --next_spmv)
+                for (int32_t b : by_level[next_spmv]) items.push_back(b | (1 << 30));
+        }
+        for (; next_spmv >= 0; --next_spmv)
+            for (int32_t b : by_level[next_spmv]) items.push_back(b | (1 << 30));
     }
     if (const char* e = getenv("ISC_LEVEL_SWEEPS")) ctx->syncfree = !(e[0] == '1');
 
@@ -300,6 +322,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->perf_cell, (size_t)std::max(npf, 1));
     ALLOC(ctx->bricks_fwd, chf.size());
     ALLOC(ctx->bricks_bwd, chb.size());
+    ALLOC(ctx->items_bwd_spmv, items.size());
     ALLOC(ctx->sweep64, (size_t)n * isc::NU);
     ALLOC(ctx->Lt, (size_t)n * 3 * isc::BS);
     ALLOC(ctx->sweep32, (size_t)n * isc::NU);
@@ -344,7 +367,8 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         hipMemsetAsync(ctx->ticket, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->flags, 0, 16 * sizeof(int32_t), ctx->stream) != hipSuccess ||
         !h2d(ctx->bricks_fwd, chf.data(), chf.size() * sizeof(int32_t)) ||
-        !h2d(ctx->bricks_bwd, chb.data(), chb.size() * sizeof(int32_t))) {
+        !h2d(ctx->bricks_bwd, chb.data(), chb.size() * sizeof(int32_t)) ||
+        !h2d(ctx->items_bwd_spmv, items.data(), items.size() * sizeof(int32_t))) {
         ctx->err = "initialising the sweep schedule failed";
         return fail(ISC_ERR_HIP);
     }
@@ -390,7 +414,7 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,     ctx->t32b,
                     ctx->small32, ctx->accJ,   ctx->qg,     ctx->qv,     ctx->rates,
                     ctx->perf_cell, ctx->well_off, ctx->bricks_fwd, ctx->bricks_bwd, ctx->sweep64,
-                    ctx->sweep32, ctx->ticket, ctx->Lt, ctx->Lt32};
+                    ctx->sweep32, ctx->ticket, ctx->Lt, ctx->Lt32, ctx->items_bwd_spmv};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (ctx->hscratch) hipHostFree(ctx->hscratch);
@@ -479,6 +503,18 @@ isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv,
     }
     ISC_HIP(isc_launch_form_ltilde(ctx, Jdec, Dinv));
     ISC_HIP(isc_launch_bilu0_apply(ctx, Jdec, Dinv, r, z));
+    return isc_check_sweeps(ctx);
+}
+
+isc_status isc_bilu0_apply_spmv(isc_ctx* ctx, const double* Jdec, const double* Dinv, const double* r, double* z,
+                                double* w) {
+    TRY(check_ctx(ctx));
+    if (!Jdec || !Dinv || !r || !z || !w || r == z || r == w || z == w) {
+        ctx->err = "isc_bilu0_apply_spmv: null or aliased arrays";
+        return ISC_ERR_ARG;
+    }
+    ISC_HIP(isc_launch_form_ltilde(ctx, Jdec, Dinv));
+    ISC_HIP(isc_launch_bilu0_apply_spmv(ctx, Jdec, Dinv, r, z, w));
     return isc_check_sweeps(ctx);
 }
 

@@ -104,6 +104,7 @@ struct isc_ctx {
     int32_t nbrick = 0;
     int32_t* bricks_fwd = nullptr;
     int32_t* bricks_bwd = nullptr;
+    int32_t* items_bwd_spmv = nullptr;   // [2 nbrick] backward bricks interleaved with SpMV bricks
     double* Lt = nullptr;        // [N][3][8][8] L D^-1 blocks of the last BILU(0) factor (z-, y-, x-)
     float* Lt32 = nullptr;       // the same for the FP32 factor of the precision form
     double* sweep64 = nullptr;   // private forward-sweep buffers, sentinel-filled between sweeps

@@ -368,6 +368,7 @@ __global__ void __launch_bounds__(256) dcgs2_update(int64_t len2, V2* Q, int64_t
 // ---------------------------------------------------------------- host side
 hipError_t isc_launch_bilu0_apply(isc_ctx*, const double*, const double*, const double*, double*);
 hipError_t isc_launch_spmv(isc_ctx*, const double*, const double*, double*);
+hipError_t isc_launch_bilu0_apply_spmv(isc_ctx*, const double*, const double*, const double*, double*, double*);
 hipError_t isc_launch_bilu0_factor(isc_ctx*, const double*, double*, int32_t*);
 
 namespace isc {
@@ -483,12 +484,9 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
         int k = m;
         for (int j = 0; j <= m; ++j) {
             const bool last = j == m;
-            if (!last) {
-                int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY);
-                isc_launch_bilu0_apply(ctx, A, Dinv, u, ctx->tvec);
-                isc_prof_end(ctx, tk);
-                tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
-                isc_launch_spmv(ctx, A, ctx->tvec, ctx->w);
+            if (!last) {   // w = A M^-1 u_j
+                const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_SPMV);
+                isc_launch_bilu0_apply_spmv(ctx, A, Dinv, u, ctx->tvec, ctx->w);
                 isc_prof_end(ctx, tk);
             }
             const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
@@ -595,7 +593,8 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
     hipLaunchKernelGGL(narrow_f32, dim3(nb), dim3(256), 0, ctx->stream, len, v, u);
     for (int j = 0; j <= m_in; ++j) {
         const bool last = j == m_in;
-        if (!last) {
+        if (!last) {   // w = A M^-1 u_j in FP32 (separate kernels: here the fused one is slower,
+                       // its SpMV bricks find little sweep latency to hide behind)
             int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY32);
             isc_launch_bilu0_apply32(ctx, A32, D32, u, ctx->t32);
             isc_prof_end(ctx, tk);

@@ -371,7 +371,7 @@ __device__ __forceinline__ void lds_row8(const double* x, double* out8) {
 template <class T, class TV>
 __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
                                           const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y,
-                                          TV* __restrict__ z, int32_t* err) {
+                                          TV* __restrict__ z, int32_t* err, BrickLds& L) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
     const int r = bc.r;
     const bool act = bc.i >= 0;
@@ -406,7 +406,6 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     double xg[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(y + (size_t)lower[q] * NU + r, first[q], err) : 0.0;
-    __shared__ BrickLds L;
     const int me = bc.g * 8 + r;
 #pragma unroll
     for (int q = 0; q < 3; ++q) L.ext[q][me] = xg[q];
@@ -434,7 +433,8 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
 template <class T, class TV>
 __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
                                           const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-                                          const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, int32_t* err) {
+                                          const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, int32_t* err,
+                                          BrickLds& L) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
     const int r = bc.r;
     const bool act = bc.i >= 0;
@@ -472,7 +472,6 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     double xg[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) xg[q] = ext[q] ? (double)await_value(z + (size_t)upper[q] * NU + r, first[q], err) : 0.0;
-    __shared__ BrickLds L;
     const int me = bc.g * 8 + r;
 #pragma unroll
     for (int q = 0; q < 3; ++q) L.ext[q][me] = xg[q];
@@ -504,15 +503,78 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     if (act) publish(z + (size_t)ii * NU + r, (TV)zout);
 }
 
+// w_i = z_i + sum_{j != i} A_ij z_j for the cells of one brick, with z read
+// as it is published by the backward sweep of the same launch (the work list
+// puts the brick after the backward bricks of all its neighbours).  Same
+// arithmetic order as spmv_unitdiag: z_i, then the blocks in ascending column
+// order.  The three lower and then the three upper neighbours' rows go
+// through LDS, eight lanes per cell.
+template <class T, class TV>
+__device__ __forceinline__ void spmv_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+                                           const int32_t* __restrict__ row_ptr, const T* __restrict__ A,
+                                           const TV* z, TV* __restrict__ w, int32_t* err, BrickLds& L) {
+    const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
+    const int r = bc.r;
+    const bool act = bc.i >= 0;
+    const int32_t ii = bc.ii;
+    const int32_t nxy = nx * ny;
+    const int32_t ix = ii % nx, iy = (ii / nx) % ny, iz = ii / nxy;
+    const int32_t nb[6] = {iz > 0 ? ii - nxy : -1, iy > 0 ? ii - nx : -1, ix > 0 ? ii - 1 : -1,
+                           ix + 1 < nx ? ii + 1 : -1, iy + 1 < ny ? ii + nx : -1, iz + 1 < nz ? ii + nxy : -1};
+    const int32_t b0 = row_ptr[ii];
+    const int me = bc.g * 8 + r;
+    const typename Bits<TV>::U own0 = act ? peek(z + (size_t)ii * NU + r) : 0;
+    double acc = act ? (double)await_value(z + (size_t)ii * NU + r, own0, err) : 0.0;
+    int32_t blk = b0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (h == 1) ++blk;   // the diagonal block (identity, not read)
+        double arow[3][8];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int32_t j = nb[3 * h + k];
+            const T* a = A + (size_t)(j >= 0 ? blk : b0) * BS + r * 8;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const double x = (double)a[c];
+                arow[k][c] = j >= 0 ? x : 0.0;
+            }
+            blk += j >= 0;
+        }
+        typename Bits<TV>::U first[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int32_t j = nb[3 * h + k];
+            first[k] = (act && j >= 0) ? peek(z + (size_t)j * NU + r) : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int32_t j = nb[3 * h + k];
+            L.ext[k][me] = (act && j >= 0) ? (double)await_value(z + (size_t)j * NU + r, first[k], err) : 0.0;
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double x[8];
+            lds_row8(&L.ext[k][bc.g * 8], x);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc += arow[k][c] * x[c];
+        }
+        wave_lds_sync();
+    }
+    if (act) w[(size_t)ii * NU + r] = (TV)acc;
+}
+
 // One workgroup per brick; workgroups take tickets in brick-list order.
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y, TV* __restrict__ z, unsigned long long* ticket,
     unsigned long long base, int32_t* err) {
+    __shared__ BrickLds L;
     const int32_t k = take_ticket(ticket, base);
     if (k >= nbrick) return;
-    fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, Lt, rin, y, z, err);
+    fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, Lt, rin, y, z, err, L);
 }
 
 template <class T, class TV>
@@ -520,9 +582,31 @@ __global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ y,
     TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
+    __shared__ BrickLds L;
     const int32_t k = take_ticket(ticket, base);
     if (k >= nbrick) return;
-    bwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, err);
+    bwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, err, L);
+}
+
+// Backward sweep and w = A z in one launch: the work list interleaves the
+// backward bricks (level by level, descending) with SpMV bricks (flag
+// SPMV_ITEM), each SpMV brick after the backward bricks of all its
+// neighbours, so the SpMV work fills the gaps of the wait chain.
+constexpr int32_t SPMV_ITEM = 1 << 30;
+template <class T, class TV>
+__global__ void __launch_bounds__(256) bilu0_bwd_spmv_syncfree(
+    const int32_t* __restrict__ items, int32_t nitem, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
+    const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, TV* __restrict__ w, unsigned long long* ticket,
+    unsigned long long base, int32_t* err) {
+    __shared__ BrickLds L;
+    const int32_t k = take_ticket(ticket, base);
+    if (k >= nitem) return;
+    const int32_t it = items[k];
+    if (it & SPMV_ITEM)
+        spmv_brick<T, TV>(it & (SPMV_ITEM - 1), nbx, nby, nx, ny, nz, row_ptr, A, z, w, err, L);
+    else
+        bwd_brick<T, TV>(it, nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, err, L);
 }
 
 template <class U>
@@ -599,6 +683,33 @@ hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, con
     return hipGetLastError();
 }
 
+// z = M^-1 r and w = A z; forward sweep, then the fused backward sweep + SpMV
+// (level launches followed by the SpMV when the sync-free sweeps are off).
+template <class T, class TV>
+hipError_t isc_launch_spmv_t(isc_ctx* ctx, const T* A, const TV* x, TV* y);
+template <class T, class TV>
+hipError_t isc_launch_bilu0_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Dinv, const TV* r, TV* z, TV* w) {
+    if (!ctx->syncfree) {
+        const hipError_t e = isc_launch_bilu0_apply_t<T, TV>(ctx, A, Dinv, r, z);
+        if (e != hipSuccess) return e;
+        return isc_launch_spmv_t<T, TV>(ctx, A, z, w);
+    }
+    TV* v = isc::sweep_buffer<TV>(ctx);
+    const int32_t nbx = (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X;
+    const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
+    hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(ctx->nbrick), dim3(256), ISC_SWEEP_LDS, ctx->stream,
+                       ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
+                       (const T*)isc::lt_buffer<T>(ctx), r, v, z, ctx->ticket, ctx->ticket_base,
+                       ctx->flags + ISC_FLAG_SWEEP);
+    ctx->ticket_base += (unsigned long long)ctx->nbrick;
+    const int32_t nitem = 2 * ctx->nbrick;
+    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<T, TV>), dim3(nitem), dim3(256), ISC_SWEEP_LDS, ctx->stream,
+                       ctx->items_bwd_spmv, nitem, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
+                       ctx->diag_pos, A, Dinv, v, z, w, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+    ctx->ticket_base += (unsigned long long)nitem;
+    return hipGetLastError();
+}
+
 template <class T, class TV>
 hipError_t isc_launch_spmv_t(isc_ctx* ctx, const T* A, const TV* x, TV* y) {
     const int blocks = (int)(((int64_t)ctx->n * 8 + 255) / 256);
@@ -624,6 +735,10 @@ hipError_t isc_launch_bilu0_apply(isc_ctx* ctx, const double* A, const double* D
 }
 hipError_t isc_launch_bilu0_apply32(isc_ctx* ctx, const float* A, const float* Dinv, const float* r, float* z) {
     return isc_launch_bilu0_apply_t<float, float>(ctx, A, Dinv, r, z);
+}
+hipError_t isc_launch_bilu0_apply_spmv(isc_ctx* ctx, const double* A, const double* Dinv, const double* r,
+                                       double* z, double* w) {
+    return isc_launch_bilu0_apply_spmv_t<double, double>(ctx, A, Dinv, r, z, w);
 }
 hipError_t isc_launch_spmv(isc_ctx* ctx, const double* A, const double* x, double* y) {
     return isc_launch_spmv_t<double, double>(ctx, A, x, y);

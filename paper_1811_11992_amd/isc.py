@@ -70,6 +70,7 @@ def lib():
         L.isc_spmv.argtypes = [_vp, _vp, _vp, _vp]
         L.isc_bilu0.argtypes = [_vp, _vp, _vp]
         L.isc_bilu0_apply.argtypes = [_vp, _vp, _vp, _vp, _vp]
+        L.isc_bilu0_apply_spmv.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.isc_update.argtypes = [_vp, _vp, _vp]
         L.isc_scaled_norm.argtypes = [_vp, _vp, _f64, ctypes.POINTER(_f64)]
         L.isc_adjoint.argtypes = [_vp, _vp, _vp, _f64, _vp, _f64, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
@@ -80,8 +81,8 @@ def lib():
         L.isc_last_error.restype = ctypes.c_char_p
         for name in ("isc_create", "isc_destroy", "isc_set_params", "isc_bcsr_pattern", "isc_assemble",
                      "isc_decouple", "isc_solve", "isc_newton_step", "isc_spmv", "isc_bilu0",
-                     "isc_bilu0_apply", "isc_update", "isc_scaled_norm", "isc_adjoint", "isc_profile",
-                     "isc_oil_rate"):
+                     "isc_bilu0_apply", "isc_bilu0_apply_spmv", "isc_update", "isc_scaled_norm", "isc_adjoint",
+                     "isc_profile", "isc_oil_rate"):
             getattr(L, name).restype = _i32
         _LIB = L
     return _LIB
@@ -192,6 +193,12 @@ class Context:
         self._check(lib().isc_bilu0_apply(self.h, _ptr(Jdec), _ptr(Dinv), _ptr(r), _ptr(z)))
         return z
 
+    def isc_bilu0_apply_spmv(self, Jdec, Dinv, r, z=None, w=None):
+        z = torch.empty_like(r) if z is None else z
+        w = torch.empty_like(r) if w is None else w
+        self._check(lib().isc_bilu0_apply_spmv(self.h, _ptr(Jdec), _ptr(Dinv), _ptr(r), _ptr(z), _ptr(w)))
+        return z, w
+
     def isc_update(self, u, du):
         return lib().isc_update(self.h, _ptr(u), _ptr(du))
 
@@ -216,12 +223,13 @@ class Context:
         return q.value
 
 
-PROF_CLASSES = ("spmv", "ilu_apply", "assemble", "decouple", "ilu_factor", "krylov", "ilu_apply32", "spmv32")
+PROF_CLASSES = ("spmv", "ilu_apply", "assemble", "decouple", "ilu_factor", "krylov", "ilu_apply32", "spmv32",
+                "ilu_spmv", "ilu_spmv32")
 
 
 def _profile_call(ctx, enable):
-    ms = (ctypes.c_double * 8)()
-    cnt = (ctypes.c_int32 * 8)()
+    ms = (ctypes.c_double * len(PROF_CLASSES))()      # ISC_PROF_NCLASS entries
+    cnt = (ctypes.c_int32 * len(PROF_CLASSES))()
     ctx._check(lib().isc_profile(ctx.h, enable, ms, cnt))
     return {name: (ms[k], cnt[k]) for k, name in enumerate(PROF_CLASSES)}
 

@@ -164,7 +164,8 @@ def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, monkeypatch):
     published values) and the one-launch-per-level sweeps do the same
     arithmetic in the same order, so their results agree bit for bit; several
     applications in a row check that each sweep leaves its private buffer
-    ready for the next."""
+    ready for the next.  The backward sweep fused with the SpMV gives the same
+    z and the same w = A z as the separate kernels."""
     wl, m, u, F, J = _decoupled_case(name, seed)
     st, Jd, Fd, _ = m.decouple(J, F)
     c_sf = ctx_for(wl)
@@ -179,6 +180,12 @@ def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, monkeypatch):
         z_lv = c_lv.isc_bilu0_apply(Jdg, D, x)
         torch.cuda.synchronize()
         assert torch.equal(z_sf, z_lv), rep
+        # backward sweep fused with the SpMV: the same z, and w equal to the separate SpMV
+        w_ref = c_sf.isc_spmv(Jdg, z_sf)
+        for c in (c_sf, c_lv):
+            z_f, w_f = c.isc_bilu0_apply_spmv(Jdg, D, x)
+            torch.cuda.synchronize()
+            assert torch.equal(z_f, z_sf) and torch.equal(w_f, w_ref), rep
 
 
 @pytest.mark.parametrize("name,seed", [("tiny:13x7x5", 21), ("C1", 22)])
