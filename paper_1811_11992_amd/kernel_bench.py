@@ -3,11 +3,13 @@
     python -m paper_1811_11992_amd.kernel_bench [--workload C3] [--reps 20]
 
 Builds the decoupled Jacobian at the workload's initial state (assemble,
-decouple, BILU(0) factor through the C-ABI), then times ``isc_bilu0_apply``
-and ``isc_spmv`` on a random right-hand side, and runs a plain 128 MB-class
-device copy of one vector as the reference kernel for hardware counters (a
-copy moves a known number of bytes).  Prints one JSON line.  Used to take
-per-kernel traffic counters without the rest of the solver in the trace.
+decouple, BILU(0) factor through the C-ABI), then times ``isc_bilu0_apply``,
+``isc_spmv`` and the fused ``isc_bilu0_apply_spmv`` on a random right-hand
+side (the public applies first form the L D^-1 blocks from their arguments),
+and a plain device copy of one vector as the reference kernel for hardware
+counters (a copy moves a known number of bytes).  Prints one JSON line.  Used
+to take per-kernel traffic counters without the rest of the solver in the
+trace.
 """
 from __future__ import annotations
 
@@ -49,11 +51,13 @@ def main(argv=None):
 
     t_apply = timed(lambda: c.isc_bilu0_apply(J, D, r, z))
     t_spmv = timed(lambda: c.isc_spmv(J, r, y))
+    w = torch.empty_like(r)
+    t_fused = timed(lambda: c.isc_bilu0_apply_spmv(J, D, r, z, w))
     t_copy = timed(lambda: y.copy_(r))
     vec_bytes = r.numel() * r.element_size()
     print(json.dumps({"workload": wl.name, "cells": c.n, "reps": a.reps, "bilu0_apply_ms": round(t_apply, 4),
-                      "spmv_ms": round(t_spmv, 4), "copy_ms": round(t_copy, 4), "copy_bytes_each_way": vec_bytes,
-                      "apply_finite": bool(torch.isfinite(z).all())}), flush=True)
+                      "spmv_ms": round(t_spmv, 4), "apply_spmv_ms": round(t_fused, 4), "copy_ms": round(t_copy, 4),
+                      "copy_bytes_each_way": vec_bytes, "apply_finite": bool(torch.isfinite(z).all())}), flush=True)
 
 
 if __name__ == "__main__":
