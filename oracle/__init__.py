@@ -125,8 +125,9 @@ class Model:
         L.orc_pattern(self.h, _ip_(self.row_ptr), _ip_(self.col_idx))
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_destroy(self.h)
+        # at interpreter shutdown the module globals may already be gone
+        if getattr(self, "h", None) and _LIB is not None and callable(lib):
+            _LIB.orc_destroy(self.h)
             self.h = None
 
     # ---- setup

@@ -363,9 +363,13 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         ctx->err = "cannot read logk/poro (device pointers expected)";
         return fail(ISC_ERR_ARG);
     }
+    // wait limit of the sweeps (ISC_SWEEP_WAIT_TICKS overrides it, e.g. to test the timeout path)
+    uint64_t wait_ticks = ISC_SWEEP_WAIT_DEFAULT;
+    if (const char* e = getenv("ISC_SWEEP_WAIT_TICKS")) wait_ticks = strtoull(e, nullptr, 10);
     if (isc_reset_sweep_buffers(ctx) != hipSuccess ||
         hipMemsetAsync(ctx->ticket, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess ||
         hipMemsetAsync(ctx->flags, 0, 16 * sizeof(int32_t), ctx->stream) != hipSuccess ||
+        !h2d(ctx->flags + ISC_FLAG_WAIT, &wait_ticks, sizeof(uint64_t)) ||
         !h2d(ctx->bricks_fwd, chf.data(), chf.size() * sizeof(int32_t)) ||
         !h2d(ctx->bricks_bwd, chb.data(), chb.size() * sizeof(int32_t)) ||
         !h2d(ctx->items_bwd_spmv, items.data(), items.size() * sizeof(int32_t))) {

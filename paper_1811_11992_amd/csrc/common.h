@@ -200,8 +200,11 @@ inline void isc_prof_drain(isc_ctx* ctx) {
 
 hipError_t isc_reset_sweep_buffers(isc_ctx* ctx);
 
-// Slot of ctx->flags raised when a sync-free triangular sweep gave up waiting.
+// Slot of ctx->flags raised when a sync-free triangular sweep gave up waiting;
+// the two slots after it hold the wait limit (uint64, wall-clock ticks).
 constexpr int ISC_FLAG_SWEEP = 3;
+constexpr int ISC_FLAG_WAIT = 4;
+constexpr uint64_t ISC_SWEEP_WAIT_DEFAULT = 1ull << 24;   // ~0.17 s of the 100 MHz wall clock
 
 // Reads (and clears) the sweep error flag; waits for the stream.
 inline isc_status isc_check_sweeps(isc_ctx* ctx) {

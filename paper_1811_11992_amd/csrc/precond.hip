@@ -251,7 +251,6 @@ __global__ void __launch_bounds__(256) spmv_unitdiag(int32_t n, const int32_t* _
 // timed out (error flag), so a sweep always terminates.
 constexpr uint64_t SENTINEL64 = 0x7FF4DEC0DE5EED01ull;   // NaN payload no arithmetic produces
 constexpr uint32_t SENTINEL32 = 0x7FA5EED1u;
-constexpr uint64_t WAIT_TICKS = 1ull << 24;               // ~0.17 s of the 100 MHz wall clock
 #ifndef ISC_SWEEP_SLEEP
 #define ISC_SWEEP_SLEEP 1      // s_sleep argument between polls (units of 64 clocks)
 #endif
@@ -281,7 +280,8 @@ template <class TV> __device__ __forceinline__ typename Bits<TV>::U peek(const T
                              __HIP_MEMORY_SCOPE_AGENT);
 }
 // Given a first read u of *p, polls *p until it no longer holds the sentinel
-// (bounded in time); returns the value, or 0 after a timeout.
+// (bounded in time: the limit in wall-clock ticks is the uint64 stored right
+// after the error flag); returns the value, or 0 after a timeout.
 template <class TV> __device__ __forceinline__ TV await_value(const TV* p, typename Bits<TV>::U u, int32_t* err) {
     if (u != Bits<TV>::sentinel) return from_bits<TV>(u);
     const uint64_t t0 = wall_clock64();
@@ -290,7 +290,7 @@ template <class TV> __device__ __forceinline__ TV await_value(const TV* p, typen
         u = peek(p);
         if (u != Bits<TV>::sentinel) return from_bits<TV>(u);
         if ((k & 63) == 0) {
-            if (wall_clock64() - t0 > WAIT_TICKS) {
+            if (wall_clock64() - t0 > *reinterpret_cast<const uint64_t*>(err + 1)) {
                 atomicOr(err, 1);
                 return TV(0);
             }

@@ -188,6 +188,30 @@ def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, monkeypatch):
             assert torch.equal(z_f, z_sf) and torch.equal(w_f, w_ref), rep
 
 
+def test_sweep_wait_limit_ends_in_an_error_not_a_hang(monkeypatch):
+    """The sync-free sweeps bound every wait in wall-clock time.  With the
+    limit forced down from the host to one tick, rows that have to wait for
+    their predecessors give up, every wavefront still exits, and the apply
+    reports the timeout as an error; a context with the normal limit applies
+    the same factor without error."""
+    from paper_1811_11992_amd import isc
+    wl = I.make_workload("tiny:60x60x20")
+    monkeypatch.setenv("ISC_SWEEP_WAIT_TICKS", "1")
+    c_tiny = ctx_for(wl)
+    monkeypatch.delenv("ISC_SWEEP_WAIT_TICKS")
+    c_ok = ctx_for(wl)
+    u0 = dev(wl.u0)
+    F, J = c_ok.isc_assemble(u0, u0, wl.dt)
+    c_ok.isc_decouple(J, F)
+    D = c_ok.isc_bilu0(J)
+    r = torch.randn((wl.ncell, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(isc.IscError, match="waited too long"):
+        c_tiny.isc_bilu0_apply(J, D, r)
+    z = c_ok.isc_bilu0_apply(J, D, r)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(z).all())
+
+
 @pytest.mark.parametrize("name,seed", [("tiny:13x7x5", 21), ("C1", 22)])
 def test_solve_reaches_tolerance_and_matches_tight_oracle_solution(name, seed):
     from paper_1811_11992_amd import isc
