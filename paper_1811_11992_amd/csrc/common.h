@@ -14,6 +14,23 @@ constexpr int NU = 8;        // unknowns per cell
 constexpr int BS = 64;       // 8x8 block
 // cells of one brick of the sync-free triangular sweeps (one 256-thread workgroup)
 constexpr int BRICK_X = 4, BRICK_Y = 4, BRICK_Z = 2;
+
+// The delayed Gram-Schmidt update of the previous GMRES iteration, done by
+// the forward sweep for its own rows before sweeping (FP64 solver):
+//   q_{j-1} = (u - sum_{k<j-1} s_k Q_k) / omega,
+//   u      <- (w - sum_{k<j-1} z_k Q_k - zeta q_{j-1}) / omega,
+// the new u being the sweep's right-hand side.  jq = j - 1 is the index of
+// the basis vector written; s, z: coefficients; omz = (omega, zeta).
+struct LagUpdate {
+    double* Q;
+    int64_t ldv;
+    int jq;
+    const double* s;
+    const double* z;
+    const double* omz;
+    double* u;
+    const double* w;
+};
 // Per-cell property payload written by the property pass and read by the
 // face-flux assembly (doubles, value followed by the 8 partial derivatives):
 //   [0, 72)     local residual terms of the 8 rows (accumulation change,

@@ -369,6 +369,8 @@ __global__ void __launch_bounds__(256) dcgs2_update(int64_t len2, V2* Q, int64_t
 hipError_t isc_launch_bilu0_apply(isc_ctx*, const double*, const double*, const double*, double*);
 hipError_t isc_launch_spmv(isc_ctx*, const double*, const double*, double*);
 hipError_t isc_launch_bilu0_apply_spmv(isc_ctx*, const double*, const double*, const double*, double*, double*);
+hipError_t isc_launch_update_apply_spmv(isc_ctx*, const double*, const double*, const isc::LagUpdate&, double*,
+                                        double*);
 hipError_t isc_launch_bilu0_factor(isc_ctx*, const double*, double*, int32_t*);
 
 namespace isc {
@@ -484,9 +486,24 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
         int k = m;
         for (int j = 0; j <= m; ++j) {
             const bool last = j == m;
+            // The Gram-Schmidt update left over from iteration j-1 (q_{j-1}
+            // and u_j) runs inside this iteration's forward sweep, where the
+            // sync-free sweep allows it; otherwise as a pass of its own.
+            const bool fold = j > 0 && !last && ctx->syncfree;
+            if (j > 0 && !fold) {
+                const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
+                hipLaunchKernelGGL(dcgs2_update<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j - 1,
+                                   red, dc.omz, u2, w2, (double*)nullptr);
+                isc_prof_end(ctx, tk);
+            }
             if (!last) {   // w = A M^-1 u_j
                 const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_SPMV);
-                isc_launch_bilu0_apply_spmv(ctx, A, Dinv, u, ctx->tvec, ctx->w);
+                if (fold) {
+                    const LagUpdate lu{ctx->V, ldv, j - 1, red, red + MAXV, dc.omz, u, ctx->w};
+                    isc_launch_update_apply_spmv(ctx, A, Dinv, lu, ctx->tvec, ctx->w);
+                } else {
+                    isc_launch_bilu0_apply_spmv(ctx, A, Dinv, u, ctx->tvec, ctx->w);
+                }
                 isc_prof_end(ctx, tk);
             }
             const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
@@ -497,9 +514,6 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
             hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hs, dc, j, last ? 1 : 0, red);
             ISC_HIP(hipMemcpyAsync(ctx->hscratch, hs.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
             ISC_HIP(hipEventRecord(ev, ctx->stream));
-            if (!last)   // speculative: unused if the estimate below ends the cycle
-                hipLaunchKernelGGL(dcgs2_update<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, red,
-                                   dc.omz, u2, w2, (double*)nullptr);
             isc_prof_end(ctx, tk);
             ISC_HIP(hipEventSynchronize(ev));
             const double est = ctx->hscratch[2];

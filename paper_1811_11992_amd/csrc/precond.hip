@@ -368,10 +368,11 @@ __device__ __forceinline__ void lds_row8(const double* x, double* out8) {
 
 // forward: y_i = r_i - sum_{k lower} Lt_ik y_k; y is the private buffer
 // (sentinel on entry), z_i is reset to the sentinel for the backward sweep
-template <class T, class TV>
+template <class T, class TV, bool UPDATE = false>
 __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
                                           const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y,
-                                          TV* __restrict__ z, int32_t* err, BrickLds& L) {
+                                          TV* __restrict__ z, int32_t* err, BrickLds& L,
+                                          const LagUpdate& lu = LagUpdate{}) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
     const int r = bc.r;
     const bool act = bc.i >= 0;
@@ -394,7 +395,36 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
             arow[q][c] = lower[q] >= 0 ? x : 0.0;
         }
     }
-    const double rv = act ? (double)rin[(size_t)ii * NU + r] : 0.0;
+    double rv;
+    if constexpr (UPDATE) {
+        const size_t e = (size_t)ii * NU + r;
+        const double uo = lu.u[e], wo = lu.w[e];
+        double sx = 0.0, zx = 0.0;
+        // eight basis rows in flight at a time (the index is clamped so the
+        // loads need no branch); summed in the order k = 0, 1, ...
+        for (int k0 = 0; k0 < lu.jq; k0 += 8) {
+            double q[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) q[t] = lu.Q[(size_t)min(k0 + t, lu.jq - 1) * lu.ldv + e];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                if (k0 + t < lu.jq) {
+                    sx += lu.s[k0 + t] * q[t];
+                    zx += lu.z[k0 + t] * q[t];
+                }
+            }
+        }
+        const double rom = lu.omz[0] > 0.0 ? 1.0 / lu.omz[0] : 0.0, zeta = lu.omz[1];
+        const double qj = (uo - sx) * rom;
+        const double un = (wo - zx - zeta * qj) * rom;
+        if (act) {
+            lu.Q[(size_t)lu.jq * lu.ldv + e] = qj;
+            lu.u[e] = un;
+        }
+        rv = act ? un : 0.0;
+    } else {
+        rv = act ? (double)rin[(size_t)ii * NU + r] : 0.0;
+    }
     if (act) z[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
     // predecessors in other bricks: first reads go out together, then wait
     bool ext[3];
@@ -577,6 +607,18 @@ __global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
     fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, Lt, rin, y, z, err, L);
 }
 
+// forward sweep preceded, row by row, by the lagged Gram-Schmidt update (FP64)
+template <class T>
+__global__ void __launch_bounds__(256) bilu0_fwd_update_syncfree(
+    const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+    const T* __restrict__ Lt, LagUpdate lu, double* y, double* __restrict__ z, unsigned long long* ticket,
+    unsigned long long base, int32_t* err) {
+    __shared__ BrickLds L;
+    const int32_t k = take_ticket(ticket, base);
+    if (k >= nbrick) return;
+    fwd_brick<T, double, true>(bricks[k], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, err, L, lu);
+}
+
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
@@ -706,6 +748,27 @@ hipError_t isc_launch_bilu0_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Dinv
     hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<T, TV>), dim3(nitem), dim3(256), ISC_SWEEP_LDS, ctx->stream,
                        ctx->items_bwd_spmv, nitem, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
                        ctx->diag_pos, A, Dinv, v, z, w, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+    ctx->ticket_base += (unsigned long long)nitem;
+    return hipGetLastError();
+}
+
+// The GMRES iteration of the FP64 solver with the previous iteration's
+// delayed Gram-Schmidt update folded into the forward sweep: writes Q_jq and
+// the new u, then z = M^-1 u and w = A z.  Sync-free sweeps only.
+hipError_t isc_launch_update_apply_spmv(isc_ctx* ctx, const double* A, const double* Dinv, const isc::LagUpdate& lu,
+                                        double* z, double* w) {
+    double* v = ctx->sweep64;
+    const int32_t nbx = (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X;
+    const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
+    hipLaunchKernelGGL((isc::bilu0_fwd_update_syncfree<double>), dim3(ctx->nbrick), dim3(256), ISC_SWEEP_LDS,
+                       ctx->stream, ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
+                       (const double*)ctx->Lt, lu, v, z, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+    ctx->ticket_base += (unsigned long long)ctx->nbrick;
+    const int32_t nitem = 2 * ctx->nbrick;
+    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<double, double>), dim3(nitem), dim3(256), ISC_SWEEP_LDS,
+                       ctx->stream, ctx->items_bwd_spmv, nitem, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
+                       ctx->row_ptr, ctx->diag_pos, A, Dinv, v, z, w, ctx->ticket, ctx->ticket_base,
+                       ctx->flags + ISC_FLAG_SWEEP);
     ctx->ticket_base += (unsigned long long)nitem;
     return hipGetLastError();
 }

@@ -231,6 +231,34 @@ def test_solve_reaches_tolerance_and_matches_tight_oracle_solution(name, seed):
     assert np.all(err <= 1e-5 * ref.max()), err / ref.max()
 
 
+@pytest.mark.parametrize("name,seed,restart", [("tiny:13x7x5", 23, 30), ("C1", 24, 30), ("C1", 25, 10)])
+def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, restart, monkeypatch):
+    """With sync-free sweeps the FP64 GMRES does each iteration's delayed
+    Gram-Schmidt update inside the next iteration's forward sweep; with level
+    sweeps it runs as a pass of its own.  The per-element arithmetic is the
+    same, so both reach the tolerance after the same number of iterations and
+    give the same solution to rounding, also across many restarts (GMRES(10)
+    needs about 25 cycles on the C1 case, as does the oracle's GMRES)."""
+    from paper_1811_11992_amd import isc
+    wl, m, u, F, J = _decoupled_case(name, seed)
+    st, Jd, Fd, _ = m.decouple(J, F)
+    b = dev(-Fd)
+    c_sf = ctx_for(wl)
+    monkeypatch.setenv("ISC_LEVEL_SWEEPS", "1")
+    c_lv = ctx_for(wl)
+    o = isc.solve_opts(rtol=1e-9, restart=restart, max_restarts=200)
+    x_sf, inf_sf, st_sf = c_sf.isc_solve(dev(Jd), b, o)
+    x_lv, inf_lv, st_lv = c_lv.isc_solve(dev(Jd), b, o)
+    assert st_sf == 0 and st_lv == 0
+    assert inf_sf.relres_true <= 1e-9 and inf_lv.relres_true <= 1e-9
+    # rounding differences may move the stopping iteration of a long run a little
+    assert abs(inf_sf.iters - inf_lv.iters) <= max(1, inf_lv.iters // 50), (inf_sf.iters, inf_lv.iters)
+    xs, xl = host(x_sf), host(x_lv)
+    err = np.abs((xs - xl) / COL).max(axis=0)
+    ref = np.abs(xl / COL).max(axis=0).max() + 1e-300
+    assert np.all(err <= 1e-6 * ref), err / ref
+
+
 def test_newton_root_matches_oracle_on_c1_first_step():
     wl = I.make_workload("C1")
     m = O.Model(wl)
