@@ -232,6 +232,15 @@ enum { ISC_PROF_SPMV = 0, ISC_PROF_ILU_APPLY, ISC_PROF_ASSEMBLE, ISC_PROF_DECOUP
        ISC_PROF_NCLASS = 10 };
 isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* count_h);
 
+/* Per class, the number of full-length vectors (n x 8 values in the class's
+ * precision) that the profiled launches streamed on top of the class's fixed
+ * access pattern, accumulated over the same window as isc_profile.  Nonzero
+ * only for class 8: the FP64 GMRES folds the previous iteration's delayed
+ * Gram-Schmidt update into the forward sweep, which then reads j - 1 basis
+ * vectors and w and writes q_{j-1} and u (j + 2 vectors at iteration j).
+ * vec_h: host array of ISC_PROF_NCLASS.  ISC_ERR_ARG if it is NULL. */
+isc_status isc_profile_vectors(isc_ctx* ctx, double* vec_h);
+
 const char* isc_last_error(const isc_ctx* ctx);
 
 #ifdef __cplusplus

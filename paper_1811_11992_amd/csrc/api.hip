@@ -695,7 +695,11 @@ isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* coun
     ISC_HIP(hipStreamSynchronize(ctx->stream));
     isc_prof_drain(ctx);
     if (enable == 1) {
-        for (int c = 0; c < ISC_PROF_NCLASS; ++c) { ctx->prof_ms[c] = 0.0; ctx->prof_cnt[c] = 0; }
+        for (int c = 0; c < ISC_PROF_NCLASS; ++c) {
+            ctx->prof_ms[c] = 0.0;
+            ctx->prof_cnt[c] = 0;
+            ctx->prof_vec[c] = 0.0;
+        }
         ctx->prof = true;
     } else if (enable == 0) {
         ctx->prof = false;
@@ -704,6 +708,16 @@ isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* coun
         if (ms_h) ms_h[c] = ctx->prof_ms[c];
         if (count_h) count_h[c] = ctx->prof_cnt[c];
     }
+    return ISC_OK;
+}
+
+isc_status isc_profile_vectors(isc_ctx* ctx, double* vec_h) {
+    TRY(check_ctx(ctx));
+    if (!vec_h) {
+        ctx->err = "isc_profile_vectors: null output";
+        return ISC_ERR_ARG;
+    }
+    for (int c = 0; c < ISC_PROF_NCLASS; ++c) vec_h[c] = ctx->prof_vec[c];
     return ISC_OK;
 }
 

@@ -169,6 +169,7 @@ struct isc_ctx {
     bool prof = false;
     double prof_ms[ISC_PROF_NCLASS] = {};
     int32_t prof_cnt[ISC_PROF_NCLASS] = {};
+    double prof_vec[ISC_PROF_NCLASS] = {};   // isc_profile_vectors
     struct Pending { int cls; hipEvent_t a, b; };
     std::vector<Pending> prof_pending;
     std::vector<hipEvent_t> prof_pool;
@@ -198,6 +199,11 @@ inline int isc_prof_begin(isc_ctx* ctx, int cls) {
     (void)hipEventRecord(p.a, ctx->stream);
     ctx->prof_pending.push_back(p);
     return (int)ctx->prof_pending.size() - 1;
+}
+// full-length vectors a profiled launch of class cls streams beyond the
+// class's fixed access pattern (isc_profile_vectors)
+inline void isc_prof_vectors(isc_ctx* ctx, int cls, double nvec) {
+    if (ctx->prof) ctx->prof_vec[cls] += nvec;
 }
 inline void isc_prof_end(isc_ctx* ctx, int tok) {
     if (tok >= 0) (void)hipEventRecord(ctx->prof_pending[tok].b, ctx->stream);

@@ -501,6 +501,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
                 if (fold) {
                     const LagUpdate lu{ctx->V, ldv, j - 1, red, red + MAXV, dc.omz, u, ctx->w};
                     isc_launch_update_apply_spmv(ctx, A, Dinv, lu, ctx->tvec, ctx->w);
+                    isc_prof_vectors(ctx, ISC_PROF_ILU_SPMV, (double)(j + 2));
                 } else {
                     isc_launch_bilu0_apply_spmv(ctx, A, Dinv, u, ctx->tvec, ctx->w);
                 }

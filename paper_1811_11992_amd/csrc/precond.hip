@@ -367,11 +367,13 @@ __device__ __forceinline__ void lds_row8(const double* x, double* out8) {
 }
 
 // forward: y_i = r_i - sum_{k lower} Lt_ik y_k; y is the private buffer
-// (sentinel on entry), z_i is reset to the sentinel for the backward sweep
+// (sentinel on entry), z_i is reset to the sentinel for the backward sweep,
+// and so is w_i when w is given (the fused SpMV's partial sums are
+// published there)
 template <class T, class TV, bool UPDATE = false>
 __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
                                           const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y,
-                                          TV* __restrict__ z, int32_t* err, BrickLds& L,
+                                          TV* __restrict__ z, TV* w, int32_t* err, BrickLds& L,
                                           const LagUpdate& lu = LagUpdate{}) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
     const int r = bc.r;
@@ -426,6 +428,7 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
         rv = act ? (double)rin[(size_t)ii * NU + r] : 0.0;
     }
     if (act) z[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
+    if (act && w) w[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
     // predecessors in other bricks: first reads go out together, then wait
     bool ext[3];
 #pragma unroll
@@ -459,12 +462,15 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
 }
 
 // backward: z_i = D_i^-1 (y_i - sum_{j upper} A_ij z_j); z holds the sentinel on
-// entry, y_i is reset to the sentinel for the next forward sweep
+// entry, y_i is reset to the sentinel for the next forward sweep.  With w
+// given (sentinel on entry), also publishes w_i = z_i + sum_{j upper} A_ij z_j,
+// the part of (A z)_i that the sweep has in hand (the diagonal block of the
+// decoupled matrix is the identity); the SpMV bricks add the lower part.
 template <class T, class TV>
 __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
                                           const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-                                          const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, int32_t* err,
-                                          BrickLds& L) {
+                                          const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, TV* w,
+                                          int32_t* err, BrickLds& L) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
     const int r = bc.r;
     const bool act = bc.i >= 0;
@@ -506,7 +512,7 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
 #pragma unroll
     for (int q = 0; q < 3; ++q) L.ext[q][me] = xg[q];
     const int mystep = BRICK_STEPS - 1 - bc.step;
-    double zout = 0.0;
+    double zout = 0.0, uz = 0.0;
     for (int s = 0; s < BRICK_STEPS; ++s) {
         const int buf = s & 1;
         L.v[buf][me] = zout;
@@ -527,70 +533,64 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
         double t = 0.0;
 #pragma unroll
         for (int c = 0; c < 8; ++c) t += drow[c] * a8[c];
-        if (mystep == s) zout = t;
+        if (mystep == s) {
+            zout = t;
+            uz = yi - acc;
+        }
         wave_lds_sync();
     }
     if (act) publish(z + (size_t)ii * NU + r, (TV)zout);
+    if (act && w) publish(w + (size_t)ii * NU + r, (TV)(zout + uz));
 }
 
-// w_i = z_i + sum_{j != i} A_ij z_j for the cells of one brick, with z read
-// as it is published by the backward sweep of the same launch (the work list
-// puts the brick after the backward bricks of all its neighbours).  Same
-// arithmetic order as spmv_unitdiag: z_i, then the blocks in ascending column
-// order.  The three lower and then the three upper neighbours' rows go
-// through LDS, eight lanes per cell.
+// w_i += sum_{k lower} A_ik z_k for the cells of one brick: w_i holds the
+// sentinel until the backward sweep publishes z_i + sum_{j upper} A_ij z_j
+// there, and the lower neighbours' z are read as the sweep publishes them
+// (the work list puts the brick after the backward bricks of all its lower
+// neighbours).  The three lower rows go through LDS, eight lanes per cell;
+// the blocks are added in ascending column order.
 template <class T, class TV>
-__device__ __forceinline__ void spmv_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-                                           const int32_t* __restrict__ row_ptr, const T* __restrict__ A,
-                                           const TV* z, TV* __restrict__ w, int32_t* err, BrickLds& L) {
+__device__ __forceinline__ void spmv_lower_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny,
+                                                 int32_t nz, const int32_t* __restrict__ row_ptr,
+                                                 const T* __restrict__ A, const TV* z, TV* w, int32_t* err,
+                                                 BrickLds& L) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
     const int r = bc.r;
     const bool act = bc.i >= 0;
     const int32_t ii = bc.ii;
     const int32_t nxy = nx * ny;
     const int32_t ix = ii % nx, iy = (ii / nx) % ny, iz = ii / nxy;
-    const int32_t nb[6] = {iz > 0 ? ii - nxy : -1, iy > 0 ? ii - nx : -1, ix > 0 ? ii - 1 : -1,
-                           ix + 1 < nx ? ii + 1 : -1, iy + 1 < ny ? ii + nx : -1, iz + 1 < nz ? ii + nxy : -1};
-    const int32_t b0 = row_ptr[ii];
+    const int32_t lower[3] = {iz > 0 ? ii - nxy : -1, iy > 0 ? ii - nx : -1, ix > 0 ? ii - 1 : -1};
+    const int32_t b0 = row_ptr[ii];   // the lower blocks lead the block row
     const int me = bc.g * 8 + r;
-    const typename Bits<TV>::U own0 = act ? peek(z + (size_t)ii * NU + r) : 0;
-    double acc = act ? (double)await_value(z + (size_t)ii * NU + r, own0, err) : 0.0;
+    double arow[3][8];
     int32_t blk = b0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (h == 1) ++blk;   // the diagonal block (identity, not read)
-        double arow[3][8];
+    for (int k = 0; k < 3; ++k) {
+        const T* a = A + (size_t)blk * BS + r * 8;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int32_t j = nb[3 * h + k];
-            const T* a = A + (size_t)(j >= 0 ? blk : b0) * BS + r * 8;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const double x = (double)a[c];
-                arow[k][c] = j >= 0 ? x : 0.0;
-            }
-            blk += j >= 0;
+        for (int c = 0; c < 8; ++c) {
+            const double x = (double)a[c];
+            arow[k][c] = lower[k] >= 0 ? x : 0.0;
         }
-        typename Bits<TV>::U first[3];
+        blk += lower[k] >= 0;
+    }
+    typename Bits<TV>::U first[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int32_t j = nb[3 * h + k];
-            first[k] = (act && j >= 0) ? peek(z + (size_t)j * NU + r) : 0;
-        }
+    for (int k = 0; k < 3; ++k) first[k] = (act && lower[k] >= 0) ? peek(z + (size_t)lower[k] * NU + r) : 0;
+    const typename Bits<TV>::U own0 = act ? peek(w + (size_t)ii * NU + r) : 0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int32_t j = nb[3 * h + k];
-            L.ext[k][me] = (act && j >= 0) ? (double)await_value(z + (size_t)j * NU + r, first[k], err) : 0.0;
-        }
-        wave_lds_sync();
+    for (int k = 0; k < 3; ++k)
+        L.ext[k][me] =
+            (act && lower[k] >= 0) ? (double)await_value(z + (size_t)lower[k] * NU + r, first[k], err) : 0.0;
+    double acc = act ? (double)await_value(w + (size_t)ii * NU + r, own0, err) : 0.0;
+    wave_lds_sync();
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            double x[8];
-            lds_row8(&L.ext[k][bc.g * 8], x);
+    for (int k = 0; k < 3; ++k) {
+        double x[8];
+        lds_row8(&L.ext[k][bc.g * 8], x);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc += arow[k][c] * x[c];
-        }
-        wave_lds_sync();
+        for (int c = 0; c < 8; ++c) acc += arow[k][c] * x[c];
     }
     if (act) w[(size_t)ii * NU + r] = (TV)acc;
 }
@@ -599,24 +599,24 @@ __device__ __forceinline__ void spmv_brick(int32_t b, int32_t nbx, int32_t nby, 
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-    const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y, TV* __restrict__ z, unsigned long long* ticket,
-    unsigned long long base, int32_t* err) {
+    const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y, TV* __restrict__ z, TV* wreset,
+    unsigned long long* ticket, unsigned long long base, int32_t* err) {
     __shared__ BrickLds L;
     const int32_t k = take_ticket(ticket, base);
     if (k >= nbrick) return;
-    fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, Lt, rin, y, z, err, L);
+    fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, Lt, rin, y, z, wreset, err, L);
 }
 
 // forward sweep preceded, row by row, by the lagged Gram-Schmidt update (FP64)
 template <class T>
 __global__ void __launch_bounds__(256) bilu0_fwd_update_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-    const T* __restrict__ Lt, LagUpdate lu, double* y, double* __restrict__ z, unsigned long long* ticket,
-    unsigned long long base, int32_t* err) {
+    const T* __restrict__ Lt, LagUpdate lu, double* y, double* __restrict__ z, double* wreset,
+    unsigned long long* ticket, unsigned long long base, int32_t* err) {
     __shared__ BrickLds L;
     const int32_t k = take_ticket(ticket, base);
     if (k >= nbrick) return;
-    fwd_brick<T, double, true>(bricks[k], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, err, L, lu);
+    fwd_brick<T, double, true>(bricks[k], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, wreset, err, L, lu);
 }
 
 template <class T, class TV>
@@ -627,7 +627,7 @@ __global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
     __shared__ BrickLds L;
     const int32_t k = take_ticket(ticket, base);
     if (k >= nbrick) return;
-    bwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, err, L);
+    bwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, nullptr, err, L);
 }
 
 // Backward sweep and w = A z in one launch: the work list interleaves the
@@ -639,16 +639,16 @@ template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_bwd_spmv_syncfree(
     const int32_t* __restrict__ items, int32_t nitem, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-    const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, TV* __restrict__ w, unsigned long long* ticket,
+    const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, TV* w, unsigned long long* ticket,
     unsigned long long base, int32_t* err) {
     __shared__ BrickLds L;
     const int32_t k = take_ticket(ticket, base);
     if (k >= nitem) return;
     const int32_t it = items[k];
     if (it & SPMV_ITEM)
-        spmv_brick<T, TV>(it & (SPMV_ITEM - 1), nbx, nby, nx, ny, nz, row_ptr, A, z, w, err, L);
+        spmv_lower_brick<T, TV>(it & (SPMV_ITEM - 1), nbx, nby, nx, ny, nz, row_ptr, A, z, w, err, L);
     else
-        bwd_brick<T, TV>(it, nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, err, L);
+        bwd_brick<T, TV>(it, nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, w, err, L);
 }
 
 template <class U>
@@ -702,7 +702,7 @@ hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, con
         const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
         hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(nwg), dim3(256), ISC_SWEEP_LDS, ctx->stream,
                            ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
-                           (const T*)isc::lt_buffer<T>(ctx), r, v, z, ctx->ticket, ctx->ticket_base,
+                           (const T*)isc::lt_buffer<T>(ctx), r, v, z, (TV*)nullptr, ctx->ticket, ctx->ticket_base,
                            ctx->flags + ISC_FLAG_SWEEP);
         ctx->ticket_base += (unsigned long long)nwg;
         hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV>), dim3(nwg), dim3(256), ISC_SWEEP_LDS, ctx->stream,
@@ -741,7 +741,7 @@ hipError_t isc_launch_bilu0_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Dinv
     const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
     hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(ctx->nbrick), dim3(256), ISC_SWEEP_LDS, ctx->stream,
                        ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
-                       (const T*)isc::lt_buffer<T>(ctx), r, v, z, ctx->ticket, ctx->ticket_base,
+                       (const T*)isc::lt_buffer<T>(ctx), r, v, z, w, ctx->ticket, ctx->ticket_base,
                        ctx->flags + ISC_FLAG_SWEEP);
     ctx->ticket_base += (unsigned long long)ctx->nbrick;
     const int32_t nitem = 2 * ctx->nbrick;
@@ -762,7 +762,8 @@ hipError_t isc_launch_update_apply_spmv(isc_ctx* ctx, const double* A, const dou
     const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
     hipLaunchKernelGGL((isc::bilu0_fwd_update_syncfree<double>), dim3(ctx->nbrick), dim3(256), ISC_SWEEP_LDS,
                        ctx->stream, ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
-                       (const double*)ctx->Lt, lu, v, z, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+                       (const double*)ctx->Lt, lu, v, z, w, ctx->ticket, ctx->ticket_base,
+                       ctx->flags + ISC_FLAG_SWEEP);
     ctx->ticket_base += (unsigned long long)ctx->nbrick;
     const int32_t nitem = 2 * ctx->nbrick;
     hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<double, double>), dim3(nitem), dim3(256), ISC_SWEEP_LDS,

@@ -77,12 +77,13 @@ def lib():
                                   ctypes.POINTER(SolveInfo)]
         L.isc_oil_rate.argtypes = [_vp, _vp, ctypes.POINTER(_f64)]
         L.isc_profile.argtypes = [_vp, _i32, _vp, _vp]
+        L.isc_profile_vectors.argtypes = [_vp, _vp]
         L.isc_last_error.argtypes = [_vp]
         L.isc_last_error.restype = ctypes.c_char_p
         for name in ("isc_create", "isc_destroy", "isc_set_params", "isc_bcsr_pattern", "isc_assemble",
                      "isc_decouple", "isc_solve", "isc_newton_step", "isc_spmv", "isc_bilu0",
                      "isc_bilu0_apply", "isc_bilu0_apply_spmv", "isc_update", "isc_scaled_norm", "isc_adjoint",
-                     "isc_profile", "isc_oil_rate"):
+                     "isc_profile", "isc_profile_vectors", "isc_oil_rate"):
             getattr(L, name).restype = _i32
         _LIB = L
     return _LIB
@@ -238,6 +239,15 @@ def isc_profile(ctx: "Context", enable: int):
     """Start (1), stop (0) or read (-1) the library's kernel-class timers;
     returns {class: (milliseconds, launches)}."""
     return _profile_call(ctx, enable)
+
+
+def isc_profile_vectors(ctx: "Context"):
+    """{class: full-length vectors streamed beyond the class's fixed access
+    pattern} over the current profiling window (the Gram-Schmidt update
+    folded into the FP64 GMRES iteration's forward sweep)."""
+    vec = (ctypes.c_double * len(PROF_CLASSES))()
+    ctx._check(lib().isc_profile_vectors(ctx.h, vec))
+    return {name: vec[k] for k, name in enumerate(PROF_CLASSES)}
 
 
 class Simulator:
