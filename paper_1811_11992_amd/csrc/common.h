@@ -12,8 +12,19 @@ namespace isc {
 
 constexpr int NU = 8;        // unknowns per cell
 constexpr int BS = 64;       // 8x8 block
-// cells of one brick of the sync-free triangular sweeps (one 256-thread workgroup)
-constexpr int BRICK_X = 4, BRICK_Y = 4, BRICK_Z = 2;
+// cells of one brick of the sync-free triangular sweeps (one workgroup, eight
+// threads per cell)
+#ifndef ISC_BRICK_X
+#define ISC_BRICK_X 4
+#endif
+#ifndef ISC_BRICK_Y
+#define ISC_BRICK_Y 4
+#endif
+#ifndef ISC_BRICK_Z
+#define ISC_BRICK_Z 2
+#endif
+constexpr int BRICK_X = ISC_BRICK_X, BRICK_Y = ISC_BRICK_Y, BRICK_Z = ISC_BRICK_Z;
+constexpr int BRICK_THREADS = BRICK_X * BRICK_Y * BRICK_Z * 8;
 
 // The delayed Gram-Schmidt update of the previous GMRES iteration, done by
 // the forward sweep for its own rows before sweeping (FP64 solver):

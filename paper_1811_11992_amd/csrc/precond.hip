@@ -180,7 +180,8 @@ __global__ void __launch_bounds__(256) bilu0_fwd_level(
     y[(size_t)i * NU + r] = (TV)acc;
 }
 
-// Backward sweep of one level (in place over y): z_i = D_i^-1 (y_i - sum_{j upper} A_ij z_j).
+// Backward sweep of one level (in place over y): z_i = D_i^-1 (y_i - sum_{j upper} A_ij z_j),
+// the sum formed on its own and then subtracted (as the sync-free sweep does).
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_bwd_level(
     const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, int32_t nz,
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(256) bilu0_bwd_level(
     const int32_t i = rows[t];
     const int32_t nxy = nx * ny;
     const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
-    double acc = (double)z[(size_t)i * NU + r];
+    double su = 0.0;
     int32_t blk = diag_pos[i] + 1;
     const int32_t upper[3] = {ix + 1 < nx ? i + 1 : -1, iy + 1 < ny ? i + nx : -1,
                               iz + 1 < nz ? i + nxy : -1};
@@ -204,14 +205,38 @@ __global__ void __launch_bounds__(256) bilu0_bwd_level(
         const T* a = A + (size_t)blk * BS + r * 8;
         const TV* x = z + (size_t)j * NU;
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc -= (double)a[c] * (double)x[c];
+        for (int c = 0; c < 8; ++c) su += (double)a[c] * (double)x[c];
         ++blk;
     }
+    const double acc = (double)z[(size_t)i * NU + r] - su;
     const T* d = Dinv + (size_t)i * BS + r * 8;
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 8; ++c) s += (double)d[c] * __shfl(acc, gbase + c);
     z[(size_t)i * NU + r] = (TV)s;
+}
+
+// The eight entries of a block row or of a cell's vector block, by 16-byte
+// loads (a row is 64-byte aligned in FP64 and 32-byte aligned in FP32).
+__device__ __forceinline__ void row8(const double* a, double* out) {
+    const double2* p = reinterpret_cast<const double2*>(a);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double2 t = p[k];
+        out[2 * k] = t.x;
+        out[2 * k + 1] = t.y;
+    }
+}
+__device__ __forceinline__ void row8(const float* a, double* out) {
+    const float4* p = reinterpret_cast<const float4*>(a);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const float4 t = p[k];
+        out[4 * k] = (double)t.x;
+        out[4 * k + 1] = (double)t.y;
+        out[4 * k + 2] = (double)t.z;
+        out[4 * k + 3] = (double)t.w;
+    }
 }
 
 // y = A x for the decoupled matrix (unit diagonal blocks are not read).
@@ -228,10 +253,11 @@ __global__ void __launch_bounds__(256) spmv_unitdiag(int32_t n, const int32_t* _
     const int32_t b0 = row_ptr[i], b1 = row_ptr[i + 1], dp = diag_pos[i];
     for (int32_t b = b0; b < b1; ++b) {
         if (b == dp) continue;
-        const T* a = A + (size_t)b * BS + r * 8;
-        const TV* xx = x + (size_t)col_idx[b] * NU;
+        double a[8], xx[8];
+        row8(A + (size_t)b * BS + r * 8, a);
+        row8(x + (size_t)col_idx[b] * NU, xx);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) acc += (double)a[c] * (double)xx[c];
+        for (int c = 0; c < 8; ++c) acc += a[c] * xx[c];
     }
     y[(size_t)i * NU + r] = (TV)acc;
 }
@@ -317,7 +343,7 @@ __device__ __forceinline__ int32_t take_ticket(unsigned long long* ticket, unsig
 // y+, z+ (backward), as the level launches do.
 constexpr int BRICK_CELLS = BRICK_X * BRICK_Y * BRICK_Z;
 constexpr int BRICK_STEPS = BRICK_X + BRICK_Y + BRICK_Z - 2;
-static_assert(BRICK_CELLS * 8 == 256, "one brick per 256-thread workgroup");
+static_assert(BRICK_THREADS % 64 == 0 && BRICK_THREADS <= 1024, "one brick per workgroup of whole wavefronts");
 
 struct BrickCell {
     int32_t i;      // row, or -1 outside the grid
@@ -390,12 +416,10 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     double arow[3][8];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const T* a = Lt + ((size_t)ii * 3 + q) * BS + r * 8;
+        double x[8];
+        row8(Lt + ((size_t)ii * 3 + q) * BS + r * 8, x);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const double x = (double)a[c];
-            arow[q][c] = lower[q] >= 0 ? x : 0.0;
-        }
+        for (int c = 0; c < 8; ++c) arow[q][c] = lower[q] >= 0 ? x[c] : 0.0;
     }
     double rv;
     if constexpr (UPDATE) {
@@ -485,18 +509,14 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     int32_t blk = b0 + 1;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const T* a = A + (size_t)(upper[q] >= 0 ? blk : b0) * BS + r * 8;
+        double x[8];
+        row8(A + (size_t)(upper[q] >= 0 ? blk : b0) * BS + r * 8, x);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const double x = (double)a[c];
-            arow[q][c] = upper[q] >= 0 ? x : 0.0;
-        }
+        for (int c = 0; c < 8; ++c) arow[q][c] = upper[q] >= 0 ? x[c] : 0.0;
         blk += upper[q] >= 0;
     }
     double drow[8];
-    const T* d = Dinv + (size_t)ii * BS + r * 8;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) drow[c] = (double)d[c];
+    row8(Dinv + (size_t)ii * BS + r * 8, drow);
     const double yi = act ? (double)y[(size_t)ii * NU + r] : 0.0;
     if (act) y[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
     bool ext[3];
@@ -517,15 +537,17 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
         const int buf = s & 1;
         L.v[buf][me] = zout;
         __syncthreads();
-        double acc = yi;
+        // (U z)_i on its own: the fused SpMV reuses it without cancellation
+        double su = 0.0;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const double* src = (upper[q] >= 0 && inb[q] >= 0) ? &L.v[buf][inb[q] * 8] : &L.ext[q][bc.g * 8];
             double x[8];
             lds_row8(src, x);
 #pragma unroll
-            for (int c = 0; c < 8; ++c) acc -= arow[q][c] * x[c];
+            for (int c = 0; c < 8; ++c) su += arow[q][c] * x[c];
         }
+        const double acc = yi - su;
         L.acc[me] = acc;
         wave_lds_sync();
         double a8[8];
@@ -535,7 +557,7 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
         for (int c = 0; c < 8; ++c) t += drow[c] * a8[c];
         if (mystep == s) {
             zout = t;
-            uz = yi - acc;
+            uz = su;
         }
         wave_lds_sync();
     }
@@ -567,12 +589,10 @@ __device__ __forceinline__ void spmv_lower_brick(int32_t b, int32_t nbx, int32_t
     int32_t blk = b0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const T* a = A + (size_t)blk * BS + r * 8;
+        double x[8];
+        row8(A + (size_t)blk * BS + r * 8, x);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            const double x = (double)a[c];
-            arow[k][c] = lower[k] >= 0 ? x : 0.0;
-        }
+        for (int c = 0; c < 8; ++c) arow[k][c] = lower[k] >= 0 ? x[c] : 0.0;
         blk += lower[k] >= 0;
     }
     typename Bits<TV>::U first[3];
@@ -597,7 +617,7 @@ __device__ __forceinline__ void spmv_lower_brick(int32_t b, int32_t nbx, int32_t
 
 // One workgroup per brick; workgroups take tickets in brick-list order.
 template <class T, class TV>
-__global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
+__global__ void __launch_bounds__(BRICK_THREADS) bilu0_fwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y, TV* __restrict__ z, TV* wreset,
     unsigned long long* ticket, unsigned long long base, int32_t* err) {
@@ -609,7 +629,7 @@ __global__ void __launch_bounds__(256) bilu0_fwd_syncfree(
 
 // forward sweep preceded, row by row, by the lagged Gram-Schmidt update (FP64)
 template <class T>
-__global__ void __launch_bounds__(256) bilu0_fwd_update_syncfree(
+__global__ void __launch_bounds__(BRICK_THREADS) bilu0_fwd_update_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const T* __restrict__ Lt, LagUpdate lu, double* y, double* __restrict__ z, double* wreset,
     unsigned long long* ticket, unsigned long long base, int32_t* err) {
@@ -620,7 +640,7 @@ __global__ void __launch_bounds__(256) bilu0_fwd_update_syncfree(
 }
 
 template <class T, class TV>
-__global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
+__global__ void __launch_bounds__(BRICK_THREADS) bilu0_bwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ y,
     TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
@@ -636,7 +656,7 @@ __global__ void __launch_bounds__(256) bilu0_bwd_syncfree(
 // neighbours, so the SpMV work fills the gaps of the wait chain.
 constexpr int32_t SPMV_ITEM = 1 << 30;
 template <class T, class TV>
-__global__ void __launch_bounds__(256) bilu0_bwd_spmv_syncfree(
+__global__ void __launch_bounds__(BRICK_THREADS) bilu0_bwd_spmv_syncfree(
     const int32_t* __restrict__ items, int32_t nitem, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
     const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, TV* w, unsigned long long* ticket,
@@ -700,12 +720,12 @@ hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, con
         const int32_t nwg = ctx->nbrick;   // one workgroup per brick
         const int32_t nbx = (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X;
         const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
-        hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(nwg), dim3(256), ISC_SWEEP_LDS, ctx->stream,
+        hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(nwg), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS, ctx->stream,
                            ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
                            (const T*)isc::lt_buffer<T>(ctx), r, v, z, (TV*)nullptr, ctx->ticket, ctx->ticket_base,
                            ctx->flags + ISC_FLAG_SWEEP);
         ctx->ticket_base += (unsigned long long)nwg;
-        hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV>), dim3(nwg), dim3(256), ISC_SWEEP_LDS, ctx->stream,
+        hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV>), dim3(nwg), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS, ctx->stream,
                            ctx->bricks_bwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->diag_pos, A,
                            Dinv, v, z, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
         ctx->ticket_base += (unsigned long long)nwg;
@@ -739,13 +759,13 @@ hipError_t isc_launch_bilu0_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Dinv
     TV* v = isc::sweep_buffer<TV>(ctx);
     const int32_t nbx = (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X;
     const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
-    hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(ctx->nbrick), dim3(256), ISC_SWEEP_LDS, ctx->stream,
+    hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(ctx->nbrick), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS, ctx->stream,
                        ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
                        (const T*)isc::lt_buffer<T>(ctx), r, v, z, w, ctx->ticket, ctx->ticket_base,
                        ctx->flags + ISC_FLAG_SWEEP);
     ctx->ticket_base += (unsigned long long)ctx->nbrick;
     const int32_t nitem = 2 * ctx->nbrick;
-    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<T, TV>), dim3(nitem), dim3(256), ISC_SWEEP_LDS, ctx->stream,
+    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<T, TV>), dim3(nitem), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS, ctx->stream,
                        ctx->items_bwd_spmv, nitem, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
                        ctx->diag_pos, A, Dinv, v, z, w, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
     ctx->ticket_base += (unsigned long long)nitem;
@@ -760,13 +780,13 @@ hipError_t isc_launch_update_apply_spmv(isc_ctx* ctx, const double* A, const dou
     double* v = ctx->sweep64;
     const int32_t nbx = (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X;
     const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
-    hipLaunchKernelGGL((isc::bilu0_fwd_update_syncfree<double>), dim3(ctx->nbrick), dim3(256), ISC_SWEEP_LDS,
+    hipLaunchKernelGGL((isc::bilu0_fwd_update_syncfree<double>), dim3(ctx->nbrick), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS,
                        ctx->stream, ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
                        (const double*)ctx->Lt, lu, v, z, w, ctx->ticket, ctx->ticket_base,
                        ctx->flags + ISC_FLAG_SWEEP);
     ctx->ticket_base += (unsigned long long)ctx->nbrick;
     const int32_t nitem = 2 * ctx->nbrick;
-    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<double, double>), dim3(nitem), dim3(256), ISC_SWEEP_LDS,
+    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<double, double>), dim3(nitem), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS,
                        ctx->stream, ctx->items_bwd_spmv, nitem, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
                        ctx->row_ptr, ctx->diag_pos, A, Dinv, v, z, w, ctx->ticket, ctx->ticket_base,
                        ctx->flags + ISC_FLAG_SWEEP);
