@@ -239,31 +239,53 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     const int32_t nbx = (nx + isc::BRICK_X - 1) / isc::BRICK_X, nby = (ny + isc::BRICK_Y - 1) / isc::BRICK_Y,
                   nbz = (nz + isc::BRICK_Z - 1) / isc::BRICK_Z;
     ctx->nbrick = nbx * nby * nbz;
-    std::vector<int32_t> chf((size_t)ctx->nbrick), chb, items;
+    std::vector<int32_t> chf, chb, items;
     {
         const int32_t nbl = nbx + nby + nbz - 2;
-        std::vector<int32_t> off(nbl + 2, 0);
-        for (int32_t b = 0; b < ctx->nbrick; ++b) off[b % nbx + (b / nbx) % nby + b / (nbx * nby) + 1]++;
-        for (int32_t s = 0; s <= nbl; ++s) off[s + 1] += off[s];
-        for (int32_t b = 0; b < ctx->nbrick; ++b) chf[off[b % nbx + (b / nbx) % nby + b / (nbx * nby)]++] = b;
-        chb.assign(chf.rbegin(), chf.rend());
+        const int32_t dummy = ctx->nbrick;   // past the last brick layer: every cell inactive
+        // pads a group of mutually independent items to whole workgroups
+        auto pad = [](std::vector<int32_t>& v, int32_t fill) {
+            while (v.size() % isc::MAX_BRICKS_PER_WG) v.push_back(fill);
+        };
+        auto level_of = [&](int32_t b) { return b % nbx + (b / nbx) % nby + b / (nbx * nby); };
+        std::vector<std::vector<int32_t>> by_level(nbl);   // ascending brick index
+        for (int32_t b = 0; b < ctx->nbrick; ++b) by_level[level_of(b)].push_back(b);
+        for (int32_t L = 0; L < nbl; ++L) {
+            chf.insert(chf.end(), by_level[L].begin(), by_level[L].end());
+            pad(chf, dummy);
+        }
+        for (int32_t L = nbl - 1; L >= 0; --L) {
+            chb.insert(chb.end(), by_level[L].rbegin(), by_level[L].rend());
+            pad(chb, dummy);
+        }
         // fused backward sweep + SpMV: after the backward bricks of level L come the
         // SpMV bricks of level L + 1 + ISC_SPMV_LAG (their neighbours are at levels
         // L + ISC_SPMV_LAG .. L + 2 + ISC_SPMV_LAG, all swept before them); the lag
         // keeps SpMV bricks from waiting on the sweep front
-        auto level_of = [&](int32_t b) { return b % nbx + (b / nbx) % nby + b / (nbx * nby); };
-        std::vector<std::vector<int32_t>> by_level(nbl);
-        for (int32_t b : chb) by_level[level_of(b)].push_back(b);
-        items.reserve((size_t)2 * ctx->nbrick);
+        items.reserve((size_t)2 * ctx->nbrick + 2 * nbl * isc::MAX_BRICKS_PER_WG);
+        auto push_spmv = [&](int32_t L) {
+            for (auto it = by_level[L].rbegin(); it != by_level[L].rend(); ++it) items.push_back(*it | (1 << 30));
+            pad(items, dummy | (1 << 30));
+        };
         int32_t next_spmv = nbl - 1;   // highest level whose SpMV bricks are not listed yet
         for (int32_t L = nbl - 1; L >= 0; --L) {
-            for (int32_t b : by_level[L]) items.push_back(b);
-            for (; next_spmv >= 0 && next_spmv >= L + 1 + ISC_SPMV_LAG; --next_spmv)
-                for (int32_t b : by_level[next_spmv]) items.push_back(b | (1 << 30));
+            items.insert(items.end(), by_level[L].rbegin(), by_level[L].rend());
+            pad(items, dummy);
+            for (; next_spmv >= 0 && next_spmv >= L + 1 + ISC_SPMV_LAG; --next_spmv) push_spmv(next_spmv);
         }
-        for (; next_spmv >= 0; --next_spmv)
-            for (int32_t b : by_level[next_spmv]) items.push_back(b | (1 << 30));
+        for (; next_spmv >= 0; --next_spmv) push_spmv(next_spmv);
     }
+    {
+        // one atomic ticket per workgroup costs about 12 ns of serialised
+        // atomic throughput; pair bricks once those exceed a fraction of the
+        // wait chain (about 200 bricks per brick level)
+        const int32_t nbl = nbx + nby + nbz - 2;
+        ctx->bpw = ctx->nbrick >= 200 * nbl ? 2 : 1;
+        if (const char* e = getenv("ISC_BRICKS_PER_WG")) ctx->bpw = e[0] == '2' ? 2 : 1;
+    }
+    ctx->nfwd_items = (int32_t)chf.size();
+    ctx->nbwd_items = (int32_t)chb.size();
+    ctx->nfused_items = (int32_t)items.size();
     if (const char* e = getenv("ISC_LEVEL_SWEEPS")) ctx->syncfree = !(e[0] == '1');
 
     // wells

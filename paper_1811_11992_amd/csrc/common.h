@@ -25,6 +25,9 @@ constexpr int BS = 64;       // 8x8 block
 #endif
 constexpr int BRICK_X = ISC_BRICK_X, BRICK_Y = ISC_BRICK_Y, BRICK_Z = ISC_BRICK_Z;
 constexpr int BRICK_THREADS = BRICK_X * BRICK_Y * BRICK_Z * 8;
+// A sweep workgroup takes one brick, or two side by side under one ticket
+// (the work lists are padded for two)
+constexpr int MAX_BRICKS_PER_WG = 2;
 
 // The delayed Gram-Schmidt update of the previous GMRES iteration, done by
 // the forward sweep for its own rows before sweeping (FP64 solver):
@@ -130,6 +133,15 @@ struct isc_ctx {
     // descending (backward) brick level; tickets order the workgroups
     bool syncfree = true;
     int32_t nbrick = 0;
+    // lengths of the three sweep work lists: each group of mutually independent
+    // items (a brick level, or the SpMV bricks of one level) is padded with
+    // inactive bricks to a multiple of MAX_BRICKS_PER_WG, so bricks sharing a
+    // workgroup never wait for one another
+    int32_t nfwd_items = 0, nbwd_items = 0, nfused_items = 0;
+    // bricks per sweep workgroup: 2 halves the ticket atomics, which bound the
+    // sweeps on large grids; 1 keeps bricks uncoupled where the chain of waits
+    // dominates (small grids)
+    int32_t bpw = 1;
     int32_t* bricks_fwd = nullptr;
     int32_t* bricks_bwd = nullptr;
     int32_t* items_bwd_spmv = nullptr;   // [2 nbrick] backward bricks interleaved with SpMV bricks

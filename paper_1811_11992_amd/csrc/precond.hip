@@ -325,9 +325,16 @@ template <class TV> __device__ __forceinline__ TV await_value(const TV* p, typen
     }
 }
 
-__device__ __forceinline__ int32_t take_ticket(unsigned long long* ticket, unsigned long long base) {
+// The workgroup's ticket: its index among the launch's workgroups in the
+// order they started.  A ticket below base (a counter that fell behind the
+// host's count) reads as n, past every work item, so such a launch does
+// nothing rather than index out of range.
+__device__ __forceinline__ int32_t take_ticket(unsigned long long* ticket, unsigned long long base, int32_t n) {
     __shared__ int32_t s_t;
-    if (threadIdx.x == 0) s_t = (int32_t)(atomicAdd(ticket, 1ULL) - base);
+    if (threadIdx.x == 0) {
+        const unsigned long long d = atomicAdd(ticket, 1ULL) - base;
+        s_t = d < (unsigned long long)n ? (int32_t)d : n;
+    }
     __syncthreads();
     return s_t;
 }
@@ -353,8 +360,9 @@ struct BrickCell {
 __device__ __forceinline__ BrickCell brick_cell(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny,
                                                 int32_t nz) {
     BrickCell bc;
-    bc.g = threadIdx.x >> 3;
-    bc.r = threadIdx.x & 7;
+    const int tid = (int)(threadIdx.x % BRICK_THREADS);   // thread within the brick
+    bc.g = tid >> 3;
+    bc.r = tid & 7;
     const int32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
     bc.dx = bc.g % BRICK_X;
     bc.dy = (bc.g / BRICK_X) % BRICK_Y;
@@ -616,59 +624,66 @@ __device__ __forceinline__ void spmv_lower_brick(int32_t b, int32_t nbx, int32_t
 }
 
 // One workgroup per brick; workgroups take tickets in brick-list order.
-template <class T, class TV>
-__global__ void __launch_bounds__(BRICK_THREADS) bilu0_fwd_syncfree(
-    const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+template <class T, class TV, int BPW>
+__global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_syncfree(
+    const int32_t* __restrict__ bricks, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y, TV* __restrict__ z, TV* wreset,
     unsigned long long* ticket, unsigned long long base, int32_t* err) {
-    __shared__ BrickLds L;
-    const int32_t k = take_ticket(ticket, base);
-    if (k >= nbrick) return;
-    fwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, Lt, rin, y, z, wreset, err, L);
+    __shared__ BrickLds L[BPW];
+    const int32_t k = take_ticket(ticket, base, ngroup);
+    if (k >= ngroup) return;
+    const int h = (int)(threadIdx.x / BRICK_THREADS);
+    fwd_brick<T, TV>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, rin, y, z, wreset, err, L[h]);
 }
 
 // forward sweep preceded, row by row, by the lagged Gram-Schmidt update (FP64)
-template <class T>
-__global__ void __launch_bounds__(BRICK_THREADS) bilu0_fwd_update_syncfree(
-    const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+template <class T, int BPW>
+__global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_update_syncfree(
+    const int32_t* __restrict__ bricks, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const T* __restrict__ Lt, LagUpdate lu, double* y, double* __restrict__ z, double* wreset,
     unsigned long long* ticket, unsigned long long base, int32_t* err) {
-    __shared__ BrickLds L;
-    const int32_t k = take_ticket(ticket, base);
-    if (k >= nbrick) return;
-    fwd_brick<T, double, true>(bricks[k], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, wreset, err, L, lu);
+    __shared__ BrickLds L[BPW];
+    const int32_t k = take_ticket(ticket, base, ngroup);
+    if (k >= ngroup) return;
+    const int h = (int)(threadIdx.x / BRICK_THREADS);
+    fwd_brick<T, double, true>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, wreset, err,
+                               L[h], lu);
 }
 
-template <class T, class TV>
-__global__ void __launch_bounds__(BRICK_THREADS) bilu0_bwd_syncfree(
-    const int32_t* __restrict__ bricks, int32_t nbrick, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+template <class T, class TV, int BPW>
+__global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_bwd_syncfree(
+    const int32_t* __restrict__ bricks, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ y,
     TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
-    __shared__ BrickLds L;
-    const int32_t k = take_ticket(ticket, base);
-    if (k >= nbrick) return;
-    bwd_brick<T, TV>(bricks[k], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, nullptr, err, L);
+    __shared__ BrickLds L[BPW];
+    const int32_t k = take_ticket(ticket, base, ngroup);
+    if (k >= ngroup) return;
+    const int h = (int)(threadIdx.x / BRICK_THREADS);
+    bwd_brick<T, TV>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, nullptr, err, L[h]);
 }
 
 // Backward sweep and w = A z in one launch: the work list interleaves the
 // backward bricks (level by level, descending) with SpMV bricks (flag
 // SPMV_ITEM), each SpMV brick after the backward bricks of all its
-// neighbours, so the SpMV work fills the gaps of the wait chain.
+// neighbours, so the SpMV work fills the gaps of the wait chain.  The bricks
+// of one workgroup come from one padded group, so they are all backward
+// bricks (same block barriers) or all SpMV bricks (none).
 constexpr int32_t SPMV_ITEM = 1 << 30;
-template <class T, class TV>
-__global__ void __launch_bounds__(BRICK_THREADS) bilu0_bwd_spmv_syncfree(
-    const int32_t* __restrict__ items, int32_t nitem, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
+template <class T, class TV, int BPW>
+__global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_bwd_spmv_syncfree(
+    const int32_t* __restrict__ items, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
     const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, TV* w, unsigned long long* ticket,
     unsigned long long base, int32_t* err) {
-    __shared__ BrickLds L;
-    const int32_t k = take_ticket(ticket, base);
-    if (k >= nitem) return;
-    const int32_t it = items[k];
+    __shared__ BrickLds L[BPW];
+    const int32_t k = take_ticket(ticket, base, ngroup);
+    if (k >= ngroup) return;
+    const int h = (int)(threadIdx.x / BRICK_THREADS);
+    const int32_t it = items[k * BPW + h];
     if (it & SPMV_ITEM)
-        spmv_lower_brick<T, TV>(it & (SPMV_ITEM - 1), nbx, nby, nx, ny, nz, row_ptr, A, z, w, err, L);
+        spmv_lower_brick<T, TV>(it & (SPMV_ITEM - 1), nbx, nby, nx, ny, nz, row_ptr, A, z, w, err, L[h]);
     else
-        bwd_brick<T, TV>(it, nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, w, err, L);
+        bwd_brick<T, TV>(it, nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, w, err, L[h]);
 }
 
 template <class U>
@@ -713,22 +728,61 @@ hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t*
     return hipGetLastError();
 }
 
+// One launch of each sync-free sweep kernel with `BPW` bricks per workgroup
+// (the context's choice); each workgroup takes one ticket.
+namespace {
+int32_t bricks_x(const isc_ctx* ctx) { return (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X; }
+int32_t bricks_y(const isc_ctx* ctx) { return (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y; }
+
+template <int BPW, class T, class TV>
+void launch_fwd(isc_ctx* ctx, const TV* r, TV* v, TV* z, TV* w) {
+    const int32_t nwg = ctx->nfwd_items / BPW;
+    hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV, BPW>), dim3(nwg), dim3(isc::BRICK_THREADS * BPW),
+                       ISC_SWEEP_LDS, ctx->stream, ctx->bricks_fwd, nwg, bricks_x(ctx), bricks_y(ctx), ctx->g.nx,
+                       ctx->g.ny, ctx->g.nz, (const T*)isc::lt_buffer<T>(ctx), r, v, z, w, ctx->ticket,
+                       ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+    ctx->ticket_base += (unsigned long long)nwg;
+}
+template <int BPW>
+void launch_fwd_update(isc_ctx* ctx, const isc::LagUpdate& lu, double* v, double* z, double* w) {
+    const int32_t nwg = ctx->nfwd_items / BPW;
+    hipLaunchKernelGGL((isc::bilu0_fwd_update_syncfree<double, BPW>), dim3(nwg), dim3(isc::BRICK_THREADS * BPW),
+                       ISC_SWEEP_LDS, ctx->stream, ctx->bricks_fwd, nwg, bricks_x(ctx), bricks_y(ctx), ctx->g.nx,
+                       ctx->g.ny, ctx->g.nz, (const double*)ctx->Lt, lu, v, z, w, ctx->ticket, ctx->ticket_base,
+                       ctx->flags + ISC_FLAG_SWEEP);
+    ctx->ticket_base += (unsigned long long)nwg;
+}
+template <int BPW, class T, class TV>
+void launch_bwd(isc_ctx* ctx, const T* A, const T* Dinv, TV* v, TV* z) {
+    const int32_t nwg = ctx->nbwd_items / BPW;
+    hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV, BPW>), dim3(nwg), dim3(isc::BRICK_THREADS * BPW),
+                       ISC_SWEEP_LDS, ctx->stream, ctx->bricks_bwd, nwg, bricks_x(ctx), bricks_y(ctx), ctx->g.nx,
+                       ctx->g.ny, ctx->g.nz, ctx->diag_pos, A, Dinv, v, z, ctx->ticket, ctx->ticket_base,
+                       ctx->flags + ISC_FLAG_SWEEP);
+    ctx->ticket_base += (unsigned long long)nwg;
+}
+template <int BPW, class T, class TV>
+void launch_bwd_spmv(isc_ctx* ctx, const T* A, const T* Dinv, TV* v, TV* z, TV* w) {
+    const int32_t nwg = ctx->nfused_items / BPW;
+    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<T, TV, BPW>), dim3(nwg), dim3(isc::BRICK_THREADS * BPW),
+                       ISC_SWEEP_LDS, ctx->stream, ctx->items_bwd_spmv, nwg, bricks_x(ctx), bricks_y(ctx), ctx->g.nx,
+                       ctx->g.ny, ctx->g.nz, ctx->row_ptr, ctx->diag_pos, A, Dinv, v, z, w, ctx->ticket,
+                       ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
+    ctx->ticket_base += (unsigned long long)nwg;
+}
+}  // namespace
+
 template <class T, class TV>
 hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, const TV* r, TV* z) {
     if (ctx->syncfree) {
         TV* v = isc::sweep_buffer<TV>(ctx);
-        const int32_t nwg = ctx->nbrick;   // one workgroup per brick
-        const int32_t nbx = (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X;
-        const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
-        hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(nwg), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS, ctx->stream,
-                           ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
-                           (const T*)isc::lt_buffer<T>(ctx), r, v, z, (TV*)nullptr, ctx->ticket, ctx->ticket_base,
-                           ctx->flags + ISC_FLAG_SWEEP);
-        ctx->ticket_base += (unsigned long long)nwg;
-        hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV>), dim3(nwg), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS, ctx->stream,
-                           ctx->bricks_bwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->diag_pos, A,
-                           Dinv, v, z, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
-        ctx->ticket_base += (unsigned long long)nwg;
+        if (ctx->bpw == 2) {
+            launch_fwd<2, T, TV>(ctx, r, v, z, (TV*)nullptr);
+            launch_bwd<2, T, TV>(ctx, A, Dinv, v, z);
+        } else {
+            launch_fwd<1, T, TV>(ctx, r, v, z, (TV*)nullptr);
+            launch_bwd<1, T, TV>(ctx, A, Dinv, v, z);
+        }
         return hipGetLastError();
     }
     for (int32_t s = 0; s < ctx->nlev; ++s) {
@@ -757,18 +811,13 @@ hipError_t isc_launch_bilu0_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Dinv
         return isc_launch_spmv_t<T, TV>(ctx, A, z, w);
     }
     TV* v = isc::sweep_buffer<TV>(ctx);
-    const int32_t nbx = (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X;
-    const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
-    hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV>), dim3(ctx->nbrick), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS, ctx->stream,
-                       ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
-                       (const T*)isc::lt_buffer<T>(ctx), r, v, z, w, ctx->ticket, ctx->ticket_base,
-                       ctx->flags + ISC_FLAG_SWEEP);
-    ctx->ticket_base += (unsigned long long)ctx->nbrick;
-    const int32_t nitem = 2 * ctx->nbrick;
-    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<T, TV>), dim3(nitem), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS, ctx->stream,
-                       ctx->items_bwd_spmv, nitem, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
-                       ctx->diag_pos, A, Dinv, v, z, w, ctx->ticket, ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
-    ctx->ticket_base += (unsigned long long)nitem;
+    if (ctx->bpw == 2) {
+        launch_fwd<2, T, TV>(ctx, r, v, z, w);
+        launch_bwd_spmv<2, T, TV>(ctx, A, Dinv, v, z, w);
+    } else {
+        launch_fwd<1, T, TV>(ctx, r, v, z, w);
+        launch_bwd_spmv<1, T, TV>(ctx, A, Dinv, v, z, w);
+    }
     return hipGetLastError();
 }
 
@@ -778,19 +827,13 @@ hipError_t isc_launch_bilu0_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Dinv
 hipError_t isc_launch_update_apply_spmv(isc_ctx* ctx, const double* A, const double* Dinv, const isc::LagUpdate& lu,
                                         double* z, double* w) {
     double* v = ctx->sweep64;
-    const int32_t nbx = (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X;
-    const int32_t nby = (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y;
-    hipLaunchKernelGGL((isc::bilu0_fwd_update_syncfree<double>), dim3(ctx->nbrick), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS,
-                       ctx->stream, ctx->bricks_fwd, ctx->nbrick, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
-                       (const double*)ctx->Lt, lu, v, z, w, ctx->ticket, ctx->ticket_base,
-                       ctx->flags + ISC_FLAG_SWEEP);
-    ctx->ticket_base += (unsigned long long)ctx->nbrick;
-    const int32_t nitem = 2 * ctx->nbrick;
-    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<double, double>), dim3(nitem), dim3(isc::BRICK_THREADS), ISC_SWEEP_LDS,
-                       ctx->stream, ctx->items_bwd_spmv, nitem, nbx, nby, ctx->g.nx, ctx->g.ny, ctx->g.nz,
-                       ctx->row_ptr, ctx->diag_pos, A, Dinv, v, z, w, ctx->ticket, ctx->ticket_base,
-                       ctx->flags + ISC_FLAG_SWEEP);
-    ctx->ticket_base += (unsigned long long)nitem;
+    if (ctx->bpw == 2) {
+        launch_fwd_update<2>(ctx, lu, v, z, w);
+        launch_bwd_spmv<2, double, double>(ctx, A, Dinv, v, z, w);
+    } else {
+        launch_fwd_update<1>(ctx, lu, v, z, w);
+        launch_bwd_spmv<1, double, double>(ctx, A, Dinv, v, z, w);
+    }
     return hipGetLastError();
 }
 

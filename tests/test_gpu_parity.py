@@ -164,8 +164,9 @@ def test_preconditioner_and_spmv_match_oracle(name, seed):
     assert np.all(np.abs(w_f - w_o).max(axis=0) <= 1e-10 * np.abs(w_o).max(axis=0))
 
 
+@pytest.mark.parametrize("bpw", ["1", "2"])
 @pytest.mark.parametrize("name,seed", [("tiny:1x1x6", 40), ("tiny:13x7x5", 41), ("C1", 42)])
-def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, monkeypatch):
+def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, bpw, monkeypatch):
     """The single-launch triangular sweeps (rows wait for their predecessors'
     published values) and the one-launch-per-level sweeps do the same
     arithmetic in the same order, so their results agree bit for bit; several
@@ -173,9 +174,12 @@ def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, monkeypatch):
     ready for the next.  The backward sweep fused with the SpMV gives the same
     z; its w = A z adds the lower blocks' products to the upper ones the sweep
     already formed, so it agrees with the separate SpMV to rounding (and bit
-    for bit under level sweeps, which run the separate SpMV)."""
+    for bit under level sweeps, which run the separate SpMV).  Both workgroup
+    shapes are checked: one brick, and two independent bricks under one
+    ticket (what large grids use)."""
     wl, m, u, F, J = _decoupled_case(name, seed)
     st, Jd, Fd, _ = m.decouple(J, F)
+    monkeypatch.setenv("ISC_BRICKS_PER_WG", bpw)
     c_sf = ctx_for(wl)
     monkeypatch.setenv("ISC_LEVEL_SWEEPS", "1")
     c_lv = ctx_for(wl)
@@ -243,8 +247,9 @@ def test_solve_reaches_tolerance_and_matches_tight_oracle_solution(name, seed):
     assert np.all(err <= 1e-5 * ref.max()), err / ref.max()
 
 
-@pytest.mark.parametrize("name,seed,restart", [("tiny:13x7x5", 23, 30), ("C1", 24, 30), ("C1", 25, 10)])
-def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, restart, monkeypatch):
+@pytest.mark.parametrize("name,seed,restart,bpw", [("tiny:13x7x5", 23, 30, "1"), ("C1", 24, 30, "2"),
+                                                   ("C1", 25, 10, "1")])
+def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, restart, bpw, monkeypatch):
     """With sync-free sweeps the FP64 GMRES does each iteration's delayed
     Gram-Schmidt update inside the next iteration's forward sweep; with level
     sweeps it runs as a pass of its own.  The per-element arithmetic is the
@@ -255,6 +260,7 @@ def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, rest
     wl, m, u, F, J = _decoupled_case(name, seed)
     st, Jd, Fd, _ = m.decouple(J, F)
     b = dev(-Fd)
+    monkeypatch.setenv("ISC_BRICKS_PER_WG", bpw)
     c_sf = ctx_for(wl)
     monkeypatch.setenv("ISC_LEVEL_SWEEPS", "1")
     c_lv = ctx_for(wl)
