@@ -74,12 +74,12 @@ def algorithmic_bytes(n, nnzb):
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "bilu0_sweeps_200x200x50_fp64_traffic.md")
+TRAFFIC_PROFILE = os.path.join(HERE, "profiles", "bilu0_sweeps_200x200x50_traffic.md")
 
 
 def sweep_source_hash():
     h = hashlib.sha256()
-    for f in ("precond.hip", "common.h"):
+    for f in ("precond.hip", "common.h", "krylov.hip", "api.hip"):
         with open(os.path.join(HERE, "paper_1811_11992_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
