@@ -68,6 +68,9 @@ def algorithmic_bytes(n, nnzb):
         # Schmidt update folded into the forward sweep adds j + 2 vectors at
         # iteration j, counted per launch from the library's tally.
         "ilu_spmv": (off64 + n * 64 * 8 + 4 * vec64) + (off64 // 2 + 4 * vec64),
+        # the same in FP32 storage (the precision form's inner iteration; its
+        # Gram-Schmidt update stays a pass of its own)
+        "ilu_spmv32": ((off64 + n * 64 * 8 + 4 * vec64) + (off64 // 2 + 4 * vec64)) // 2,
         # u, u_old, porosity, 3 transmissibilities in; F and J out
         "assemble": 2 * vec64 + n * 8 * 4 + vec64 + nnzb * 64 * 8,
     }

@@ -574,6 +574,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
 // ---------------------------------------------------------------- precision form
 hipError_t isc_launch_bilu0_apply32(isc_ctx*, const float*, const float*, const float*, float*);
 hipError_t isc_launch_spmv32(isc_ctx*, const float*, const float*, float*);
+hipError_t isc_launch_bilu0_apply_spmv32(isc_ctx*, const float*, const float*, const float*, float*, float*);
 
 namespace isc {
 
@@ -608,14 +609,9 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
     hipLaunchKernelGGL(narrow_f32, dim3(nb), dim3(256), 0, ctx->stream, len, v, u);
     for (int j = 0; j <= m_in; ++j) {
         const bool last = j == m_in;
-        if (!last) {   // w = A M^-1 u_j in FP32 (separate kernels: here the fused one is slower,
-                       // 2.6 ms against 1.9 + 0.55 ms on 2M cells, its SpMV bricks find little
-                       // sweep latency to hide behind)
-            int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY32);
-            isc_launch_bilu0_apply32(ctx, A32, D32, u, ctx->t32);
-            isc_prof_end(ctx, tk);
-            tk = isc_prof_begin(ctx, ISC_PROF_SPMV32);
-            isc_launch_spmv32(ctx, A32, ctx->t32, ctx->w32);
+        if (!last) {   // w = A M^-1 u_j in FP32: forward sweep, backward sweep fused with the SpMV
+            const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_SPMV32);
+            isc_launch_bilu0_apply_spmv32(ctx, A32, D32, u, ctx->t32, ctx->w32);
             isc_prof_end(ctx, tk);
         }
         const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);

@@ -870,6 +870,10 @@ hipError_t isc_launch_bilu0_apply_spmv(isc_ctx* ctx, const double* A, const doub
 hipError_t isc_launch_spmv(isc_ctx* ctx, const double* A, const double* x, double* y) {
     return isc_launch_spmv_t<double, double>(ctx, A, x, y);
 }
+hipError_t isc_launch_bilu0_apply_spmv32(isc_ctx* ctx, const float* A, const float* Dinv, const float* r, float* z,
+                                         float* w) {
+    return isc_launch_bilu0_apply_spmv_t<float, float>(ctx, A, Dinv, r, z, w);
+}
 hipError_t isc_launch_spmv32(isc_ctx* ctx, const float* A, const float* x, float* y) {
     return isc_launch_spmv_t<float, float>(ctx, A, x, y);
 }
