@@ -350,8 +350,8 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->sweep32, (size_t)n * isc::NU);
     ALLOC(ctx->ticket, (size_t)1);
     ALLOC(ctx->well_off, (size_t)nwells + 1);
+    ALLOC(ctx->Z, nv * ctx->mmax);
     if (ctx->inner_max > 0) {
-        ALLOC(ctx->Z, nv * ctx->mmax);
         ALLOC(ctx->J32, (size_t)ctx->nnzb * isc::BS);
         ALLOC(ctx->Dinv32, (size_t)n * isc::BS);
         ALLOC(ctx->Lt32, (size_t)n * 3 * isc::BS);

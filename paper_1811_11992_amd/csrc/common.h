@@ -161,7 +161,7 @@ struct isc_ctx {
     // Krylov
     int32_t mmax = 30, inner_max = 0;
     double* V = nullptr;            // [(mmax+1)][N*8]
-    double* Z = nullptr;            // [mmax][N*8] (flexible variant)
+    double* Z = nullptr;            // [mmax][N*8] preconditioned lagged vectors z_j = P(u_j)
     double* w = nullptr;            // [N*8]
     double* tvec = nullptr;         // [N*8]
     double* tvec2 = nullptr;        // [N*8]

@@ -446,6 +446,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
     const int nb2 = nblocks(len2);
     Hess hs = hess_of(ctx);
     Dcgs dc = dcgs_at(ctx->small, ctx->mmax);
+    dc.Rs = ctx->small + RS_OFF;   // u_j = Q_j s_j + omega_j q_j, kept to form the solution from Z
     double* red = ctx->small + RED_OFF;
     double2* Q2 = reinterpret_cast<double2*>(ctx->V);
     double* u = ctx->V + (size_t)m * ldv;
@@ -496,14 +497,15 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
                                    red, dc.omz, u2, w2, (double*)nullptr);
                 isc_prof_end(ctx, tk);
             }
-            if (!last) {   // w = A M^-1 u_j
+            if (!last) {   // z_j = M^-1 u_j (kept in Z) and w = A z_j
                 const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_SPMV);
+                double* Zj = ctx->Z + (size_t)j * ldv;
                 if (fold) {
                     const LagUpdate lu{ctx->V, ldv, j - 1, red, red + MAXV, dc.omz, u, ctx->w};
-                    isc_launch_update_apply_spmv(ctx, A, Dinv, lu, ctx->tvec, ctx->w);
+                    isc_launch_update_apply_spmv(ctx, A, Dinv, lu, Zj, ctx->w);
                     isc_prof_vectors(ctx, ISC_PROF_ILU_SPMV, (double)(j + 2));
                 } else {
-                    isc_launch_bilu0_apply_spmv(ctx, A, Dinv, u, ctx->tvec, ctx->w);
+                    isc_launch_bilu0_apply_spmv(ctx, A, Dinv, u, Zj, ctx->w);
                 }
                 isc_prof_end(ctx, tk);
             }
@@ -540,15 +542,13 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
                 break;
             }
         }
-        // x += M^-1 (Q_k y)
+        // x += M^-1 Q_k y = Z_k (Rs^-1 y): the preconditioned lagged vectors are
+        // at hand, so no further BILU(0) apply
         if (k > 0) {
             hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hs, k);
-            hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V, ldv, k,
-                               hs.y, ctx->tvec2, 0);
-            const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY);
-            isc_launch_bilu0_apply(ctx, A, Dinv, ctx->tvec2, ctx->tvec);
-            isc_prof_end(ctx, tk);
-            hipLaunchKernelGGL(axpy_kernel, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->tvec, x);
+            hipLaunchKernelGGL(dcgs2_solve_rs, dim3(1), dim3(1), 0, ctx->stream, hs, dc, k);
+            hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->Z, ldv, k,
+                               hs.y, x, 1);
         }
     }
     if (st != ISC_OK) {
