@@ -276,11 +276,13 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         for (; next_spmv >= 0; --next_spmv) push_spmv(next_spmv);
     }
     {
-        // one atomic ticket per workgroup costs about 12 ns of serialised
-        // atomic throughput; pair bricks once those exceed a fraction of the
-        // wait chain (about 200 bricks per brick level)
+        // cooperative static schedule unless switched off (ISC_SWEEP_COOP=0);
+        // under tickets, one atomic per workgroup costs about 12 ns of
+        // serialised atomic throughput, so bricks are paired once those exceed
+        // a fraction of the wait chain (about 200 bricks per brick level)
+        if (const char* e = getenv("ISC_SWEEP_COOP")) ctx->coop = e[0] != '0';
         const int32_t nbl = nbx + nby + nbz - 2;
-        ctx->bpw = ctx->nbrick >= 200 * nbl ? 2 : 1;
+        ctx->bpw = (!ctx->coop && ctx->nbrick >= 200 * nbl) ? 2 : 1;
         if (const char* e = getenv("ISC_BRICKS_PER_WG")) ctx->bpw = e[0] == '2' ? 2 : 1;
     }
     ctx->nfwd_items = (int32_t)chf.size();

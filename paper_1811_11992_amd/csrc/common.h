@@ -138,10 +138,16 @@ struct isc_ctx {
     // inactive bricks to a multiple of MAX_BRICKS_PER_WG, so bricks sharing a
     // workgroup never wait for one another
     int32_t nfwd_items = 0, nbwd_items = 0, nfused_items = 0;
-    // bricks per sweep workgroup: 2 halves the ticket atomics, which bound the
-    // sweeps on large grids; 1 keeps bricks uncoupled where the chain of waits
-    // dominates (small grids)
+    // Sync-free sweeps run as cooperative launches with a static schedule (no
+    // ticket atomics); if a cooperative launch is refused they take tickets.
+    bool coop = true;
+    // bricks per sweep workgroup under tickets: 2 halves the ticket atomics,
+    // which bound the sweeps on large grids; 1 keeps bricks uncoupled where the
+    // chain of waits dominates (small grids), and always under the static
+    // schedule
     int32_t bpw = 1;
+    // co-resident workgroups per sweep kernel
+    std::vector<std::pair<const void*, int32_t>> grid_cache;
     int32_t* bricks_fwd = nullptr;
     int32_t* bricks_bwd = nullptr;
     int32_t* items_bwd_spmv = nullptr;   // [2 nbrick] backward bricks interleaved with SpMV bricks

@@ -339,6 +339,25 @@ __device__ __forceinline__ int32_t take_ticket(unsigned long long* ticket, unsig
     return s_t;
 }
 
+// The work groups of a launch: by ticket (any grid), or, under a cooperative
+// launch whose workgroups are all resident at once, statically: workgroup b
+// takes groups b, b + grid, ... in order.  The static order needs no atomic:
+// the lowest unfinished group's workgroup has finished all its earlier
+// groups, so it is working on that group, whose predecessors are all lower.
+template <bool STATIC, class Body>
+__device__ __forceinline__ void for_each_group(unsigned long long* ticket, unsigned long long base, int32_t n,
+                                               Body&& body) {
+    if constexpr (STATIC) {
+        for (int32_t k = (int32_t)blockIdx.x; k < n; k += (int32_t)gridDim.x) {
+            body(k);
+            __syncthreads();   // the next group reuses the LDS
+        }
+    } else {
+        const int32_t k = take_ticket(ticket, base, n);
+        if (k < n) body(k);
+    }
+}
+
 // Bricks: a workgroup owns a BRICK_X x BRICK_Y x BRICK_Z brick of cells
 // (thread = 8 * g + r, brick cell g = dx + BRICK_X (dy + BRICK_Y dz), block
 // row r; the eight rows of a cell share one wavefront).  A brick depends only
@@ -360,7 +379,10 @@ struct BrickCell {
 __device__ __forceinline__ BrickCell brick_cell(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny,
                                                 int32_t nz) {
     BrickCell bc;
-    const int tid = (int)(threadIdx.x % BRICK_THREADS);   // thread within the brick
+    // thread within the brick, behind an empty asm so that what derives from it
+    // is formed per brick rather than held in registers across a loop over bricks
+    int tid = (int)(threadIdx.x % BRICK_THREADS);
+    asm volatile("" : "+v"(tid));
     bc.g = tid >> 3;
     bc.r = tid & 7;
     const int32_t bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
@@ -624,42 +646,42 @@ __device__ __forceinline__ void spmv_lower_brick(int32_t b, int32_t nbx, int32_t
 }
 
 // One workgroup per brick; workgroups take tickets in brick-list order.
-template <class T, class TV, int BPW>
+template <class T, class TV, int BPW, bool STATIC>
 __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y, TV* __restrict__ z, TV* wreset,
     unsigned long long* ticket, unsigned long long base, int32_t* err) {
     __shared__ BrickLds L[BPW];
-    const int32_t k = take_ticket(ticket, base, ngroup);
-    if (k >= ngroup) return;
     const int h = (int)(threadIdx.x / BRICK_THREADS);
-    fwd_brick<T, TV>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, rin, y, z, wreset, err, L[h]);
+    for_each_group<STATIC>(ticket, base, ngroup, [&](int32_t k) {
+        fwd_brick<T, TV>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, rin, y, z, wreset, err, L[h]);
+    });
 }
 
 // forward sweep preceded, row by row, by the lagged Gram-Schmidt update (FP64)
-template <class T, int BPW>
+template <class T, int BPW, bool STATIC>
 __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_update_syncfree(
     const int32_t* __restrict__ bricks, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const T* __restrict__ Lt, LagUpdate lu, double* y, double* __restrict__ z, double* wreset,
     unsigned long long* ticket, unsigned long long base, int32_t* err) {
     __shared__ BrickLds L[BPW];
-    const int32_t k = take_ticket(ticket, base, ngroup);
-    if (k >= ngroup) return;
     const int h = (int)(threadIdx.x / BRICK_THREADS);
-    fwd_brick<T, double, true>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, wreset, err,
-                               L[h], lu);
+    for_each_group<STATIC>(ticket, base, ngroup, [&](int32_t k) {
+        fwd_brick<T, double, true>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, wreset, err,
+                                   L[h], lu);
+    });
 }
 
-template <class T, class TV, int BPW>
+template <class T, class TV, int BPW, bool STATIC>
 __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_bwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ y,
     TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
     __shared__ BrickLds L[BPW];
-    const int32_t k = take_ticket(ticket, base, ngroup);
-    if (k >= ngroup) return;
     const int h = (int)(threadIdx.x / BRICK_THREADS);
-    bwd_brick<T, TV>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, nullptr, err, L[h]);
+    for_each_group<STATIC>(ticket, base, ngroup, [&](int32_t k) {
+        bwd_brick<T, TV>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, nullptr, err, L[h]);
+    });
 }
 
 // Backward sweep and w = A z in one launch: the work list interleaves the
@@ -669,21 +691,21 @@ __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_bwd_syncfree(
 // of one workgroup come from one padded group, so they are all backward
 // bricks (same block barriers) or all SpMV bricks (none).
 constexpr int32_t SPMV_ITEM = 1 << 30;
-template <class T, class TV, int BPW>
+template <class T, class TV, int BPW, bool STATIC>
 __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_bwd_spmv_syncfree(
     const int32_t* __restrict__ items, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
     const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, TV* w, unsigned long long* ticket,
     unsigned long long base, int32_t* err) {
     __shared__ BrickLds L[BPW];
-    const int32_t k = take_ticket(ticket, base, ngroup);
-    if (k >= ngroup) return;
     const int h = (int)(threadIdx.x / BRICK_THREADS);
-    const int32_t it = items[k * BPW + h];
-    if (it & SPMV_ITEM)
-        spmv_lower_brick<T, TV>(it & (SPMV_ITEM - 1), nbx, nby, nx, ny, nz, row_ptr, A, z, w, err, L[h]);
-    else
-        bwd_brick<T, TV>(it, nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, w, err, L[h]);
+    for_each_group<STATIC>(ticket, base, ngroup, [&](int32_t k) {
+        const int32_t it = items[k * BPW + h];
+        if (it & SPMV_ITEM)
+            spmv_lower_brick<T, TV>(it & (SPMV_ITEM - 1), nbx, nby, nx, ny, nz, row_ptr, A, z, w, err, L[h]);
+        else
+            bwd_brick<T, TV>(it, nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, w, err, L[h]);
+    });
 }
 
 template <class U>
@@ -734,41 +756,79 @@ namespace {
 int32_t bricks_x(const isc_ctx* ctx) { return (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X; }
 int32_t bricks_y(const isc_ctx* ctx) { return (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y; }
 
+// Workgroups of `kernel` that fit on the device at once (cached per context).
+int32_t coresident(isc_ctx* ctx, const void* kernel, int threads) {
+    for (const auto& e : ctx->grid_cache)
+        if (e.first == kernel) return e.second;
+    int dev = 0, ncu = 0, per_cu = 0;
+    int32_t g = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, ISC_SWEEP_LDS) == hipSuccess)
+        g = ncu * per_cu;
+    (void)hipGetLastError();
+    ctx->grid_cache.emplace_back(kernel, g);
+    return g;
+}
+
+// One launch of a sync-free sweep kernel over `ngroup` workgroup-sized groups:
+// cooperative with a static schedule (grid = the co-resident workgroups, at
+// most ngroup) when the context uses it, else one workgroup per group taking
+// tickets.  The kernel's arguments after the group count are `args`; the
+// ticket pointer, its base and the error flag are appended here.
+template <class... Args>
+void launch_sweep(isc_ctx* ctx, const void* ticket_kernel, const void* static_kernel, int threads, int32_t ngroup,
+                  const int32_t* list, Args... args) {
+    unsigned long long* ticket = ctx->ticket;
+    unsigned long long base = ctx->ticket_base;
+    int32_t* err = ctx->flags + ISC_FLAG_SWEEP;
+    int32_t n = ngroup;
+    if (ctx->coop) {
+        const int32_t cap = coresident(ctx, static_kernel, threads);
+        if (cap > 0) {
+            const int32_t grid = cap < ngroup ? cap : (ngroup > 0 ? ngroup : 1);
+            void* argv[] = {(void*)&list, (void*)&n, (void*)&args..., (void*)&ticket, (void*)&base, (void*)&err};
+            if (hipLaunchCooperativeKernel(static_kernel, dim3(grid), dim3(threads), argv, ISC_SWEEP_LDS,
+                                           ctx->stream) == hipSuccess)
+                return;
+            (void)hipGetLastError();   // fall back to tickets
+        }
+    }
+    void* argv[] = {(void*)&list, (void*)&n, (void*)&args..., (void*)&ticket, (void*)&base, (void*)&err};
+    (void)hipLaunchKernel(ticket_kernel, dim3(ngroup), dim3(threads), argv, ISC_SWEEP_LDS, ctx->stream);
+    ctx->ticket_base += (unsigned long long)ngroup;
+}
+
 template <int BPW, class T, class TV>
 void launch_fwd(isc_ctx* ctx, const TV* r, TV* v, TV* z, TV* w) {
-    const int32_t nwg = ctx->nfwd_items / BPW;
-    hipLaunchKernelGGL((isc::bilu0_fwd_syncfree<T, TV, BPW>), dim3(nwg), dim3(isc::BRICK_THREADS * BPW),
-                       ISC_SWEEP_LDS, ctx->stream, ctx->bricks_fwd, nwg, bricks_x(ctx), bricks_y(ctx), ctx->g.nx,
-                       ctx->g.ny, ctx->g.nz, (const T*)isc::lt_buffer<T>(ctx), r, v, z, w, ctx->ticket,
-                       ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
-    ctx->ticket_base += (unsigned long long)nwg;
+    const T* Lt = isc::lt_buffer<T>(ctx);
+    launch_sweep(ctx, reinterpret_cast<const void*>(&isc::bilu0_fwd_syncfree<T, TV, BPW, false>),
+                 reinterpret_cast<const void*>(&isc::bilu0_fwd_syncfree<T, TV, BPW, true>),
+                 isc::BRICK_THREADS * BPW, ctx->nfwd_items / BPW, (const int32_t*)ctx->bricks_fwd, bricks_x(ctx),
+                 bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, Lt, r, v, z, w);
 }
 template <int BPW>
 void launch_fwd_update(isc_ctx* ctx, const isc::LagUpdate& lu, double* v, double* z, double* w) {
-    const int32_t nwg = ctx->nfwd_items / BPW;
-    hipLaunchKernelGGL((isc::bilu0_fwd_update_syncfree<double, BPW>), dim3(nwg), dim3(isc::BRICK_THREADS * BPW),
-                       ISC_SWEEP_LDS, ctx->stream, ctx->bricks_fwd, nwg, bricks_x(ctx), bricks_y(ctx), ctx->g.nx,
-                       ctx->g.ny, ctx->g.nz, (const double*)ctx->Lt, lu, v, z, w, ctx->ticket, ctx->ticket_base,
-                       ctx->flags + ISC_FLAG_SWEEP);
-    ctx->ticket_base += (unsigned long long)nwg;
+    const double* Lt = ctx->Lt;
+    launch_sweep(ctx, reinterpret_cast<const void*>(&isc::bilu0_fwd_update_syncfree<double, BPW, false>),
+                 reinterpret_cast<const void*>(&isc::bilu0_fwd_update_syncfree<double, BPW, true>),
+                 isc::BRICK_THREADS * BPW, ctx->nfwd_items / BPW, (const int32_t*)ctx->bricks_fwd, bricks_x(ctx),
+                 bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, Lt, lu, v, z, w);
 }
 template <int BPW, class T, class TV>
 void launch_bwd(isc_ctx* ctx, const T* A, const T* Dinv, TV* v, TV* z) {
-    const int32_t nwg = ctx->nbwd_items / BPW;
-    hipLaunchKernelGGL((isc::bilu0_bwd_syncfree<T, TV, BPW>), dim3(nwg), dim3(isc::BRICK_THREADS * BPW),
-                       ISC_SWEEP_LDS, ctx->stream, ctx->bricks_bwd, nwg, bricks_x(ctx), bricks_y(ctx), ctx->g.nx,
-                       ctx->g.ny, ctx->g.nz, ctx->diag_pos, A, Dinv, v, z, ctx->ticket, ctx->ticket_base,
-                       ctx->flags + ISC_FLAG_SWEEP);
-    ctx->ticket_base += (unsigned long long)nwg;
+    launch_sweep(ctx, reinterpret_cast<const void*>(&isc::bilu0_bwd_syncfree<T, TV, BPW, false>),
+                 reinterpret_cast<const void*>(&isc::bilu0_bwd_syncfree<T, TV, BPW, true>),
+                 isc::BRICK_THREADS * BPW, ctx->nbwd_items / BPW, (const int32_t*)ctx->bricks_bwd, bricks_x(ctx),
+                 bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, (const int32_t*)ctx->diag_pos, A, Dinv, v, z);
 }
 template <int BPW, class T, class TV>
 void launch_bwd_spmv(isc_ctx* ctx, const T* A, const T* Dinv, TV* v, TV* z, TV* w) {
-    const int32_t nwg = ctx->nfused_items / BPW;
-    hipLaunchKernelGGL((isc::bilu0_bwd_spmv_syncfree<T, TV, BPW>), dim3(nwg), dim3(isc::BRICK_THREADS * BPW),
-                       ISC_SWEEP_LDS, ctx->stream, ctx->items_bwd_spmv, nwg, bricks_x(ctx), bricks_y(ctx), ctx->g.nx,
-                       ctx->g.ny, ctx->g.nz, ctx->row_ptr, ctx->diag_pos, A, Dinv, v, z, w, ctx->ticket,
-                       ctx->ticket_base, ctx->flags + ISC_FLAG_SWEEP);
-    ctx->ticket_base += (unsigned long long)nwg;
+    launch_sweep(ctx, reinterpret_cast<const void*>(&isc::bilu0_bwd_spmv_syncfree<T, TV, BPW, false>),
+                 reinterpret_cast<const void*>(&isc::bilu0_bwd_spmv_syncfree<T, TV, BPW, true>),
+                 isc::BRICK_THREADS * BPW, ctx->nfused_items / BPW, (const int32_t*)ctx->items_bwd_spmv,
+                 bricks_x(ctx), bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, (const int32_t*)ctx->row_ptr,
+                 (const int32_t*)ctx->diag_pos, A, Dinv, v, z, w);
 }
 }  // namespace
 

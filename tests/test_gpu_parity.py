@@ -164,9 +164,9 @@ def test_preconditioner_and_spmv_match_oracle(name, seed):
     assert np.all(np.abs(w_f - w_o).max(axis=0) <= 1e-10 * np.abs(w_o).max(axis=0))
 
 
-@pytest.mark.parametrize("bpw", ["1", "2"])
+@pytest.mark.parametrize("coop,bpw", [("1", "1"), ("0", "1"), ("0", "2")])
 @pytest.mark.parametrize("name,seed", [("tiny:1x1x6", 40), ("tiny:13x7x5", 41), ("C1", 42)])
-def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, bpw, monkeypatch):
+def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, coop, bpw, monkeypatch):
     """The single-launch triangular sweeps (rows wait for their predecessors'
     published values) and the one-launch-per-level sweeps do the same
     arithmetic in the same order, so their results agree bit for bit; several
@@ -174,11 +174,12 @@ def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, bpw, monkeypatc
     ready for the next.  The backward sweep fused with the SpMV gives the same
     z; its w = A z adds the lower blocks' products to the upper ones the sweep
     already formed, so it agrees with the separate SpMV to rounding (and bit
-    for bit under level sweeps, which run the separate SpMV).  Both workgroup
-    shapes are checked: one brick, and two independent bricks under one
-    ticket (what large grids use)."""
+    for bit under level sweeps, which run the separate SpMV).  Each schedule
+    is checked: the cooperative static one (the default), and tickets with one
+    brick or with two independent bricks per workgroup."""
     wl, m, u, F, J = _decoupled_case(name, seed)
     st, Jd, Fd, _ = m.decouple(J, F)
+    monkeypatch.setenv("ISC_SWEEP_COOP", coop)
     monkeypatch.setenv("ISC_BRICKS_PER_WG", bpw)
     c_sf = ctx_for(wl)
     monkeypatch.setenv("ISC_LEVEL_SWEEPS", "1")
@@ -204,7 +205,8 @@ def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, bpw, monkeypatc
         assert torch.equal(c_lv.isc_bilu0_apply_spmv(Jdg, D, x)[1], w_ref)
 
 
-def test_sweep_wait_limit_ends_in_an_error_not_a_hang(monkeypatch):
+@pytest.mark.parametrize("coop", ["1", "0"])
+def test_sweep_wait_limit_ends_in_an_error_not_a_hang(coop, monkeypatch):
     """The sync-free sweeps bound every wait in wall-clock time.  With the
     limit forced down from the host to one tick, rows that have to wait for
     their predecessors give up, every wavefront still exits, and the apply
@@ -212,6 +214,7 @@ def test_sweep_wait_limit_ends_in_an_error_not_a_hang(monkeypatch):
     the same factor without error."""
     from paper_1811_11992_amd import isc
     wl = I.make_workload("tiny:60x60x20")
+    monkeypatch.setenv("ISC_SWEEP_COOP", coop)
     monkeypatch.setenv("ISC_SWEEP_WAIT_TICKS", "1")
     c_tiny = ctx_for(wl)
     monkeypatch.delenv("ISC_SWEEP_WAIT_TICKS")
@@ -247,9 +250,9 @@ def test_solve_reaches_tolerance_and_matches_tight_oracle_solution(name, seed):
     assert np.all(err <= 1e-5 * ref.max()), err / ref.max()
 
 
-@pytest.mark.parametrize("name,seed,restart,bpw", [("tiny:13x7x5", 23, 30, "1"), ("C1", 24, 30, "2"),
-                                                   ("C1", 25, 10, "1")])
-def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, restart, bpw, monkeypatch):
+@pytest.mark.parametrize("name,seed,restart,coop,bpw", [("tiny:13x7x5", 23, 30, "1", "1"),
+                                                        ("C1", 24, 30, "0", "2"), ("C1", 25, 10, "1", "1")])
+def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, restart, coop, bpw, monkeypatch):
     """With sync-free sweeps the FP64 GMRES does each iteration's delayed
     Gram-Schmidt update inside the next iteration's forward sweep; with level
     sweeps it runs as a pass of its own.  The per-element arithmetic is the
@@ -260,6 +263,7 @@ def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, rest
     wl, m, u, F, J = _decoupled_case(name, seed)
     st, Jd, Fd, _ = m.decouple(J, F)
     b = dev(-Fd)
+    monkeypatch.setenv("ISC_SWEEP_COOP", coop)
     monkeypatch.setenv("ISC_BRICKS_PER_WG", bpw)
     c_sf = ctx_for(wl)
     monkeypatch.setenv("ISC_LEVEL_SWEEPS", "1")
