@@ -68,8 +68,8 @@ def algorithmic_bytes(n, nnzb):
         # Schmidt update folded into the forward sweep adds j + 2 vectors at
         # iteration j, counted per launch from the library's tally.
         "ilu_spmv": (off64 + n * 64 * 8 + 4 * vec64) + (off64 // 2 + 4 * vec64),
-        # the same in FP32 storage (the precision form's inner iteration; its
-        # Gram-Schmidt update stays a pass of its own)
+        # the same in FP32 storage (the precision form's inner iteration, its
+        # folded Gram-Schmidt update counted like the FP64 one)
         "ilu_spmv32": ((off64 + n * 64 * 8 + 4 * vec64) + (off64 // 2 + 4 * vec64)) // 2,
         # u, u_old, porosity, 3 transmissibilities in; F and J out
         "assemble": 2 * vec64 + n * 8 * 4 + vec64 + nnzb * 64 * 8,
@@ -235,13 +235,14 @@ def adjoint_cost(name="C4", nsteps=20, every=5):
 
 def launch_bytes(nbytes, prof, vec, n):
     """Algorithmic bytes per launch of each class: the fixed pattern plus
-    the average number of extra full-length FP64 vectors per launch that the
-    library tallied (isc_profile_vectors)."""
+    the average number of extra full-length vectors per launch that the
+    library tallied (isc_profile_vectors), in the class's precision."""
     out = dict(nbytes)
     for k, v in vec.items():
         cnt = prof.get(k, (0, 0))[1]
         if k in out and cnt > 0 and v > 0:
-            out[k] = out[k] + int(round(v / cnt * n * 8 * 8))
+            elem = 4 if k.endswith("32") else 8
+            out[k] = out[k] + int(round(v / cnt * n * 8 * elem))
     return out
 
 

@@ -236,7 +236,8 @@ isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* coun
 /* Per class, the number of full-length vectors (n x 8 values in the class's
  * precision) that the profiled launches streamed on top of the class's fixed
  * access pattern, accumulated over the same window as isc_profile.  Nonzero
- * only for class 8: the FP64 GMRES folds the previous iteration's delayed
+ * only for classes 8 and 9: the GMRES iterations (FP64, and the FP32 inner
+ * one of the precision form) fold the previous iteration's delayed
  * Gram-Schmidt update into the forward sweep, which then reads j - 1 basis
  * vectors and w and writes q_{j-1} and u (j + 2 vectors at iteration j).
  * vec_h: host array of ISC_PROF_NCLASS.  ISC_ERR_ARG if it is NULL. */

@@ -30,21 +30,24 @@ constexpr int BRICK_THREADS = BRICK_X * BRICK_Y * BRICK_Z * 8;
 constexpr int MAX_BRICKS_PER_WG = 2;
 
 // The delayed Gram-Schmidt update of the previous GMRES iteration, done by
-// the forward sweep for its own rows before sweeping (FP64 solver):
+// the forward sweep for its own rows before sweeping:
 //   q_{j-1} = (u - sum_{k<j-1} s_k Q_k) / omega,
 //   u      <- (w - sum_{k<j-1} z_k Q_k - zeta q_{j-1}) / omega,
 // the new u being the sweep's right-hand side.  jq = j - 1 is the index of
-// the basis vector written; s, z: coefficients; omz = (omega, zeta).
-struct LagUpdate {
-    double* Q;
+// the basis vector written; s, z: coefficients; omz = (omega, zeta).  TV is
+// the storage of the basis and the vectors (the arithmetic is FP64).
+template <class TV>
+struct LagUpdateT {
+    TV* Q;
     int64_t ldv;
     int jq;
     const double* s;
     const double* z;
     const double* omz;
-    double* u;
-    const double* w;
+    TV* u;
+    const TV* w;
 };
+using LagUpdate = LagUpdateT<double>;
 // Per-cell property payload written by the property pass and read by the
 // face-flux assembly (doubles, value followed by the 8 partial derivatives):
 //   [0, 72)     local residual terms of the 8 rows (accumulation change,

@@ -575,6 +575,8 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
 hipError_t isc_launch_bilu0_apply32(isc_ctx*, const float*, const float*, const float*, float*);
 hipError_t isc_launch_spmv32(isc_ctx*, const float*, const float*, float*);
 hipError_t isc_launch_bilu0_apply_spmv32(isc_ctx*, const float*, const float*, const float*, float*, float*);
+hipError_t isc_launch_update_apply_spmv32(isc_ctx*, const float*, const float*, const isc::LagUpdateT<float>&, float*,
+                                          float*);
 
 namespace isc {
 
@@ -609,9 +611,24 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
     hipLaunchKernelGGL(narrow_f32, dim3(nb), dim3(256), 0, ctx->stream, len, v, u);
     for (int j = 0; j <= m_in; ++j) {
         const bool last = j == m_in;
+        // iteration j-1's Gram-Schmidt update (q_{j-1}, u_j): in this iteration's
+        // forward sweep where the sync-free sweeps run, else a pass of its own
+        const bool fold = j > 0 && !last && ctx->syncfree;
+        if (j > 0 && !fold) {
+            const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
+            hipLaunchKernelGGL(dcgs2_update<float2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, len2, j - 1,
+                               red, di.omz, u2, w2, (double*)nullptr);
+            isc_prof_end(ctx, tk);
+        }
         if (!last) {   // w = A M^-1 u_j in FP32: forward sweep, backward sweep fused with the SpMV
             const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_SPMV32);
-            isc_launch_bilu0_apply_spmv32(ctx, A32, D32, u, ctx->t32, ctx->w32);
+            if (fold) {
+                const LagUpdateT<float> lu{ctx->V32, len, j - 1, red, red + MAXV, di.omz, u, ctx->w32};
+                isc_launch_update_apply_spmv32(ctx, A32, D32, lu, ctx->t32, ctx->w32);
+                isc_prof_vectors(ctx, ISC_PROF_ILU_SPMV32, (double)(j + 2));
+            } else {
+                isc_launch_bilu0_apply_spmv32(ctx, A32, D32, u, ctx->t32, ctx->w32);
+            }
             isc_prof_end(ctx, tk);
         }
         const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
@@ -620,9 +637,6 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
         hipLaunchKernelGGL(reduce_rows_dcgs, dim3(last ? j + 1 : 2 * (j + 1)), dim3(256), 0, ctx->stream,
                            ctx->partial, nb2, j, red);
         hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hi, di, j, last ? 1 : 0, red);
-        if (!last)
-            hipLaunchKernelGGL(dcgs2_update<float2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, len2, j, red,
-                               di.omz, u2, w2, (double*)nullptr);
         isc_prof_end(ctx, tk);
     }
     hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hi, m_in);

@@ -430,7 +430,7 @@ template <class T, class TV, bool UPDATE = false>
 __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
                                           const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y,
                                           TV* __restrict__ z, TV* w, int32_t* err, BrickLds& L,
-                                          const LagUpdate& lu = LagUpdate{}) {
+                                          const LagUpdateT<TV>& lu = LagUpdateT<TV>{}) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
     const int r = bc.r;
     const bool act = bc.i >= 0;
@@ -454,14 +454,14 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     double rv;
     if constexpr (UPDATE) {
         const size_t e = (size_t)ii * NU + r;
-        const double uo = lu.u[e], wo = lu.w[e];
+        const double uo = (double)lu.u[e], wo = (double)lu.w[e];
         double sx = 0.0, zx = 0.0;
         // eight basis rows in flight at a time (the index is clamped so the
         // loads need no branch); summed in the order k = 0, 1, ...
         for (int k0 = 0; k0 < lu.jq; k0 += 8) {
             double q[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) q[t] = lu.Q[(size_t)min(k0 + t, lu.jq - 1) * lu.ldv + e];
+            for (int t = 0; t < 8; ++t) q[t] = (double)lu.Q[(size_t)min(k0 + t, lu.jq - 1) * lu.ldv + e];
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
                 if (k0 + t < lu.jq) {
@@ -474,10 +474,10 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
         const double qj = (uo - sx) * rom;
         const double un = (wo - zx - zeta * qj) * rom;
         if (act) {
-            lu.Q[(size_t)lu.jq * lu.ldv + e] = qj;
-            lu.u[e] = un;
+            lu.Q[(size_t)lu.jq * lu.ldv + e] = (TV)qj;
+            lu.u[e] = (TV)un;
         }
-        rv = act ? un : 0.0;
+        rv = act ? (double)(TV)un : 0.0;   // the stored u, as a separate update pass leaves it
     } else {
         rv = act ? (double)rin[(size_t)ii * NU + r] : 0.0;
     }
@@ -658,17 +658,17 @@ __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_syncfree(
     });
 }
 
-// forward sweep preceded, row by row, by the lagged Gram-Schmidt update (FP64)
-template <class T, int BPW, bool STATIC>
+// forward sweep preceded, row by row, by the lagged Gram-Schmidt update
+template <class T, class TV, int BPW, bool STATIC>
 __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_update_syncfree(
     const int32_t* __restrict__ bricks, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-    const T* __restrict__ Lt, LagUpdate lu, double* y, double* __restrict__ z, double* wreset,
+    const T* __restrict__ Lt, LagUpdateT<TV> lu, TV* y, TV* __restrict__ z, TV* wreset,
     unsigned long long* ticket, unsigned long long base, int32_t* err) {
     __shared__ BrickLds L[BPW];
     const int h = (int)(threadIdx.x / BRICK_THREADS);
     for_each_group<STATIC>(ticket, base, ngroup, [&](int32_t k) {
-        fwd_brick<T, double, true>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, wreset, err,
-                                   L[h], lu);
+        fwd_brick<T, TV, true>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, wreset, err, L[h],
+                               lu);
     });
 }
 
@@ -807,11 +807,11 @@ void launch_fwd(isc_ctx* ctx, const TV* r, TV* v, TV* z, TV* w) {
                  isc::BRICK_THREADS * BPW, ctx->nfwd_items / BPW, (const int32_t*)ctx->bricks_fwd, bricks_x(ctx),
                  bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, Lt, r, v, z, w);
 }
-template <int BPW>
-void launch_fwd_update(isc_ctx* ctx, const isc::LagUpdate& lu, double* v, double* z, double* w) {
-    const double* Lt = ctx->Lt;
-    launch_sweep(ctx, reinterpret_cast<const void*>(&isc::bilu0_fwd_update_syncfree<double, BPW, false>),
-                 reinterpret_cast<const void*>(&isc::bilu0_fwd_update_syncfree<double, BPW, true>),
+template <int BPW, class T>
+void launch_fwd_update(isc_ctx* ctx, const isc::LagUpdateT<T>& lu, T* v, T* z, T* w) {
+    const T* Lt = isc::lt_buffer<T>(ctx);
+    launch_sweep(ctx, reinterpret_cast<const void*>(&isc::bilu0_fwd_update_syncfree<T, T, BPW, false>),
+                 reinterpret_cast<const void*>(&isc::bilu0_fwd_update_syncfree<T, T, BPW, true>),
                  isc::BRICK_THREADS * BPW, ctx->nfwd_items / BPW, (const int32_t*)ctx->bricks_fwd, bricks_x(ctx),
                  bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, Lt, lu, v, z, w);
 }
@@ -881,20 +881,30 @@ hipError_t isc_launch_bilu0_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Dinv
     return hipGetLastError();
 }
 
-// The GMRES iteration of the FP64 solver with the previous iteration's
-// delayed Gram-Schmidt update folded into the forward sweep: writes Q_jq and
-// the new u, then z = M^-1 u and w = A z.  Sync-free sweeps only.
-hipError_t isc_launch_update_apply_spmv(isc_ctx* ctx, const double* A, const double* Dinv, const isc::LagUpdate& lu,
-                                        double* z, double* w) {
-    double* v = ctx->sweep64;
+// A GMRES iteration with the previous iteration's delayed Gram-Schmidt update
+// folded into the forward sweep: writes Q_jq and the new u, then z = M^-1 u
+// and w = A z (FP64, or FP32 storage for the inner solver).  Sync-free sweeps
+// only.
+template <class T>
+hipError_t isc_launch_update_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Dinv, const isc::LagUpdateT<T>& lu,
+                                          T* z, T* w) {
+    T* v = isc::sweep_buffer<T>(ctx);
     if (ctx->bpw == 2) {
-        launch_fwd_update<2>(ctx, lu, v, z, w);
-        launch_bwd_spmv<2, double, double>(ctx, A, Dinv, v, z, w);
+        launch_fwd_update<2, T>(ctx, lu, v, z, w);
+        launch_bwd_spmv<2, T, T>(ctx, A, Dinv, v, z, w);
     } else {
-        launch_fwd_update<1>(ctx, lu, v, z, w);
-        launch_bwd_spmv<1, double, double>(ctx, A, Dinv, v, z, w);
+        launch_fwd_update<1, T>(ctx, lu, v, z, w);
+        launch_bwd_spmv<1, T, T>(ctx, A, Dinv, v, z, w);
     }
     return hipGetLastError();
+}
+hipError_t isc_launch_update_apply_spmv(isc_ctx* ctx, const double* A, const double* Dinv, const isc::LagUpdate& lu,
+                                        double* z, double* w) {
+    return isc_launch_update_apply_spmv_t<double>(ctx, A, Dinv, lu, z, w);
+}
+hipError_t isc_launch_update_apply_spmv32(isc_ctx* ctx, const float* A, const float* Dinv,
+                                          const isc::LagUpdateT<float>& lu, float* z, float* w) {
+    return isc_launch_update_apply_spmv_t<float>(ctx, A, Dinv, lu, z, w);
 }
 
 template <class T, class TV>
