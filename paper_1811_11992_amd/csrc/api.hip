@@ -281,6 +281,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         // serialised atomic throughput, so bricks are paired once those exceed
         // a fraction of the wait chain (about 200 bricks per brick level)
         if (const char* e = getenv("ISC_SWEEP_COOP")) ctx->coop = e[0] != '0';
+        if (const char* e = getenv("ISC_FOLD_UPDATE")) ctx->fold_update = e[0] == '1';
         const int32_t nbl = nbx + nby + nbz - 2;
         ctx->bpw = (!ctx->coop && ctx->nbrick >= 200 * nbl) ? 2 : 1;
         if (const char* e = getenv("ISC_BRICKS_PER_WG")) ctx->bpw = e[0] == '2' ? 2 : 1;

@@ -144,6 +144,10 @@ struct isc_ctx {
     // Sync-free sweeps run as cooperative launches with a static schedule (no
     // ticket atomics); if a cooperative launch is refused they take tickets.
     bool coop = true;
+    // FP64 GMRES: fold the delayed Gram-Schmidt update into the forward sweep
+    // (off: a separate pass launched while the host reads the residual
+    // estimate, which measured faster under the static sweep schedule)
+    bool fold_update = false;
     // bricks per sweep workgroup under tickets: 2 halves the ticket atomics,
     // which bound the sweeps on large grids; 1 keeps bricks uncoupled where the
     // chain of waits dominates (small grids), and always under the static

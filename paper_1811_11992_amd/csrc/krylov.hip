@@ -485,13 +485,15 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
             inf.restarts = cyc;
         }
         int k = m;
+        // The Gram-Schmidt update of iteration j-1 (q_{j-1} and u_j) runs
+        // inside iteration j's forward sweep where the sync-free sweeps allow
+        // it (fold mode); otherwise as a pass of its own, launched while the
+        // host reads iteration j-1's residual estimate.
+        const bool fold_mode = ctx->syncfree && ctx->fold_update;
         for (int j = 0; j <= m; ++j) {
             const bool last = j == m;
-            // The Gram-Schmidt update left over from iteration j-1 (q_{j-1}
-            // and u_j) runs inside this iteration's forward sweep, where the
-            // sync-free sweep allows it; otherwise as a pass of its own.
-            const bool fold = j > 0 && !last && ctx->syncfree;
-            if (j > 0 && !fold) {
+            const bool fold = fold_mode && j > 0 && !last;
+            if (fold_mode && j > 0 && !fold) {
                 const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
                 hipLaunchKernelGGL(dcgs2_update<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j - 1,
                                    red, dc.omz, u2, w2, (double*)nullptr);
@@ -517,6 +519,9 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
             hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hs, dc, j, last ? 1 : 0, red);
             ISC_HIP(hipMemcpyAsync(ctx->hscratch, hs.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
             ISC_HIP(hipEventRecord(ev, ctx->stream));
+            if (!fold_mode && !last)   // speculative: unused if the estimate below ends the cycle
+                hipLaunchKernelGGL(dcgs2_update<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j,
+                                   red, dc.omz, u2, w2, (double*)nullptr);
             isc_prof_end(ctx, tk);
             ISC_HIP(hipEventSynchronize(ev));
             const double est = ctx->hscratch[2];

@@ -250,12 +250,15 @@ def test_solve_reaches_tolerance_and_matches_tight_oracle_solution(name, seed):
     assert np.all(err <= 1e-5 * ref.max()), err / ref.max()
 
 
-@pytest.mark.parametrize("name,seed,restart,coop,bpw", [("tiny:13x7x5", 23, 30, "1", "1"),
-                                                        ("C1", 24, 30, "0", "2"), ("C1", 25, 10, "1", "1")])
-def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, restart, coop, bpw, monkeypatch):
-    """With sync-free sweeps the FP64 GMRES does each iteration's delayed
-    Gram-Schmidt update inside the next iteration's forward sweep; with level
-    sweeps it runs as a pass of its own.  The per-element arithmetic is the
+@pytest.mark.parametrize("name,seed,restart,coop,bpw,fold", [("tiny:13x7x5", 23, 30, "1", "1", "1"),
+                                                             ("C1", 24, 30, "0", "2", "1"),
+                                                             ("C1", 25, 10, "1", "1", "1"),
+                                                             ("C1", 26, 10, "1", "1", "0")])
+def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, restart, coop, bpw, fold, monkeypatch):
+    """With sync-free sweeps the FP64 GMRES can do each iteration's delayed
+    Gram-Schmidt update inside the next iteration's forward sweep
+    (ISC_FOLD_UPDATE=1); by default, and with level sweeps, it runs as a pass
+    of its own.  The per-element arithmetic is the
     same, so both reach the tolerance after the same number of iterations and
     give the same solution to rounding, also across many restarts (GMRES(10)
     needs about 25 cycles on the C1 case, as does the oracle's GMRES)."""
@@ -265,6 +268,7 @@ def test_solve_with_update_in_the_sweep_matches_separate_update(name, seed, rest
     b = dev(-Fd)
     monkeypatch.setenv("ISC_SWEEP_COOP", coop)
     monkeypatch.setenv("ISC_BRICKS_PER_WG", bpw)
+    monkeypatch.setenv("ISC_FOLD_UPDATE", fold)
     c_sf = ctx_for(wl)
     monkeypatch.setenv("ISC_LEVEL_SWEEPS", "1")
     c_lv = ctx_for(wl)
