@@ -287,6 +287,19 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         if (const char* e = getenv("ISC_BRICKS_PER_WG")) ctx->bpw = e[0] == '2' ? 2 : 1;
     }
     ctx->nfwd_items = (int32_t)chf.size();
+    // slot of each cell's L D^-1 blocks: its brick's position in the forward list
+    std::vector<int32_t> lt_slot(n);
+    {
+        std::vector<int32_t> pos((size_t)ctx->nbrick, 0);
+        for (size_t k = 0; k < chf.size(); ++k)
+            if (chf[k] < ctx->nbrick) pos[chf[k]] = (int32_t)k;
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+            const int32_t b = ix / isc::BRICK_X + nbx * (iy / isc::BRICK_Y + nby * (iz / isc::BRICK_Z));
+            const int32_t g = ix % isc::BRICK_X + isc::BRICK_X * (iy % isc::BRICK_Y + isc::BRICK_Y * (iz % isc::BRICK_Z));
+            lt_slot[i] = pos[b] * (isc::BRICK_X * isc::BRICK_Y * isc::BRICK_Z) + g;
+        }
+    }
     ctx->nbwd_items = (int32_t)chb.size();
     ctx->nfused_items = (int32_t)items.size();
     if (const char* e = getenv("ISC_LEVEL_SWEEPS")) ctx->syncfree = !(e[0] == '1');
@@ -349,7 +362,9 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->bricks_bwd, chb.size());
     ALLOC(ctx->items_bwd_spmv, items.size());
     ALLOC(ctx->sweep64, (size_t)n * isc::NU);
-    ALLOC(ctx->Lt, (size_t)n * 3 * isc::BS);
+    const size_t lt_cells = (size_t)ctx->nfwd_items * isc::BRICK_X * isc::BRICK_Y * isc::BRICK_Z;
+    ALLOC(ctx->Lt, lt_cells * 3 * isc::BS);
+    ALLOC(ctx->lt_slot, (size_t)n);
     ALLOC(ctx->sweep32, (size_t)n * isc::NU);
     ALLOC(ctx->ticket, (size_t)1);
     ALLOC(ctx->well_off, (size_t)nwells + 1);
@@ -357,7 +372,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     if (ctx->inner_max > 0) {
         ALLOC(ctx->J32, (size_t)ctx->nnzb * isc::BS);
         ALLOC(ctx->Dinv32, (size_t)n * isc::BS);
-        ALLOC(ctx->Lt32, (size_t)n * 3 * isc::BS);
+        ALLOC(ctx->Lt32, lt_cells * 3 * isc::BS);
         ALLOC(ctx->V32, nv * (ctx->inner_max + 1));
         ALLOC(ctx->w32, nv);
         ALLOC(ctx->t32, nv);
@@ -407,7 +422,8 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         !h2d(ctx->row_ptr, ctx->row_ptr_h.data(), ((size_t)n + 1) * sizeof(int32_t)) ||
         !h2d(ctx->col_idx, ctx->col_idx_h.data(), (size_t)ctx->nnzb * sizeof(int32_t)) ||
         !h2d(ctx->diag_pos, ctx->diag_pos_h.data(), (size_t)n * sizeof(int32_t)) ||
-        !h2d(ctx->lvl_rows, lvl_rows.data(), (size_t)n * sizeof(int32_t))) {
+        !h2d(ctx->lvl_rows, lvl_rows.data(), (size_t)n * sizeof(int32_t)) ||
+        !h2d(ctx->lt_slot, lt_slot.data(), (size_t)n * sizeof(int32_t))) {
         ctx->err = "host to device copy failed";
         return fail(ISC_ERR_HIP);
     }
@@ -437,7 +453,7 @@ isc_status isc_destroy(isc_ctx* ctx) {
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     else hipDeviceSynchronize();
     void* ptrs[] = {ctx->fluid_d, ctx->logk,  ctx->poro,    ctx->trans,  ctx->row_ptr, ctx->col_idx,
-                    ctx->diag_pos, ctx->well_slot, ctx->perf, ctx->lvl_rows, ctx->payload, ctx->F,
+                    ctx->diag_pos, ctx->well_slot, ctx->perf, ctx->lvl_rows, ctx->lt_slot, ctx->payload, ctx->F,
                     ctx->J,       ctx->Dinv,  ctx->du,      ctx->rhs,    ctx->V,       ctx->Z,
                     ctx->w,       ctx->tvec,  ctx->tvec2,   ctx->partial, ctx->small,  ctx->flags,
                     ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,     ctx->t32b,

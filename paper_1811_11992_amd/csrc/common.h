@@ -141,6 +141,10 @@ struct isc_ctx {
     // inactive bricks to a multiple of MAX_BRICKS_PER_WG, so bricks sharing a
     // workgroup never wait for one another
     int32_t nfwd_items = 0, nbwd_items = 0, nfused_items = 0;
+    // L D^-1 blocks are stored in forward-sweep order: cell i's three blocks
+    // sit at slot lt_slot[i] = (position of its brick in the forward list) x
+    // brick cells + its index in the brick, so the sweep streams them
+    int32_t* lt_slot = nullptr;
     // Sync-free sweeps run as cooperative launches with a static schedule (no
     // ticket atomics); if a cooperative launch is refused they take tickets.
     bool coop = true;

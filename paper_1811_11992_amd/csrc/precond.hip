@@ -40,7 +40,7 @@ template <class T>
 __global__ void __launch_bounds__(256) bilu0_factor_level(
     const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-    T* __restrict__ Dinv, T* __restrict__ Lt, int32_t* __restrict__ bad) {
+    T* __restrict__ Dinv, T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, int32_t* __restrict__ bad) {
     __shared__ double sm[4][4][64];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) bilu0_factor_level(
 #pragma unroll
         for (int j = 0; j < 8; ++j) p += sA[r * 8 + j] * sK[j * 8 + c];
         sP[lane] = p;
-        Lt[((size_t)i * 3 + q) * BS + lane] = (T)p;
+        Lt[((size_t)lt_slot[i] * 3 + q) * BS + lane] = (T)p;
         __builtin_amdgcn_wave_barrier();
         double q2 = 0.0;
 #pragma unroll
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(256) bilu0_factor_level(
 template <class T>
 __global__ void __launch_bounds__(256) form_ltilde(int32_t n, int32_t nx, int32_t ny, const int32_t* __restrict__ row_ptr,
                                                    const T* __restrict__ A, const T* __restrict__ Dinv,
-                                                   T* __restrict__ Lt) {
+                                                   T* __restrict__ Lt, const int32_t* __restrict__ lt_slot) {
     __shared__ double sm[4][2][64];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
@@ -150,7 +150,7 @@ __global__ void __launch_bounds__(256) form_ltilde(int32_t n, int32_t nx, int32_
         double p = 0.0;
 #pragma unroll
         for (int j = 0; j < 8; ++j) p += sA[r * 8 + j] * sK[j * 8 + c];
-        Lt[((size_t)i * 3 + q) * BS + lane] = (T)p;
+        Lt[((size_t)lt_slot[i] * 3 + q) * BS + lane] = (T)p;
         __builtin_amdgcn_wave_barrier();
     }
 }
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256) form_ltilde(int32_t n, int32_t nx, int32_
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_fwd_level(
     const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, const T* __restrict__ Lt,
-    const TV* rin, TV* y) {
+    const int32_t* __restrict__ lt_slot, const TV* rin, TV* y) {
     const int32_t t = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
     const int r = threadIdx.x & 7;
     if (t >= cnt) return;
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(256) bilu0_fwd_level(
     for (int q = 0; q < 3; ++q) {
         const int32_t k = lower[q];
         if (k < 0) continue;
-        const T* a = Lt + ((size_t)i * 3 + q) * BS + r * 8;
+        const T* a = Lt + ((size_t)lt_slot[i] * 3 + q) * BS + r * 8;
         const TV* x = y + (size_t)k * NU;
 #pragma unroll
         for (int c = 0; c < 8; ++c) acc -= (double)a[c] * (double)x[c];
@@ -422,13 +422,14 @@ __device__ __forceinline__ void lds_row8(const double* x, double* out8) {
     }
 }
 
-// forward: y_i = r_i - sum_{k lower} Lt_ik y_k; y is the private buffer
-// (sentinel on entry), z_i is reset to the sentinel for the backward sweep,
-// and so is w_i when w is given (the fused SpMV's partial sums are
-// published there)
+// forward: y_i = r_i - sum_{k lower} Lt_ik y_k for brick b, the entry at
+// position pos of the forward list (its L D^-1 blocks are stored there); y is
+// the private buffer (sentinel on entry), z_i is reset to the sentinel for the
+// backward sweep, and so is w_i when w is given (the fused SpMV's partial sums
+// are published there)
 template <class T, class TV, bool UPDATE = false>
-__device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-                                          const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y,
+__device__ __forceinline__ void fwd_brick(int32_t pos, int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny,
+                                          int32_t nz, const T* __restrict__ Lt, const TV* __restrict__ rin, TV* y,
                                           TV* __restrict__ z, TV* w, int32_t* err, BrickLds& L,
                                           const LagUpdateT<TV>& lu = LagUpdateT<TV>{}) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
@@ -447,7 +448,7 @@ __device__ __forceinline__ void fwd_brick(int32_t b, int32_t nbx, int32_t nby, i
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         double x[8];
-        row8(Lt + ((size_t)ii * 3 + q) * BS + r * 8, x);
+        row8(Lt + (((size_t)pos * BRICK_CELLS + bc.g) * 3 + q) * BS + r * 8, x);
 #pragma unroll
         for (int c = 0; c < 8; ++c) arow[q][c] = lower[q] >= 0 ? x[c] : 0.0;
     }
@@ -654,7 +655,7 @@ __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_syncfree(
     __shared__ BrickLds L[BPW];
     const int h = (int)(threadIdx.x / BRICK_THREADS);
     for_each_group<STATIC>(ticket, base, ngroup, [&](int32_t k) {
-        fwd_brick<T, TV>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, rin, y, z, wreset, err, L[h]);
+        fwd_brick<T, TV>(k * BPW + h, bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, rin, y, z, wreset, err, L[h]);
     });
 }
 
@@ -667,8 +668,8 @@ __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_update_syncfree
     __shared__ BrickLds L[BPW];
     const int h = (int)(threadIdx.x / BRICK_THREADS);
     for_each_group<STATIC>(ticket, base, ngroup, [&](int32_t k) {
-        fwd_brick<T, TV, true>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, wreset, err, L[h],
-                               lu);
+        fwd_brick<T, TV, true>(k * BPW + h, bricks[k * BPW + h], nbx, nby, nx, ny, nz, Lt, nullptr, y, z, wreset,
+                               err, L[h], lu);
     });
 }
 
@@ -745,7 +746,7 @@ hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t*
         const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
         hipLaunchKernelGGL(isc::bilu0_factor_level<T>, dim3((cnt + 3) / 4), dim3(256), 0, ctx->stream,
                            ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
-                           ctx->diag_pos, A, Dinv, isc::lt_buffer<T>(ctx), bad_dev);
+                           ctx->diag_pos, A, Dinv, isc::lt_buffer<T>(ctx), ctx->lt_slot, bad_dev);
     }
     return hipGetLastError();
 }
@@ -848,7 +849,8 @@ hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, con
     for (int32_t s = 0; s < ctx->nlev; ++s) {
         const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
         hipLaunchKernelGGL((isc::bilu0_fwd_level<T, TV>), dim3((cnt + 31) / 32), dim3(256), 0, ctx->stream,
-                           ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, (const T*)isc::lt_buffer<T>(ctx), r, z);
+                           ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, (const T*)isc::lt_buffer<T>(ctx),
+                           (const int32_t*)ctx->lt_slot, r, z);
     }
     for (int32_t s = ctx->nlev - 1; s >= 0; --s) {
         const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
@@ -924,7 +926,7 @@ hipError_t isc_launch_bilu0_factor32(isc_ctx* ctx, const float* A, float* Dinv, 
 // Lt of the context from a factor computed elsewhere (FP64).
 hipError_t isc_launch_form_ltilde(isc_ctx* ctx, const double* A, const double* Dinv) {
     hipLaunchKernelGGL(isc::form_ltilde<double>, dim3((ctx->n + 3) / 4), dim3(256), 0, ctx->stream, ctx->n,
-                       ctx->g.nx, ctx->g.ny, ctx->row_ptr, A, Dinv, ctx->Lt);
+                       ctx->g.nx, ctx->g.ny, ctx->row_ptr, A, Dinv, ctx->Lt, (const int32_t*)ctx->lt_slot);
     return hipGetLastError();
 }
 hipError_t isc_launch_bilu0_apply(isc_ctx* ctx, const double* A, const double* Dinv, const double* r, double* z) {
