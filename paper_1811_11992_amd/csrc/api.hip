@@ -239,7 +239,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     const int32_t nbx = (nx + isc::BRICK_X - 1) / isc::BRICK_X, nby = (ny + isc::BRICK_Y - 1) / isc::BRICK_Y,
                   nbz = (nz + isc::BRICK_Z - 1) / isc::BRICK_Z;
     ctx->nbrick = nbx * nby * nbz;
-    std::vector<int32_t> chf, chb, items;
+    std::vector<int32_t> chf, chb, items, items_rank;
     {
         const int32_t nbl = nbx + nby + nbz - 2;
         const int32_t dummy = ctx->nbrick;   // past the last brick layer: every cell inactive
@@ -263,17 +263,31 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         // L + ISC_SPMV_LAG .. L + 2 + ISC_SPMV_LAG, all swept before them); the lag
         // keeps SpMV bricks from waiting on the sweep front
         items.reserve((size_t)2 * ctx->nbrick + 2 * nbl * isc::MAX_BRICKS_PER_WG);
-        auto push_spmv = [&](int32_t L) {
-            for (auto it = by_level[L].rbegin(); it != by_level[L].rend(); ++it) items.push_back(*it | (1 << 30));
-            pad(items, dummy | (1 << 30));
+        // Each item also records its rank: the position of its brick in the
+        // backward list, where the brick's backward and SpMV data are stored
+        // (both kinds of groups come in the backward list's order and padding).
+        int32_t rank_b = 0, rank_s = 0;
+        auto push_group = [&](int32_t L, int32_t flag, int32_t& rank) {
+            for (auto it = by_level[L].rbegin(); it != by_level[L].rend(); ++it) {
+                items.push_back(*it | flag);
+                items_rank.push_back(rank++);
+            }
+            while (items.size() % isc::MAX_BRICKS_PER_WG) {
+                items.push_back(dummy | flag);
+                items_rank.push_back(rank++);
+            }
         };
         int32_t next_spmv = nbl - 1;   // highest level whose SpMV bricks are not listed yet
         for (int32_t L = nbl - 1; L >= 0; --L) {
-            items.insert(items.end(), by_level[L].rbegin(), by_level[L].rend());
-            pad(items, dummy);
-            for (; next_spmv >= 0 && next_spmv >= L + 1 + ISC_SPMV_LAG; --next_spmv) push_spmv(next_spmv);
+            push_group(L, 0, rank_b);
+            for (; next_spmv >= 0 && next_spmv >= L + 1 + ISC_SPMV_LAG; --next_spmv)
+                push_group(next_spmv, 1 << 30, rank_s);
         }
-        for (; next_spmv >= 0; --next_spmv) push_spmv(next_spmv);
+        for (; next_spmv >= 0; --next_spmv) push_group(next_spmv, 1 << 30, rank_s);
+        if (rank_b != (int32_t)chb.size() || rank_s != (int32_t)chb.size()) {
+            ctx->err = "internal: fused work list out of step with the backward list";
+            return fail(ISC_ERR_ARG);
+        }
     }
     {
         // cooperative static schedule unless switched off (ISC_SWEEP_COOP=0);
@@ -287,17 +301,21 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         if (const char* e = getenv("ISC_BRICKS_PER_WG")) ctx->bpw = e[0] == '2' ? 2 : 1;
     }
     ctx->nfwd_items = (int32_t)chf.size();
-    // slot of each cell's L D^-1 blocks: its brick's position in the forward list
-    std::vector<int32_t> lt_slot(n);
+    // slot of each cell's L D^-1 blocks: its brick's position in the forward
+    // list; slot of its backward and SpMV data: the position in the backward list
+    std::vector<int32_t> lt_slot(n), b_slot(n);
     {
-        std::vector<int32_t> pos((size_t)ctx->nbrick, 0);
+        std::vector<int32_t> pos((size_t)ctx->nbrick, 0), posb((size_t)ctx->nbrick, 0);
         for (size_t k = 0; k < chf.size(); ++k)
             if (chf[k] < ctx->nbrick) pos[chf[k]] = (int32_t)k;
+        for (size_t k = 0; k < chb.size(); ++k)
+            if (chb[k] < ctx->nbrick) posb[chb[k]] = (int32_t)k;
         for (int32_t i = 0; i < n; ++i) {
             const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
             const int32_t b = ix / isc::BRICK_X + nbx * (iy / isc::BRICK_Y + nby * (iz / isc::BRICK_Z));
             const int32_t g = ix % isc::BRICK_X + isc::BRICK_X * (iy % isc::BRICK_Y + isc::BRICK_Y * (iz % isc::BRICK_Z));
             lt_slot[i] = pos[b] * (isc::BRICK_X * isc::BRICK_Y * isc::BRICK_Z) + g;
+            b_slot[i] = posb[b] * (isc::BRICK_X * isc::BRICK_Y * isc::BRICK_Z) + g;
         }
     }
     ctx->nbwd_items = (int32_t)chb.size();
@@ -365,6 +383,11 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     const size_t lt_cells = (size_t)ctx->nfwd_items * isc::BRICK_X * isc::BRICK_Y * isc::BRICK_Z;
     ALLOC(ctx->Lt, lt_cells * 3 * isc::BS);
     ALLOC(ctx->lt_slot, (size_t)n);
+    ALLOC(ctx->b_slot, (size_t)n);
+    ALLOC(ctx->items_rank, items_rank.size());
+    const size_t b_cells = (size_t)ctx->nbwd_items * isc::BRICK_X * isc::BRICK_Y * isc::BRICK_Z;
+    ALLOC(ctx->bpack64, b_cells * 4 * isc::BS);
+    ALLOC(ctx->spack64, b_cells * 3 * isc::BS);
     ALLOC(ctx->sweep32, (size_t)n * isc::NU);
     ALLOC(ctx->ticket, (size_t)1);
     ALLOC(ctx->well_off, (size_t)nwells + 1);
@@ -373,6 +396,8 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         ALLOC(ctx->J32, (size_t)ctx->nnzb * isc::BS);
         ALLOC(ctx->Dinv32, (size_t)n * isc::BS);
         ALLOC(ctx->Lt32, lt_cells * 3 * isc::BS);
+        ALLOC(ctx->bpack32, b_cells * 4 * isc::BS);
+        ALLOC(ctx->spack32, b_cells * 3 * isc::BS);
         ALLOC(ctx->V32, nv * (ctx->inner_max + 1));
         ALLOC(ctx->w32, nv);
         ALLOC(ctx->t32, nv);
@@ -423,7 +448,9 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         !h2d(ctx->col_idx, ctx->col_idx_h.data(), (size_t)ctx->nnzb * sizeof(int32_t)) ||
         !h2d(ctx->diag_pos, ctx->diag_pos_h.data(), (size_t)n * sizeof(int32_t)) ||
         !h2d(ctx->lvl_rows, lvl_rows.data(), (size_t)n * sizeof(int32_t)) ||
-        !h2d(ctx->lt_slot, lt_slot.data(), (size_t)n * sizeof(int32_t))) {
+        !h2d(ctx->lt_slot, lt_slot.data(), (size_t)n * sizeof(int32_t)) ||
+        !h2d(ctx->b_slot, b_slot.data(), (size_t)n * sizeof(int32_t)) ||
+        !h2d(ctx->items_rank, items_rank.data(), items_rank.size() * sizeof(int32_t))) {
         ctx->err = "host to device copy failed";
         return fail(ISC_ERR_HIP);
     }
@@ -453,7 +480,8 @@ isc_status isc_destroy(isc_ctx* ctx) {
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     else hipDeviceSynchronize();
     void* ptrs[] = {ctx->fluid_d, ctx->logk,  ctx->poro,    ctx->trans,  ctx->row_ptr, ctx->col_idx,
-                    ctx->diag_pos, ctx->well_slot, ctx->perf, ctx->lvl_rows, ctx->lt_slot, ctx->payload, ctx->F,
+                    ctx->diag_pos, ctx->well_slot, ctx->perf, ctx->lvl_rows, ctx->lt_slot, ctx->b_slot, ctx->items_rank,
+                    ctx->bpack64, ctx->spack64, ctx->bpack32, ctx->spack32, ctx->payload, ctx->F,
                     ctx->J,       ctx->Dinv,  ctx->du,      ctx->rhs,    ctx->V,       ctx->Z,
                     ctx->w,       ctx->tvec,  ctx->tvec2,   ctx->partial, ctx->small,  ctx->flags,
                     ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,     ctx->t32b,

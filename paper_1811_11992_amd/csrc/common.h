@@ -145,6 +145,17 @@ struct isc_ctx {
     // sit at slot lt_slot[i] = (position of its brick in the forward list) x
     // brick cells + its index in the brick, so the sweep streams them
     int32_t* lt_slot = nullptr;
+    // The backward sweep's blocks (U x+, U y+, U z+, D^-1) and the SpMV's lower
+    // blocks (z-, y-, x-) are copied, when the factor is formed, into packs in
+    // backward-list order: cell i at slot b_slot[i] (its brick's position in
+    // the backward list x brick cells + its index in the brick).  items_rank
+    // gives each fused work item that position.
+    int32_t* b_slot = nullptr;
+    int32_t* items_rank = nullptr;
+    double* bpack64 = nullptr;   // [slots][4][64]
+    double* spack64 = nullptr;   // [slots][3][64]
+    float* bpack32 = nullptr;
+    float* spack32 = nullptr;
     // Sync-free sweeps run as cooperative launches with a static schedule (no
     // ticket atomics); if a cooperative launch is refused they take tickets.
     bool coop = true;

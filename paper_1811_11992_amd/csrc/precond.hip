@@ -155,6 +155,41 @@ __global__ void __launch_bounds__(256) form_ltilde(int32_t n, int32_t nx, int32_
     }
 }
 
+// The backward sweep's and the SpMV's blocks of each cell, copied into the
+// packs at the cell's backward-list slot: U x+, U y+, U z+, D^-1 into the
+// backward pack, the lower blocks z-, y-, x- into the SpMV pack (a missing
+// neighbour's slot is left as it is; the sweeps mask it).  One wavefront per
+// cell, one lane per block entry.
+template <class T>
+__global__ void __launch_bounds__(256) form_packs(int32_t n, int32_t nx, int32_t ny, int32_t nz,
+                                                  const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
+                                                  const T* __restrict__ Dinv, const int32_t* __restrict__ b_slot,
+                                                  T* __restrict__ bpack, T* __restrict__ spack) {
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int32_t i = (int32_t)blockIdx.x * 4 + w;
+    if (i >= n) return;
+    const int32_t nxy = nx * ny;
+    const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    const size_t s = (size_t)b_slot[i];
+    const bool up[3] = {ix + 1 < nx, iy + 1 < ny, iz + 1 < nz};
+    int32_t blk = diag_pos[i] + 1;
+    for (int q = 0; q < 3; ++q) {
+        if (!up[q]) continue;
+        bpack[(s * 4 + q) * BS + lane] = A[(size_t)blk * BS + lane];
+        ++blk;
+    }
+    bpack[(s * 4 + 3) * BS + lane] = Dinv[(size_t)i * BS + lane];
+    const bool lo[3] = {iz > 0, iy > 0, ix > 0};
+    blk = row_ptr[i];
+    for (int q = 0; q < 3; ++q) {
+        if (!lo[q]) continue;
+        spack[(s * 3 + q) * BS + lane] = A[(size_t)blk * BS + lane];
+        ++blk;
+    }
+}
+
 // Forward sweep of one level: y_i = r_i - sum_{k lower} Lt_ik y_k.
 template <class T, class TV>
 __global__ void __launch_bounds__(256) bilu0_fwd_level(
@@ -520,11 +555,12 @@ __device__ __forceinline__ void fwd_brick(int32_t pos, int32_t b, int32_t nbx, i
 // entry, y_i is reset to the sentinel for the next forward sweep.  With w
 // given (sentinel on entry), also publishes w_i = z_i + sum_{j upper} A_ij z_j,
 // the part of (A z)_i that the sweep has in hand (the diagonal block of the
-// decoupled matrix is the identity); the SpMV bricks add the lower part.
+// decoupled matrix is the identity); the SpMV bricks add the lower part.  The
+// blocks U x+, U y+, U z+ and D^-1 of the brick's cells come from the backward
+// pack, at the brick's position in the backward list (rank).
 template <class T, class TV>
-__device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-                                          const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-                                          const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, TV* w,
+__device__ __forceinline__ void bwd_brick(int32_t rank, int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny,
+                                          int32_t nz, const T* __restrict__ bpack, TV* __restrict__ y, TV* z, TV* w,
                                           int32_t* err, BrickLds& L) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
     const int r = bc.r;
@@ -535,19 +571,18 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
     const int32_t upper[3] = {ix + 1 < nx ? ii + 1 : -1, iy + 1 < ny ? ii + nx : -1, iz + 1 < nz ? ii + nxy : -1};
     const int inb[3] = {bc.dx < BRICK_X - 1 ? bc.g + 1 : -1, bc.dy < BRICK_Y - 1 ? bc.g + BRICK_X : -1,
                         bc.dz < BRICK_Z - 1 ? bc.g + BRICK_X * BRICK_Y : -1};
+    // the slot of a missing neighbour is read and masked
+    const T* pk = bpack + ((size_t)rank * BRICK_CELLS + bc.g) * 4 * BS + r * 8;
     double arow[3][8];
-    const int32_t b0 = diag_pos[ii];
-    int32_t blk = b0 + 1;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         double x[8];
-        row8(A + (size_t)(upper[q] >= 0 ? blk : b0) * BS + r * 8, x);
+        row8(pk + q * BS, x);
 #pragma unroll
         for (int c = 0; c < 8; ++c) arow[q][c] = upper[q] >= 0 ? x[c] : 0.0;
-        blk += upper[q] >= 0;
     }
     double drow[8];
-    row8(Dinv + (size_t)ii * BS + r * 8, drow);
+    row8(pk + 3 * BS, drow);
     const double yi = act ? (double)y[(size_t)ii * NU + r] : 0.0;
     if (act) y[(size_t)ii * NU + r] = from_bits<TV>(Bits<TV>::sentinel);
     bool ext[3];
@@ -601,12 +636,12 @@ __device__ __forceinline__ void bwd_brick(int32_t b, int32_t nbx, int32_t nby, i
 // there, and the lower neighbours' z are read as the sweep publishes them
 // (the work list puts the brick after the backward bricks of all its lower
 // neighbours).  The three lower rows go through LDS, eight lanes per cell;
-// the blocks are added in ascending column order.
+// the blocks are added in ascending column order.  The lower blocks come from
+// the SpMV pack, at the brick's position in the backward list (rank).
 template <class T, class TV>
-__device__ __forceinline__ void spmv_lower_brick(int32_t b, int32_t nbx, int32_t nby, int32_t nx, int32_t ny,
-                                                 int32_t nz, const int32_t* __restrict__ row_ptr,
-                                                 const T* __restrict__ A, const TV* z, TV* w, int32_t* err,
-                                                 BrickLds& L) {
+__device__ __forceinline__ void spmv_lower_brick(int32_t rank, int32_t b, int32_t nbx, int32_t nby, int32_t nx,
+                                                 int32_t ny, int32_t nz, const T* __restrict__ spack, const TV* z,
+                                                 TV* w, int32_t* err, BrickLds& L) {
     const BrickCell bc = brick_cell(b, nbx, nby, nx, ny, nz);
     const int r = bc.r;
     const bool act = bc.i >= 0;
@@ -614,17 +649,15 @@ __device__ __forceinline__ void spmv_lower_brick(int32_t b, int32_t nbx, int32_t
     const int32_t nxy = nx * ny;
     const int32_t ix = ii % nx, iy = (ii / nx) % ny, iz = ii / nxy;
     const int32_t lower[3] = {iz > 0 ? ii - nxy : -1, iy > 0 ? ii - nx : -1, ix > 0 ? ii - 1 : -1};
-    const int32_t b0 = row_ptr[ii];   // the lower blocks lead the block row
     const int me = bc.g * 8 + r;
+    const T* pk = spack + ((size_t)rank * BRICK_CELLS + bc.g) * 3 * BS + r * 8;
     double arow[3][8];
-    int32_t blk = b0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         double x[8];
-        row8(A + (size_t)blk * BS + r * 8, x);
+        row8(pk + k * BS, x);
 #pragma unroll
         for (int c = 0; c < 8; ++c) arow[k][c] = lower[k] >= 0 ? x[c] : 0.0;
-        blk += lower[k] >= 0;
     }
     typename Bits<TV>::U first[3];
 #pragma unroll
@@ -676,12 +709,12 @@ __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_update_syncfree
 template <class T, class TV, int BPW, bool STATIC>
 __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_bwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-    const int32_t* __restrict__ diag_pos, const T* __restrict__ A, const T* __restrict__ Dinv, TV* __restrict__ y,
-    TV* z, unsigned long long* ticket, unsigned long long base, int32_t* err) {
+    const T* __restrict__ bpack, TV* __restrict__ y, TV* z, unsigned long long* ticket, unsigned long long base,
+    int32_t* err) {
     __shared__ BrickLds L[BPW];
     const int h = (int)(threadIdx.x / BRICK_THREADS);
     for_each_group<STATIC>(ticket, base, ngroup, [&](int32_t k) {
-        bwd_brick<T, TV>(bricks[k * BPW + h], nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, nullptr, err, L[h]);
+        bwd_brick<T, TV>(k * BPW + h, bricks[k * BPW + h], nbx, nby, nx, ny, nz, bpack, y, z, nullptr, err, L[h]);
     });
 }
 
@@ -695,17 +728,17 @@ constexpr int32_t SPMV_ITEM = 1 << 30;
 template <class T, class TV, int BPW, bool STATIC>
 __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_bwd_spmv_syncfree(
     const int32_t* __restrict__ items, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-    const T* __restrict__ Dinv, TV* __restrict__ y, TV* z, TV* w, unsigned long long* ticket,
-    unsigned long long base, int32_t* err) {
+    const int32_t* __restrict__ items_rank, const T* __restrict__ bpack, const T* __restrict__ spack,
+    TV* __restrict__ y, TV* z, TV* w, unsigned long long* ticket, unsigned long long base, int32_t* err) {
     __shared__ BrickLds L[BPW];
     const int h = (int)(threadIdx.x / BRICK_THREADS);
     for_each_group<STATIC>(ticket, base, ngroup, [&](int32_t k) {
         const int32_t it = items[k * BPW + h];
+        const int32_t rank = items_rank[k * BPW + h];
         if (it & SPMV_ITEM)
-            spmv_lower_brick<T, TV>(it & (SPMV_ITEM - 1), nbx, nby, nx, ny, nz, row_ptr, A, z, w, err, L[h]);
+            spmv_lower_brick<T, TV>(rank, it & (SPMV_ITEM - 1), nbx, nby, nx, ny, nz, spack, z, w, err, L[h]);
         else
-            bwd_brick<T, TV>(it, nbx, nby, nx, ny, nz, diag_pos, A, Dinv, y, z, w, err, L[h]);
+            bwd_brick<T, TV>(rank, it, nbx, nby, nx, ny, nz, bpack, y, z, w, err, L[h]);
     });
 }
 
@@ -725,6 +758,19 @@ template <> float* sweep_buffer<float>(isc_ctx* ctx) { return ctx->sweep32; }
 template <class T> T* lt_buffer(isc_ctx* ctx);
 template <> double* lt_buffer<double>(isc_ctx* ctx) { return ctx->Lt; }
 template <> float* lt_buffer<float>(isc_ctx* ctx) { return ctx->Lt32; }
+// the backward and SpMV packs of the last factor in each precision
+template <class T> T* bpack_buffer(isc_ctx* ctx);
+template <> double* bpack_buffer<double>(isc_ctx* ctx) { return ctx->bpack64; }
+template <> float* bpack_buffer<float>(isc_ctx* ctx) { return ctx->bpack32; }
+template <class T> T* spack_buffer(isc_ctx* ctx);
+template <> double* spack_buffer<double>(isc_ctx* ctx) { return ctx->spack64; }
+template <> float* spack_buffer<float>(isc_ctx* ctx) { return ctx->spack32; }
+template <class T>
+void launch_form_packs(isc_ctx* ctx, const T* A, const T* Dinv) {
+    hipLaunchKernelGGL(isc::form_packs<T>, dim3((ctx->n + 3) / 4), dim3(256), 0, ctx->stream, ctx->n, ctx->g.nx,
+                       ctx->g.ny, ctx->g.nz, ctx->row_ptr, ctx->diag_pos, A, Dinv, ctx->b_slot,
+                       isc::bpack_buffer<T>(ctx), isc::spack_buffer<T>(ctx));
+}
 }  // namespace isc
 
 // Fills the private sweep buffers with the sentinel (at creation and after a
@@ -748,6 +794,7 @@ hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t*
                            ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
                            ctx->diag_pos, A, Dinv, isc::lt_buffer<T>(ctx), ctx->lt_slot, bad_dev);
     }
+    isc::launch_form_packs<T>(ctx, A, Dinv);
     return hipGetLastError();
 }
 
@@ -817,19 +864,22 @@ void launch_fwd_update(isc_ctx* ctx, const isc::LagUpdateT<T>& lu, T* v, T* z, T
                  bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, Lt, lu, v, z, w);
 }
 template <int BPW, class T, class TV>
-void launch_bwd(isc_ctx* ctx, const T* A, const T* Dinv, TV* v, TV* z) {
+void launch_bwd(isc_ctx* ctx, TV* v, TV* z) {
+    const T* bpack = isc::bpack_buffer<T>(ctx);
     launch_sweep(ctx, reinterpret_cast<const void*>(&isc::bilu0_bwd_syncfree<T, TV, BPW, false>),
                  reinterpret_cast<const void*>(&isc::bilu0_bwd_syncfree<T, TV, BPW, true>),
                  isc::BRICK_THREADS * BPW, ctx->nbwd_items / BPW, (const int32_t*)ctx->bricks_bwd, bricks_x(ctx),
-                 bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, (const int32_t*)ctx->diag_pos, A, Dinv, v, z);
+                 bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, bpack, v, z);
 }
 template <int BPW, class T, class TV>
-void launch_bwd_spmv(isc_ctx* ctx, const T* A, const T* Dinv, TV* v, TV* z, TV* w) {
+void launch_bwd_spmv(isc_ctx* ctx, TV* v, TV* z, TV* w) {
+    const T* bpack = isc::bpack_buffer<T>(ctx);
+    const T* spack = isc::spack_buffer<T>(ctx);
     launch_sweep(ctx, reinterpret_cast<const void*>(&isc::bilu0_bwd_spmv_syncfree<T, TV, BPW, false>),
                  reinterpret_cast<const void*>(&isc::bilu0_bwd_spmv_syncfree<T, TV, BPW, true>),
                  isc::BRICK_THREADS * BPW, ctx->nfused_items / BPW, (const int32_t*)ctx->items_bwd_spmv,
-                 bricks_x(ctx), bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, (const int32_t*)ctx->row_ptr,
-                 (const int32_t*)ctx->diag_pos, A, Dinv, v, z, w);
+                 bricks_x(ctx), bricks_y(ctx), ctx->g.nx, ctx->g.ny, ctx->g.nz, (const int32_t*)ctx->items_rank,
+                 bpack, spack, v, z, w);
 }
 }  // namespace
 
@@ -839,10 +889,10 @@ hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, con
         TV* v = isc::sweep_buffer<TV>(ctx);
         if (ctx->bpw == 2) {
             launch_fwd<2, T, TV>(ctx, r, v, z, (TV*)nullptr);
-            launch_bwd<2, T, TV>(ctx, A, Dinv, v, z);
+            launch_bwd<2, T, TV>(ctx, v, z);
         } else {
             launch_fwd<1, T, TV>(ctx, r, v, z, (TV*)nullptr);
-            launch_bwd<1, T, TV>(ctx, A, Dinv, v, z);
+            launch_bwd<1, T, TV>(ctx, v, z);
         }
         return hipGetLastError();
     }
@@ -875,10 +925,10 @@ hipError_t isc_launch_bilu0_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Dinv
     TV* v = isc::sweep_buffer<TV>(ctx);
     if (ctx->bpw == 2) {
         launch_fwd<2, T, TV>(ctx, r, v, z, w);
-        launch_bwd_spmv<2, T, TV>(ctx, A, Dinv, v, z, w);
+        launch_bwd_spmv<2, T, TV>(ctx, v, z, w);
     } else {
         launch_fwd<1, T, TV>(ctx, r, v, z, w);
-        launch_bwd_spmv<1, T, TV>(ctx, A, Dinv, v, z, w);
+        launch_bwd_spmv<1, T, TV>(ctx, v, z, w);
     }
     return hipGetLastError();
 }
@@ -893,10 +943,10 @@ hipError_t isc_launch_update_apply_spmv_t(isc_ctx* ctx, const T* A, const T* Din
     T* v = isc::sweep_buffer<T>(ctx);
     if (ctx->bpw == 2) {
         launch_fwd_update<2, T>(ctx, lu, v, z, w);
-        launch_bwd_spmv<2, T, T>(ctx, A, Dinv, v, z, w);
+        launch_bwd_spmv<2, T, T>(ctx, v, z, w);
     } else {
         launch_fwd_update<1, T>(ctx, lu, v, z, w);
-        launch_bwd_spmv<1, T, T>(ctx, A, Dinv, v, z, w);
+        launch_bwd_spmv<1, T, T>(ctx, v, z, w);
     }
     return hipGetLastError();
 }
@@ -927,6 +977,7 @@ hipError_t isc_launch_bilu0_factor32(isc_ctx* ctx, const float* A, float* Dinv, 
 hipError_t isc_launch_form_ltilde(isc_ctx* ctx, const double* A, const double* Dinv) {
     hipLaunchKernelGGL(isc::form_ltilde<double>, dim3((ctx->n + 3) / 4), dim3(256), 0, ctx->stream, ctx->n,
                        ctx->g.nx, ctx->g.ny, ctx->row_ptr, A, Dinv, ctx->Lt, (const int32_t*)ctx->lt_slot);
+    isc::launch_form_packs<double>(ctx, A, Dinv);
     return hipGetLastError();
 }
 hipError_t isc_launch_bilu0_apply(isc_ctx* ctx, const double* A, const double* Dinv, const double* r, double* z) {
