@@ -204,6 +204,7 @@ struct isc_ctx {
     float* t32 = nullptr;
     float* t32b = nullptr;
     double* small32 = nullptr;
+    float* Z32 = nullptr;           // [inner][N*8] the inner solver's z_j = P(u_j)
     // adjoint workspace
     double* accJ = nullptr;         // [N][64] accumulation Jacobian
     double* qg = nullptr;           // [N][8]  producer oil-rate gradient

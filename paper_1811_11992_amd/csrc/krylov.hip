@@ -608,6 +608,7 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
     const int nb2 = nblocks(len2);
     Hess hi = hess_at(ctx->small32, ctx->inner_max);
     Dcgs di = dcgs_at(ctx->small32, ctx->inner_max);
+    di.Rs = ctx->small32 + RS_OFF;   // u_j = Q_j s_j + omega_j q_j, to form the result from Z32
     double* red = ctx->small32 + RED_OFF;
     float2* Q2 = reinterpret_cast<float2*>(ctx->V32);
     float* u = ctx->V32 + (size_t)m_in * len;
@@ -627,12 +628,13 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
         }
         if (!last) {   // w = A M^-1 u_j in FP32: forward sweep, backward sweep fused with the SpMV
             const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_SPMV32);
+            float* Zj = ctx->Z32 + (size_t)j * len;   // z_j = M^-1 u_j, kept
             if (fold) {
                 const LagUpdateT<float> lu{ctx->V32, len, j - 1, red, red + MAXV, di.omz, u, ctx->w32};
-                isc_launch_update_apply_spmv32(ctx, A32, D32, lu, ctx->t32, ctx->w32);
+                isc_launch_update_apply_spmv32(ctx, A32, D32, lu, Zj, ctx->w32);
                 isc_prof_vectors(ctx, ISC_PROF_ILU_SPMV32, (double)(j + 2));
             } else {
-                isc_launch_bilu0_apply_spmv32(ctx, A32, D32, u, ctx->t32, ctx->w32);
+                isc_launch_bilu0_apply_spmv32(ctx, A32, D32, u, Zj, ctx->w32);
             }
             isc_prof_end(ctx, tk);
         }
@@ -644,12 +646,11 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
         hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hi, di, j, last ? 1 : 0, red);
         isc_prof_end(ctx, tk);
     }
+    // z = M^-1 Q y = Z32 (Rs^-1 y): no further BILU(0) apply
     hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hi, m_in);
-    hipLaunchKernelGGL((lincomb<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->V32, len, m_in, hi.y,
-                       ctx->t32b, 0);
-    const int tk = isc_prof_begin(ctx, ISC_PROF_ILU_APPLY32);
-    isc_launch_bilu0_apply32(ctx, A32, D32, ctx->t32b, ctx->t32);
-    isc_prof_end(ctx, tk);
+    hipLaunchKernelGGL(dcgs2_solve_rs, dim3(1), dim3(1), 0, ctx->stream, hi, di, m_in);
+    hipLaunchKernelGGL((lincomb<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->Z32, len, m_in, hi.y,
+                       ctx->t32, 0);
     hipLaunchKernelGGL(to_f64, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->t32, z);
 }
 
