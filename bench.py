@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
-    ap.add_argument("--inner", type=int, default=6, help="FP32 inner iterations (mixed)")
+    ap.add_argument("--inner", type=int, default=12, help="FP32 inner iterations (mixed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision and the adjoint-cost legs")
