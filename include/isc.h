@@ -224,8 +224,8 @@ isc_status isc_oil_rate(isc_ctx* ctx, const double* u, double* q_h);
  * 0 SpMV, 1 BILU(0) apply (one forward plus one backward sweep), 2 assembly
  * (property pass + face assembly), 3 decoupling, 4 BILU(0) factor (all
  * levels), 5 Krylov vector work (orthogonalisation, updates, norms, in both
- * precisions), 6 FP32 BILU(0) apply (the inner solver's solution update) and
- * 7 FP32 SpMV, 8 BILU(0) apply fused with the SpMV (z = M^-1 r, w = A z; the
+ * precisions), 6 and 7 no longer used (FP32 apply and SpMV as separate
+ * kernels), 8 BILU(0) apply fused with the SpMV (z = M^-1 r, w = A z; the
  * FP64 GMRES iteration, with its folded Gram-Schmidt update), 9 the same in
  * FP32 (the inner GMRES iteration of the precision form). */
 enum { ISC_PROF_SPMV = 0, ISC_PROF_ILU_APPLY, ISC_PROF_ASSEMBLE, ISC_PROF_DECOUPLE, ISC_PROF_ILU_FACTOR,

@@ -401,7 +401,6 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         ALLOC(ctx->V32, nv * (ctx->inner_max + 1));
         ALLOC(ctx->w32, nv);
         ALLOC(ctx->t32, nv);
-        ALLOC(ctx->t32b, nv);
         ALLOC(ctx->small32, (size_t)4096 + 32 * 32);   // as small: Rs past 4096
         ALLOC(ctx->Z32, nv * ctx->inner_max);
     }
@@ -485,7 +484,7 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->bpack64, ctx->spack64, ctx->bpack32, ctx->spack32, ctx->payload, ctx->F,
                     ctx->J,       ctx->Dinv,  ctx->du,      ctx->rhs,    ctx->V,       ctx->Z,
                     ctx->w,       ctx->tvec,  ctx->tvec2,   ctx->partial, ctx->small,  ctx->flags,
-                    ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,     ctx->t32b,
+                    ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,
                     ctx->small32, ctx->Z32, ctx->accJ,   ctx->qg,     ctx->qv,     ctx->rates,
                     ctx->perf_cell, ctx->well_off, ctx->bricks_fwd, ctx->bricks_bwd, ctx->sweep64,
                     ctx->sweep32, ctx->ticket, ctx->Lt, ctx->Lt32, ctx->items_bwd_spmv};

@@ -202,7 +202,6 @@ struct isc_ctx {
     float* V32 = nullptr;           // [(inner+1)][N*8]
     float* w32 = nullptr;
     float* t32 = nullptr;
-    float* t32b = nullptr;
     double* small32 = nullptr;
     float* Z32 = nullptr;           // [inner][N*8] the inner solver's z_j = P(u_j)
     // adjoint workspace

@@ -577,8 +577,6 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
 }
 
 // ---------------------------------------------------------------- precision form
-hipError_t isc_launch_bilu0_apply32(isc_ctx*, const float*, const float*, const float*, float*);
-hipError_t isc_launch_spmv32(isc_ctx*, const float*, const float*, float*);
 hipError_t isc_launch_bilu0_apply_spmv32(isc_ctx*, const float*, const float*, const float*, float*, float*);
 hipError_t isc_launch_update_apply_spmv32(isc_ctx*, const float*, const float*, const isc::LagUpdateT<float>&, float*,
                                           float*);

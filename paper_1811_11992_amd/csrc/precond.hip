@@ -983,9 +983,6 @@ hipError_t isc_launch_form_ltilde(isc_ctx* ctx, const double* A, const double* D
 hipError_t isc_launch_bilu0_apply(isc_ctx* ctx, const double* A, const double* Dinv, const double* r, double* z) {
     return isc_launch_bilu0_apply_t<double, double>(ctx, A, Dinv, r, z);
 }
-hipError_t isc_launch_bilu0_apply32(isc_ctx* ctx, const float* A, const float* Dinv, const float* r, float* z) {
-    return isc_launch_bilu0_apply_t<float, float>(ctx, A, Dinv, r, z);
-}
 hipError_t isc_launch_bilu0_apply_spmv(isc_ctx* ctx, const double* A, const double* Dinv, const double* r,
                                        double* z, double* w) {
     return isc_launch_bilu0_apply_spmv_t<double, double>(ctx, A, Dinv, r, z, w);
@@ -996,7 +993,4 @@ hipError_t isc_launch_spmv(isc_ctx* ctx, const double* A, const double* x, doubl
 hipError_t isc_launch_bilu0_apply_spmv32(isc_ctx* ctx, const float* A, const float* Dinv, const float* r, float* z,
                                          float* w) {
     return isc_launch_bilu0_apply_spmv_t<float, float>(ctx, A, Dinv, r, z, w);
-}
-hipError_t isc_launch_spmv32(isc_ctx* ctx, const float* A, const float* x, float* y) {
-    return isc_launch_spmv_t<float, float>(ctx, A, x, y);
 }
