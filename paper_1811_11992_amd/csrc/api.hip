@@ -563,9 +563,10 @@ isc_status isc_bilu0(isc_ctx* ctx, const double* Jdec, double* Dinv) {
     TRY(read_flag(ctx, FLAG_BAD, &bad));
     if (bad != INT32_MAX) {
         ctx->err = "block ILU(0): singular pivot block at cell " + std::to_string(bad);
+        (void)isc_check_sweeps(ctx);
         return ISC_ERR_SINGULAR;
     }
-    return ISC_OK;
+    return isc_check_sweeps(ctx);
 }
 
 isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv, const double* r, double* z) {

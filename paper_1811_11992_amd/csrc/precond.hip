@@ -11,14 +11,15 @@
 //     forward   y_i = r_i - sum_{k lower} Lt_ik y_k
 //     backward  z_i = D_i^-1 (y_i - sum_{j upper} A_ij z_j),
 // which reads seven blocks per row instead of eight (D^-1 once).
-// The factor is scheduled by hyperplanes ix + iy + iz = s (all rows of a
-// hyperplane are independent), one launch each; the triangular sweeps of the
-// apply run as one launch each over 2x2x2 bricks (below), with one launch per
-// hyperplane kept as the reference schedule.  Every schedule gives the
-// natural-order factorisation exactly.
+// The factor is one cooperative launch over the rows in hyperplane order
+// (ix + iy + iz = s), each row awaiting the D_k^-1 of its lower neighbours;
+// the triangular sweeps of the apply run as one launch each over 4x4x2 bricks
+// of 256 threads (below).  One launch per hyperplane is kept for both as the
+// reference schedule.  Every schedule gives the natural-order factorisation
+// exactly, bit for bit the same.
 //
 // Mappings: factor - one wavefront per row, lane (r, c) with LDS-staged 8x8
-// products and a column-per-lane Gauss-Jordan inverse; apply - one wavefront
+// products and a column-per-lane Gauss-Jordan inverse; sweeps - one workgroup
 // per brick, eight lanes per cell; SpMV - eight lanes per block row, lane r
 // owns output row r.
 #include "common.h"
@@ -34,91 +35,6 @@ __device__ __forceinline__ int32_t upper_block(int32_t k, int dir, int32_t nx, i
     if (dir >= 2) b += (iy + 1 < ny);
     (void)nz;
     return b;
-}
-
-template <class T>
-__global__ void __launch_bounds__(256) bilu0_factor_level(
-    const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, int32_t nz,
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-    T* __restrict__ Dinv, T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, int32_t* __restrict__ bad) {
-    __shared__ double sm[4][4][64];
-    const int w = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int32_t t = blockIdx.x * 4 + w;
-    if (t >= cnt) return;
-    const int32_t i = rows[t];
-    const int r = lane >> 3, c = lane & 7;
-    double* sA = sm[w][0];
-    double* sK = sm[w][1];
-    double* sB = sm[w][2];
-    double* sP = sm[w][3];
-    const int32_t nxy = nx * ny;
-    const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
-    double D = (r == c) ? 1.0 : 0.0;
-    int32_t blk = row_ptr[i];
-    const int32_t lower[3] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1};
-    const int ldir[3] = {2, 1, 0};
-    for (int q = 0; q < 3; ++q) {
-        const int32_t k = lower[q];
-        if (k < 0) continue;
-        const int32_t bki = upper_block(k, ldir[q], nx, ny, nz, diag_pos);
-        sA[lane] = (double)A[(size_t)blk * BS + lane];
-        sK[lane] = (double)Dinv[(size_t)k * BS + lane];
-        sB[lane] = (double)A[(size_t)bki * BS + lane];
-        ++blk;
-        __builtin_amdgcn_wave_barrier();
-        double p = 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) p += sA[r * 8 + j] * sK[j * 8 + c];
-        sP[lane] = p;
-        Lt[((size_t)lt_slot[i] * 3 + q) * BS + lane] = (T)p;
-        __builtin_amdgcn_wave_barrier();
-        double q2 = 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) q2 += sP[r * 8 + j] * sB[j * 8 + c];
-        D -= q2;
-        __builtin_amdgcn_wave_barrier();
-    }
-    // invert D: lanes 0..15 hold the columns of [D | I]
-    sP[lane] = D;
-    __builtin_amdgcn_wave_barrier();
-    double a[8];
-#pragma unroll
-    for (int rr = 0; rr < 8; ++rr) a[rr] = lane < 8 ? sP[rr * 8 + lane] : ((lane - 8) == rr ? 1.0 : 0.0);
-    bool singular = false;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        double col[8];
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr) col[rr] = __shfl(a[rr], k);
-        int piv = k;
-        double best = fabs(col[k]);
-#pragma unroll
-        for (int rr = k + 1; rr < 8; ++rr) {
-            const double tt = fabs(col[rr]);
-            if (tt > best) { best = tt; piv = rr; }
-        }
-#pragma unroll
-        for (int rr = k + 1; rr < 8; ++rr)
-            if (rr == piv) {
-                const double x = a[k]; a[k] = a[rr]; a[rr] = x;
-                const double y = col[k]; col[k] = col[rr]; col[rr] = y;
-            }
-        const double pv = col[k];
-        if (!(fabs(pv) > 0.0) || !isfinite(pv)) { singular = true; break; }
-        a[k] = a[k] / pv;
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr)
-            if (rr != k) a[rr] -= col[rr] * a[k];
-    }
-    if (singular) {
-        if (lane == 0) atomicMin(bad, i);
-        return;
-    }
-    if (lane >= 8 && lane < 16) {
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr) Dinv[(size_t)i * BS + rr * 8 + (lane - 8)] = (T)a[rr];
-    }
 }
 
 // Lt_ik = A_ik D_k^-1 for every lower neighbour k of i, from a given factor
@@ -679,6 +595,143 @@ __device__ __forceinline__ void spmv_lower_brick(int32_t rank, int32_t b, int32_
     if (act) w[(size_t)ii * NU + r] = (TV)acc;
 }
 
+// One row of the factor, one wavefront, lane (r, c): D_i = I - sum_k Lt_ik A_ki
+// with Lt_ik = A_ik D_k^-1 for the lower neighbours k (stored in sweep order),
+// then D_i^-1 by Gauss-Jordan with partial pivoting, a column per lane.  With
+// SF (sync-free) the D_k^-1 are awaited element by element (Dinv holds the
+// sentinel until a row publishes its block) and D_i^-1 is published; a
+// singular row publishes zeros so that its dependants finish, and reports
+// itself through bad.  Same arithmetic either way.
+template <class T, bool SF>
+__device__ __forceinline__ void factor_row(int32_t i, int32_t nx, int32_t ny, int32_t nz,
+                                           const int32_t* __restrict__ row_ptr,
+                                           const int32_t* __restrict__ diag_pos, const T* __restrict__ A, T* Dinv,
+                                           T* __restrict__ Lt, const int32_t* __restrict__ lt_slot,
+                                           int32_t* __restrict__ bad, int32_t* err, double (*sm)[64]) {
+    const int lane = threadIdx.x & 63;
+    const int r = lane >> 3, c = lane & 7;
+    double* sA = sm[0];
+    double* sK = sm[1];
+    double* sB = sm[2];
+    double* sP = sm[3];
+    const int32_t nxy = nx * ny;
+    const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
+    double D = (r == c) ? 1.0 : 0.0;
+    int32_t blk = row_ptr[i];
+    const int32_t lower[3] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1};
+    const int ldir[3] = {2, 1, 0};
+    for (int q = 0; q < 3; ++q) {
+        const int32_t k = lower[q];
+        if (k < 0) continue;
+        const int32_t bki = upper_block(k, ldir[q], nx, ny, nz, diag_pos);
+        sA[lane] = (double)A[(size_t)blk * BS + lane];
+        if constexpr (SF) {
+            const T* dk = Dinv + (size_t)k * BS + lane;
+            sK[lane] = (double)await_value(dk, peek(dk), err);
+        } else {
+            sK[lane] = (double)Dinv[(size_t)k * BS + lane];
+        }
+        sB[lane] = (double)A[(size_t)bki * BS + lane];
+        ++blk;
+        __builtin_amdgcn_wave_barrier();
+        double p = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) p += sA[r * 8 + j] * sK[j * 8 + c];
+        sP[lane] = p;
+        Lt[((size_t)lt_slot[i] * 3 + q) * BS + lane] = (T)p;
+        __builtin_amdgcn_wave_barrier();
+        double q2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) q2 += sP[r * 8 + j] * sB[j * 8 + c];
+        D -= q2;
+        __builtin_amdgcn_wave_barrier();
+    }
+    // invert D: lanes 0..15 hold the columns of [D | I]
+    sP[lane] = D;
+    __builtin_amdgcn_wave_barrier();
+    double a[8];
+#pragma unroll
+    for (int rr = 0; rr < 8; ++rr) a[rr] = lane < 8 ? sP[rr * 8 + lane] : ((lane - 8) == rr ? 1.0 : 0.0);
+    __builtin_amdgcn_wave_barrier();   // the LDS is reused by the wavefront's next row
+    bool singular = false;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        double col[8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) col[rr] = __shfl(a[rr], k);
+        int piv = k;
+        double best = fabs(col[k]);
+#pragma unroll
+        for (int rr = k + 1; rr < 8; ++rr) {
+            const double tt = fabs(col[rr]);
+            if (tt > best) { best = tt; piv = rr; }
+        }
+#pragma unroll
+        for (int rr = k + 1; rr < 8; ++rr)
+            if (rr == piv) {
+                const double x = a[k]; a[k] = a[rr]; a[rr] = x;
+                const double y = col[k]; col[k] = col[rr]; col[rr] = y;
+            }
+        const double pv = col[k];
+        if (!(fabs(pv) > 0.0) || !isfinite(pv)) { singular = true; break; }
+        a[k] = a[k] / pv;
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr)
+            if (rr != k) a[rr] -= col[rr] * a[k];
+    }
+    if (singular) {
+        if (lane == 0) atomicMin(bad, i);
+        if constexpr (SF) {
+            if (lane >= 8 && lane < 16) {
+#pragma unroll
+                for (int rr = 0; rr < 8; ++rr) publish(Dinv + (size_t)i * BS + rr * 8 + (lane - 8), T(0));
+            }
+        }
+        return;
+    }
+    if (lane >= 8 && lane < 16) {
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) {
+            if constexpr (SF)
+                publish(Dinv + (size_t)i * BS + rr * 8 + (lane - 8), (T)a[rr]);
+            else
+                Dinv[(size_t)i * BS + rr * 8 + (lane - 8)] = (T)a[rr];
+        }
+    }
+}
+
+// The factor by hyperplanes ix + iy + iz = s, one launch each (the reference
+// schedule): one wavefront per row of the hyperplane.
+template <class T>
+__global__ void __launch_bounds__(256) bilu0_factor_level(
+    const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, int32_t nz,
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
+    T* __restrict__ Dinv, T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, int32_t* __restrict__ bad) {
+    __shared__ double sm[4][4][64];
+    const int w = threadIdx.x >> 6;
+    const int32_t t = blockIdx.x * 4 + w;
+    if (t >= cnt) return;
+    factor_row<T, false>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, bad, nullptr, sm[w]);
+}
+
+// The whole factor in one cooperative launch (every wavefront resident): the
+// rows in hyperplane order, wavefront t of the grid taking rows t, t + W,
+// t + 2W, ... (W = the grid's wavefronts).  The lowest unfinished row's
+// wavefront has finished its earlier rows, so it is working on that row, and
+// the rows it waits for lie on earlier hyperplanes: no deadlock.  Dinv must
+// hold the sentinel on entry.
+template <class T>
+__global__ void __launch_bounds__(256) bilu0_factor_syncfree(
+    const int32_t* __restrict__ rows, int32_t n, int32_t nx, int32_t ny, int32_t nz,
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A, T* Dinv,
+    T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, int32_t* __restrict__ bad, int32_t* err) {
+    __shared__ double sm[4][4][64];
+    const int w = threadIdx.x >> 6;
+    const int32_t nwave = (int32_t)gridDim.x * 4;
+    for (int32_t t = (int32_t)blockIdx.x * 4 + w; t < n; t += nwave)
+        factor_row<T, true>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, bad, err, sm[w]);
+}
+
 // One workgroup per brick; workgroups take tickets in brick-list order.
 template <class T, class TV, int BPW, bool STATIC>
 __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_syncfree(
@@ -786,17 +839,6 @@ hipError_t isc_reset_sweep_buffers(isc_ctx* ctx) {
 }
 
 // ------------------------------------------------------------------ launchers
-template <class T>
-hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t* bad_dev) {
-    for (int32_t s = 0; s < ctx->nlev; ++s) {
-        const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
-        hipLaunchKernelGGL(isc::bilu0_factor_level<T>, dim3((cnt + 3) / 4), dim3(256), 0, ctx->stream,
-                           ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
-                           ctx->diag_pos, A, Dinv, isc::lt_buffer<T>(ctx), ctx->lt_slot, bad_dev);
-    }
-    isc::launch_form_packs<T>(ctx, A, Dinv);
-    return hipGetLastError();
-}
 
 // One launch of each sync-free sweep kernel with `BPW` bricks per workgroup
 // (the context's choice); each workgroup takes one ticket.
@@ -882,6 +924,49 @@ void launch_bwd_spmv(isc_ctx* ctx, TV* v, TV* z, TV* w) {
                  bpack, spack, v, z, w);
 }
 }  // namespace
+
+template <class T>
+hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t* bad_dev) {
+    bool done = false;
+    if (ctx->syncfree) {   // one cooperative launch; Dinv starts as the sentinel
+        const int64_t len = (int64_t)ctx->n * isc::BS;
+        const int nb = (int)((len + 255) / 256);
+        if (sizeof(T) == 8)
+            hipLaunchKernelGGL((isc::fill_bits<unsigned long long>), dim3(nb), dim3(256), 0, ctx->stream, len,
+                               reinterpret_cast<unsigned long long*>(Dinv), (unsigned long long)isc::SENTINEL64);
+        else
+            hipLaunchKernelGGL((isc::fill_bits<unsigned int>), dim3(nb), dim3(256), 0, ctx->stream, len,
+                               reinterpret_cast<unsigned int*>(Dinv), (unsigned int)isc::SENTINEL32);
+        const void* k = reinterpret_cast<const void*>(&isc::bilu0_factor_syncfree<T>);
+        const int32_t cap = coresident(ctx, k, 256);
+        if (cap > 0) {
+            const int32_t rows_n = ctx->n;
+            const int32_t grid = cap < (rows_n + 3) / 4 ? cap : (rows_n + 3) / 4;
+            const int32_t* rows = ctx->lvl_rows;
+            int32_t nx = ctx->g.nx, ny = ctx->g.ny, nz = ctx->g.nz, n = rows_n;
+            const int32_t* row_ptr = ctx->row_ptr;
+            const int32_t* diag_pos = ctx->diag_pos;
+            T* Lt = isc::lt_buffer<T>(ctx);
+            const int32_t* lt_slot = ctx->lt_slot;
+            int32_t* err = ctx->flags + ISC_FLAG_SWEEP;
+            void* argv[] = {(void*)&rows, (void*)&n, (void*)&nx, (void*)&ny, (void*)&nz, (void*)&row_ptr,
+                            (void*)&diag_pos, (void*)&A, (void*)&Dinv, (void*)&Lt, (void*)&lt_slot,
+                            (void*)&bad_dev, (void*)&err};
+            done = hipLaunchCooperativeKernel(k, dim3(grid), dim3(256), argv, 0, ctx->stream) == hipSuccess;
+            if (!done) (void)hipGetLastError();   // the level launches below
+        }
+    }
+    if (!done) {
+        for (int32_t s = 0; s < ctx->nlev; ++s) {
+            const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
+            hipLaunchKernelGGL(isc::bilu0_factor_level<T>, dim3((cnt + 3) / 4), dim3(256), 0, ctx->stream,
+                               ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
+                               ctx->diag_pos, A, Dinv, isc::lt_buffer<T>(ctx), ctx->lt_slot, bad_dev);
+        }
+    }
+    isc::launch_form_packs<T>(ctx, A, Dinv);
+    return hipGetLastError();
+}
 
 template <class T, class TV>
 hipError_t isc_launch_bilu0_apply_t(isc_ctx* ctx, const T* A, const T* Dinv, const TV* r, TV* z) {

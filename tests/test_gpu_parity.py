@@ -164,6 +164,45 @@ def test_preconditioner_and_spmv_match_oracle(name, seed):
     assert np.all(np.abs(w_f - w_o).max(axis=0) <= 1e-10 * np.abs(w_o).max(axis=0))
 
 
+@pytest.mark.parametrize("name,seed", [("tiny:13x7x5", 61), ("C1", 62), ("tiny:9x17x6", 63)])
+def test_sync_free_factor_equals_level_factor_bitwise(name, seed, monkeypatch):
+    """The factor as one cooperative launch (each row awaits its lower
+    neighbours' D^-1 as they are published) and as one launch per hyperplane
+    run the same per-row arithmetic, so D^-1 agrees bit for bit, and so do
+    the applies built on it."""
+    wl, m, u, F, J = _decoupled_case(name, seed)
+    st, Jd, Fd, _ = m.decouple(J, F)
+    c_sf = ctx_for(wl)
+    monkeypatch.setenv("ISC_LEVEL_SWEEPS", "1")
+    c_lv = ctx_for(wl)
+    Jdg = dev(Jd)
+    D_sf = c_sf.isc_bilu0(Jdg)
+    D_lv = c_lv.isc_bilu0(Jdg)
+    torch.cuda.synchronize()
+    assert torch.equal(D_sf, D_lv)
+    x = dev(np.random.default_rng(seed).standard_normal((m.n, 8)) * COL[None, :])
+    assert torch.equal(c_sf.isc_bilu0_apply(Jdg, D_sf, x), c_lv.isc_bilu0_apply(Jdg, D_lv, x))
+
+
+@pytest.mark.parametrize("level", ["0", "1"])
+def test_factor_reports_singular_pivot_without_hanging(level, monkeypatch):
+    """A column of three cells whose off-diagonal blocks are the identity:
+    D_0 = I, D_1 = I - I I = 0 is singular.  Both factor schedules report
+    cell 1; in the sync-free one the singular row still publishes a block, so
+    the row after it finishes instead of waiting."""
+    from paper_1811_11992_amd import isc
+    wl = I.make_workload("tiny:1x1x3")
+    m = O.Model(wl)
+    Jd = np.zeros((m.row_ptr[-1], 8, 8))
+    Jd[:] = np.eye(8)
+    monkeypatch.setenv("ISC_LEVEL_SWEEPS", level)
+    c = ctx_for(wl)
+    with pytest.raises(isc.IscError, match="singular pivot block at cell 1"):
+        c.isc_bilu0(dev(Jd))
+    st, LU, Dinv_o = m.bilu0(Jd)
+    assert st == -4
+
+
 @pytest.mark.parametrize("coop,bpw", [("1", "1"), ("0", "1"), ("0", "2")])
 @pytest.mark.parametrize("name,seed", [("tiny:1x1x6", 40), ("tiny:13x7x5", 41), ("C1", 42)])
 def test_sync_free_sweeps_equal_level_sweeps_bitwise(name, seed, coop, bpw, monkeypatch):
