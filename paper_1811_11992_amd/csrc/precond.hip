@@ -595,13 +595,23 @@ __device__ __forceinline__ void spmv_lower_brick(int32_t rank, int32_t b, int32_
     if (act) w[(size_t)ii * NU + r] = (TV)acc;
 }
 
+// Lane l's value, read into a scalar register (l the same on every lane).
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // One row of the factor, one wavefront, lane (r, c): D_i = I - sum_k Lt_ik A_ki
 // with Lt_ik = A_ik D_k^-1 for the lower neighbours k (stored in sweep order),
-// then D_i^-1 by Gauss-Jordan with partial pivoting, a column per lane.  With
-// SF (sync-free) the D_k^-1 are awaited element by element (Dinv holds the
-// sentinel until a row publishes its block) and D_i^-1 is published; a
-// singular row publishes zeros so that its dependants finish, and reports
-// itself through bad.  Same arithmetic either way.
+// then D_i^-1 by Gauss-Jordan with partial pivoting, a column per lane.  The
+// blocks of A that the row needs are loaded first, all six at once, then the
+// three D_k^-1: with SF (sync-free) awaited element by element, all three in
+// flight together (Dinv holds the sentinel until a row publishes its block),
+// and D_i^-1 is published; a singular row publishes zeros so that its
+// dependants finish, and reports itself through bad.  Same arithmetic either
+// way.  sm holds 12 tiles of 64 doubles.
 template <class T, bool SF>
 __device__ __forceinline__ void factor_row(int32_t i, int32_t nx, int32_t ny, int32_t nz,
                                            const int32_t* __restrict__ row_ptr,
@@ -610,42 +620,59 @@ __device__ __forceinline__ void factor_row(int32_t i, int32_t nx, int32_t ny, in
                                            int32_t* __restrict__ bad, int32_t* err, double (*sm)[64]) {
     const int lane = threadIdx.x & 63;
     const int r = lane >> 3, c = lane & 7;
-    double* sA = sm[0];
-    double* sK = sm[1];
-    double* sB = sm[2];
-    double* sP = sm[3];
     const int32_t nxy = nx * ny;
     const int32_t ix = i % nx, iy = (i / nx) % ny, iz = i / nxy;
-    double D = (r == c) ? 1.0 : 0.0;
-    int32_t blk = row_ptr[i];
     const int32_t lower[3] = {iz > 0 ? i - nxy : -1, iy > 0 ? i - nx : -1, ix > 0 ? i - 1 : -1};
     const int ldir[3] = {2, 1, 0};
+    T av[3], bv[3], kv[3];
+    int32_t blk = row_ptr[i];
+#pragma unroll
     for (int q = 0; q < 3; ++q) {
-        const int32_t k = lower[q];
-        if (k < 0) continue;
-        const int32_t bki = upper_block(k, ldir[q], nx, ny, nz, diag_pos);
-        sA[lane] = (double)A[(size_t)blk * BS + lane];
-        if constexpr (SF) {
-            const T* dk = Dinv + (size_t)k * BS + lane;
-            sK[lane] = (double)await_value(dk, peek(dk), err);
-        } else {
-            sK[lane] = (double)Dinv[(size_t)k * BS + lane];
-        }
-        sB[lane] = (double)A[(size_t)bki * BS + lane];
+        av[q] = bv[q] = T(0);
+        if (lower[q] < 0) continue;
+        av[q] = A[(size_t)blk * BS + lane];   // A_ik: the row's lower blocks come first, in this order
+        bv[q] = A[(size_t)upper_block(lower[q], ldir[q], nx, ny, nz, diag_pos) * BS + lane];   // A_ki
         ++blk;
-        __builtin_amdgcn_wave_barrier();
+    }
+    if constexpr (SF) {
+        typename Bits<T>::U first[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) first[q] = lower[q] >= 0 ? peek(Dinv + (size_t)lower[q] * BS + lane) : 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            kv[q] = lower[q] >= 0 ? await_value(Dinv + (size_t)lower[q] * BS + lane, first[q], err) : T(0);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) kv[q] = lower[q] >= 0 ? Dinv[(size_t)lower[q] * BS + lane] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        sm[q][lane] = (double)av[q];
+        sm[3 + q][lane] = (double)kv[q];
+        sm[6 + q][lane] = (double)bv[q];
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (lower[q] < 0) continue;
         double p = 0.0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) p += sA[r * 8 + j] * sK[j * 8 + c];
-        sP[lane] = p;
+        for (int j = 0; j < 8; ++j) p += sm[q][r * 8 + j] * sm[3 + q][j * 8 + c];
+        sm[9 + q][lane] = p;
         Lt[((size_t)lt_slot[i] * 3 + q) * BS + lane] = (T)p;
-        __builtin_amdgcn_wave_barrier();
+    }
+    __builtin_amdgcn_wave_barrier();
+    double D = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (lower[q] < 0) continue;
         double q2 = 0.0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) q2 += sP[r * 8 + j] * sB[j * 8 + c];
+        for (int j = 0; j < 8; ++j) q2 += sm[9 + q][r * 8 + j] * sm[6 + q][j * 8 + c];
         D -= q2;
-        __builtin_amdgcn_wave_barrier();
     }
+    __builtin_amdgcn_wave_barrier();
+    double* sP = sm[0];
     // invert D: lanes 0..15 hold the columns of [D | I]
     sP[lane] = D;
     __builtin_amdgcn_wave_barrier();
@@ -658,7 +685,7 @@ __device__ __forceinline__ void factor_row(int32_t i, int32_t nx, int32_t ny, in
     for (int k = 0; k < 8; ++k) {
         double col[8];
 #pragma unroll
-        for (int rr = 0; rr < 8; ++rr) col[rr] = __shfl(a[rr], k);
+        for (int rr = 0; rr < 8; ++rr) col[rr] = read_lane(a[rr], k);
         int piv = k;
         double best = fabs(col[k]);
 #pragma unroll
@@ -707,7 +734,7 @@ __global__ void __launch_bounds__(256) bilu0_factor_level(
     const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
     T* __restrict__ Dinv, T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, int32_t* __restrict__ bad) {
-    __shared__ double sm[4][4][64];
+    __shared__ double sm[4][12][64];
     const int w = threadIdx.x >> 6;
     const int32_t t = blockIdx.x * 4 + w;
     if (t >= cnt) return;
@@ -725,7 +752,7 @@ __global__ void __launch_bounds__(256) bilu0_factor_syncfree(
     const int32_t* __restrict__ rows, int32_t n, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A, T* Dinv,
     T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, int32_t* __restrict__ bad, int32_t* err) {
-    __shared__ double sm[4][4][64];
+    __shared__ double sm[4][12][64];
     const int w = threadIdx.x >> 6;
     const int32_t nwave = (int32_t)gridDim.x * 4;
     for (int32_t t = (int32_t)blockIdx.x * 4 + w; t < n; t += nwave)
