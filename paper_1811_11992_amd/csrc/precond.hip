@@ -611,13 +611,17 @@ __device__ __forceinline__ double read_lane(double v, int l) {
 // flight together (Dinv holds the sentinel until a row publishes its block),
 // and D_i^-1 is published; a singular row publishes zeros so that its
 // dependants finish, and reports itself through bad.  Same arithmetic either
-// way.  sm holds 12 tiles of 64 doubles.
+// way.  The row also writes the sweep packs (the layout of form_packs): its
+// lower blocks, the upper block of each lower neighbour that points at it,
+// and D_i^-1.  sm holds 12 tiles of 64 doubles.
 template <class T, bool SF>
 __device__ __forceinline__ void factor_row(int32_t i, int32_t nx, int32_t ny, int32_t nz,
                                            const int32_t* __restrict__ row_ptr,
                                            const int32_t* __restrict__ diag_pos, const T* __restrict__ A, T* Dinv,
                                            T* __restrict__ Lt, const int32_t* __restrict__ lt_slot,
-                                           int32_t* __restrict__ bad, int32_t* err, double (*sm)[64]) {
+                                           const int32_t* __restrict__ b_slot, T* __restrict__ bpack,
+                                           T* __restrict__ spack, int32_t* __restrict__ bad, int32_t* err,
+                                           double (*sm)[64]) {
     const int lane = threadIdx.x & 63;
     const int r = lane >> 3, c = lane & 7;
     const int32_t nxy = nx * ny;
@@ -645,11 +649,15 @@ __device__ __forceinline__ void factor_row(int32_t i, int32_t nx, int32_t ny, in
 #pragma unroll
         for (int q = 0; q < 3; ++q) kv[q] = lower[q] >= 0 ? Dinv[(size_t)lower[q] * BS + lane] : T(0);
     }
+    const size_t si = (size_t)b_slot[i];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         sm[q][lane] = (double)av[q];
         sm[3 + q][lane] = (double)kv[q];
         sm[6 + q][lane] = (double)bv[q];
+        if (lower[q] < 0) continue;
+        spack[(si * 3 + q) * BS + lane] = av[q];
+        bpack[((size_t)b_slot[lower[q]] * 4 + ldir[q]) * BS + lane] = bv[q];
     }
     __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -719,10 +727,12 @@ __device__ __forceinline__ void factor_row(int32_t i, int32_t nx, int32_t ny, in
     if (lane >= 8 && lane < 16) {
 #pragma unroll
         for (int rr = 0; rr < 8; ++rr) {
+            const T v = (T)a[rr];
             if constexpr (SF)
-                publish(Dinv + (size_t)i * BS + rr * 8 + (lane - 8), (T)a[rr]);
+                publish(Dinv + (size_t)i * BS + rr * 8 + (lane - 8), v);
             else
-                Dinv[(size_t)i * BS + rr * 8 + (lane - 8)] = (T)a[rr];
+                Dinv[(size_t)i * BS + rr * 8 + (lane - 8)] = v;
+            bpack[(si * 4 + 3) * BS + rr * 8 + (lane - 8)] = v;
         }
     }
 }
@@ -733,12 +743,14 @@ template <class T>
 __global__ void __launch_bounds__(256) bilu0_factor_level(
     const int32_t* __restrict__ rows, int32_t cnt, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A,
-    T* __restrict__ Dinv, T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, int32_t* __restrict__ bad) {
+    T* __restrict__ Dinv, T* __restrict__ Lt, const int32_t* __restrict__ lt_slot,
+    const int32_t* __restrict__ b_slot, T* __restrict__ bpack, T* __restrict__ spack, int32_t* __restrict__ bad) {
     __shared__ double sm[4][12][64];
     const int w = threadIdx.x >> 6;
     const int32_t t = blockIdx.x * 4 + w;
     if (t >= cnt) return;
-    factor_row<T, false>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, bad, nullptr, sm[w]);
+    factor_row<T, false>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, b_slot, bpack, spack, bad,
+                         nullptr, sm[w]);
 }
 
 // The whole factor in one cooperative launch (every wavefront resident): the
@@ -751,12 +763,14 @@ template <class T>
 __global__ void __launch_bounds__(256) bilu0_factor_syncfree(
     const int32_t* __restrict__ rows, int32_t n, int32_t nx, int32_t ny, int32_t nz,
     const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A, T* Dinv,
-    T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, int32_t* __restrict__ bad, int32_t* err) {
+    T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, const int32_t* __restrict__ b_slot,
+    T* __restrict__ bpack, T* __restrict__ spack, int32_t* __restrict__ bad, int32_t* err) {
     __shared__ double sm[4][12][64];
     const int w = threadIdx.x >> 6;
     const int32_t nwave = (int32_t)gridDim.x * 4;
     for (int32_t t = (int32_t)blockIdx.x * 4 + w; t < n; t += nwave)
-        factor_row<T, true>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, bad, err, sm[w]);
+        factor_row<T, true>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, b_slot, bpack, spack,
+                            bad, err, sm[w]);
 }
 
 // One workgroup per brick; workgroups take tickets in brick-list order.
@@ -975,10 +989,13 @@ hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t*
             const int32_t* diag_pos = ctx->diag_pos;
             T* Lt = isc::lt_buffer<T>(ctx);
             const int32_t* lt_slot = ctx->lt_slot;
+            const int32_t* b_slot = ctx->b_slot;
+            T* bpack = isc::bpack_buffer<T>(ctx);
+            T* spack = isc::spack_buffer<T>(ctx);
             int32_t* err = ctx->flags + ISC_FLAG_SWEEP;
             void* argv[] = {(void*)&rows, (void*)&n, (void*)&nx, (void*)&ny, (void*)&nz, (void*)&row_ptr,
                             (void*)&diag_pos, (void*)&A, (void*)&Dinv, (void*)&Lt, (void*)&lt_slot,
-                            (void*)&bad_dev, (void*)&err};
+                            (void*)&b_slot, (void*)&bpack, (void*)&spack, (void*)&bad_dev, (void*)&err};
             done = hipLaunchCooperativeKernel(k, dim3(grid), dim3(256), argv, 0, ctx->stream) == hipSuccess;
             if (!done) (void)hipGetLastError();   // the level launches below
         }
@@ -988,11 +1005,11 @@ hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t*
             const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
             hipLaunchKernelGGL(isc::bilu0_factor_level<T>, dim3((cnt + 3) / 4), dim3(256), 0, ctx->stream,
                                ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
-                               ctx->diag_pos, A, Dinv, isc::lt_buffer<T>(ctx), ctx->lt_slot, bad_dev);
+                               ctx->diag_pos, A, Dinv, isc::lt_buffer<T>(ctx), ctx->lt_slot, ctx->b_slot,
+                               isc::bpack_buffer<T>(ctx), isc::spack_buffer<T>(ctx), bad_dev);
         }
     }
-    isc::launch_form_packs<T>(ctx, A, Dinv);
-    return hipGetLastError();
+    return hipGetLastError();   // the factor wrote the packs
 }
 
 template <class T, class TV>
