@@ -202,6 +202,7 @@ __global__ void __launch_bounds__(256) reduce_rows_dcgs(const double* __restrict
     const int r = blockIdx.x;
     const int row = r <= j ? r : MAXV + (r - j - 1);
     double s = 0.0;
+#pragma unroll 8
     for (int b = threadIdx.x; b < nblk; b += 256) s += partial[(size_t)row * nblk + b];
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -218,75 +219,106 @@ struct Dcgs {
     double* Rs;      // flexible variant only (else null): [m x (m+1)], column j = (s_j, omega_j)
 };
 
-// Iteration j (one thread).  c holds the dots of this iteration.  Finishes
-// the reorthogonalisation of u_j (s = Q_j^T u_j, omega = ||u_j - Q_j s|| by
-// Pythagoras), completes Hessenberg column j-1 and its Givens rotation
-// (residual estimate of a j-column solution in scal[2]), then forms the
-// first-pass coefficients of A M^-1 q_j from those of w = A M^-1 u_j:
+// Iteration j, one wavefront: lane i owns row i of the columns below (the
+// restart length is at most 31, so every row has a lane).  c holds the dots
+// of this iteration.  Finishes the reorthogonalisation of u_j (s = Q_j^T u_j,
+// omega = ||u_j - Q_j s|| by Pythagoras), completes Hessenberg column j-1 and
+// its Givens rotation (residual estimate of a j-column solution in scal[2]),
+// then forms the first-pass coefficients of A M^-1 q_j from those of
+// w = A M^-1 u_j:
 //   zeta = q_j^T w = (u_j^T w - s^T z) / omega,  z = Q_j^T w,
 //   h    = ([z; zeta] - H_j s) / omega           (H_j: columns 0..j-1).
 // scal[4] = 1 flags omega = 0 (u_j in the span of Q_j).
-__global__ void dcgs2_step(Hess hs, Dcgs d, int j, int last, const double* __restrict__ c) {
+__global__ void __launch_bounds__(64) dcgs2_step(Hess hs, Dcgs d, int j, int last, const double* __restrict__ c) {
+    __shared__ double sc[MAXV], scol[MAXV + 1], scs[MAXV], ssn[MAXV];
+    const int l = threadIdx.x;
     const int m = hs.m;
     const int ld = m + 1;
-    double ss = 0.0;
-    for (int k = 0; k < j; ++k) ss += c[k] * c[k];
-    const double om2 = c[j] - ss;
+    const double cl = l <= j ? c[l] : 0.0;
+    const double czl = (!last && l <= j) ? c[MAXV + l] : 0.0;
+    // H_j rows of this lane (columns lo..j-2 of the unrotated matrix), all loads in flight at once
+    const int lo = l > 0 ? l - 1 : 0;
+    double hr[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k)
+        hr[k] = (!last && l <= j && k >= lo && k < j - 1) ? d.Hraw[(size_t)k * ld + l] : 0.0;
+    const double hp = (j > 0 && l < j) ? d.hprev[l] : 0.0;
+    if (l < j - 1) {
+        scs[l] = hs.cs[l];
+        ssn[l] = hs.sn[l];
+    }
+    if (l < j) sc[l] = cl;
+    const double om2 = __shfl(cl, j) - wave_sum(l < j ? cl * cl : 0.0);
     if (!isfinite(om2)) {
-        hs.scal[2] = om2;
-        hs.scal[4] = 1.0;
+        if (l == 0) {
+            hs.scal[2] = om2;
+            hs.scal[4] = 1.0;
+        }
         return;
     }
     const double om = om2 > 0.0 ? sqrt(om2) : 0.0;
     if (d.Rs && j < m) {   // u_j = omega_j q_j + Q_j s_j
-        for (int i = 0; i < j; ++i) d.Rs[(size_t)j * ld + i] = c[i];
-        d.Rs[(size_t)j * ld + j] = om;
+        if (l < j) d.Rs[(size_t)j * ld + l] = cl;
+        if (l == j) d.Rs[(size_t)j * ld + j] = om;
     }
+    double rawl = 0.0;
     if (j == 0) {
-        for (int k = 0; k <= m; ++k) hs.g[k] = 0.0;
-        hs.g[0] = om;
-        hs.scal[0] = om;
-        hs.scal[2] = om;
-    } else {
-        double* raw = d.Hraw + (size_t)(j - 1) * ld;
-        for (int i = 0; i < j; ++i) raw[i] = d.hprev[i] + c[i];
-        raw[j] = om;
-        for (int i = j + 1; i <= m; ++i) raw[i] = 0.0;
-        double* col = hs.H + (size_t)(j - 1) * ld;
-        for (int i = 0; i <= j; ++i) col[i] = raw[i];
-        for (int i = 0; i < j - 1; ++i) {
-            const double a = col[i], b = col[i + 1];
-            col[i] = hs.cs[i] * a + hs.sn[i] * b;
-            col[i + 1] = -hs.sn[i] * a + hs.cs[i] * b;
+        for (int k = l; k <= m; k += 64) hs.g[k] = k == 0 ? om : 0.0;
+        if (l == 0) {
+            hs.scal[0] = om;
+            hs.scal[2] = om;
         }
-        const double a = col[j - 1], b = col[j];
-        const double den = hypot(a, b);
-        hs.cs[j - 1] = den > 0.0 ? a / den : 1.0;
-        hs.sn[j - 1] = den > 0.0 ? b / den : 0.0;
-        col[j - 1] = den;
-        col[j] = 0.0;
-        hs.g[j] = -hs.sn[j - 1] * hs.g[j - 1];
-        hs.g[j - 1] = hs.cs[j - 1] * hs.g[j - 1];
-        hs.scal[2] = fabs(hs.g[j]);
+    } else {
+        rawl = l < j ? hp + cl : (l == j ? om : 0.0);
+        if (l <= m) d.Hraw[(size_t)(j - 1) * ld + l] = rawl;
+        if (l <= j) scol[l] = rawl;
+        __syncthreads();
+        if (l == 0) {   // the earlier rotations, then a new one for rows j-1, j
+            double a = scol[0];
+            for (int i = 0; i < j - 1; ++i) {
+                const double b = scol[i + 1];
+                scol[i] = scs[i] * a + ssn[i] * b;
+                a = -ssn[i] * a + scs[i] * b;
+            }
+            const double b = scol[j];
+            const double den = hypot(a, b);
+            const double cn = den > 0.0 ? a / den : 1.0;
+            const double sn = den > 0.0 ? b / den : 0.0;
+            hs.cs[j - 1] = cn;
+            hs.sn[j - 1] = sn;
+            scol[j - 1] = den;
+            scol[j] = 0.0;
+            const double g = hs.g[j - 1];
+            hs.g[j] = -sn * g;
+            hs.g[j - 1] = cn * g;
+            hs.scal[2] = fabs(sn * g);
+        }
+        __syncthreads();
+        if (l <= j) hs.H[(size_t)(j - 1) * ld + l] = scol[l];
     }
-    hs.scal[4] = om > 0.0 ? 0.0 : 1.0;
+    if (l == 0) hs.scal[4] = om > 0.0 ? 0.0 : 1.0;
     if (last) return;
     if (!(om > 0.0)) {   // u_j lies in the span of Q_j: q_j = u_{j+1} = 0 from here on
-        for (int i = 0; i <= j; ++i) d.hprev[i] = 0.0;
-        d.omz[0] = 0.0;
-        d.omz[1] = 0.0;
+        if (l <= j) d.hprev[l] = 0.0;
+        if (l == 0) {
+            d.omz[0] = 0.0;
+            d.omz[1] = 0.0;
+        }
         return;
     }
-    double sz = 0.0;
-    for (int k = 0; k < j; ++k) sz += c[k] * c[MAXV + k];
-    const double zeta = (c[MAXV + j] - sz) / om;
-    for (int i = 0; i <= j; ++i) {
-        double v = i < j ? c[MAXV + i] : zeta;
-        for (int k = i > 0 ? i - 1 : 0; k < j; ++k) v -= d.Hraw[(size_t)k * ld + i] * c[k];
-        d.hprev[i] = v / om;
+    const double zeta = (__shfl(czl, j) - wave_sum(l < j ? cl * czl : 0.0)) / om;
+    __syncthreads();
+    if (l <= j) {
+        double v = l < j ? czl : zeta;
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k)
+            if (k >= lo && k < j) v -= (k == j - 1 ? rawl : hr[k]) * sc[k];
+        d.hprev[l] = v / om;
     }
-    d.omz[0] = om;
-    d.omz[1] = zeta;
+    if (l == 0) {
+        d.omz[0] = om;
+        d.omz[1] = zeta;
+    }
 }
 
 // Residual estimate a j-column solution would have, taking column j-1 as
@@ -516,7 +548,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
                                last ? nullptr : w2, ctx->partial);
             hipLaunchKernelGGL(reduce_rows_dcgs, dim3(last ? j + 1 : 2 * (j + 1)), dim3(256), 0, ctx->stream,
                                ctx->partial, nb2, j, red);
-            hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hs, dc, j, last ? 1 : 0, red);
+            hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(64), 0, ctx->stream, hs, dc, j, last ? 1 : 0, red);
             ISC_HIP(hipMemcpyAsync(ctx->hscratch, hs.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
             ISC_HIP(hipEventRecord(ev, ctx->stream));
             if (!fold_mode && !last)   // speculative: unused if the estimate below ends the cycle
@@ -641,7 +673,7 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
                            last ? nullptr : w2, ctx->partial);
         hipLaunchKernelGGL(reduce_rows_dcgs, dim3(last ? j + 1 : 2 * (j + 1)), dim3(256), 0, ctx->stream,
                            ctx->partial, nb2, j, red);
-        hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hi, di, j, last ? 1 : 0, red);
+        hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(64), 0, ctx->stream, hi, di, j, last ? 1 : 0, red);
         isc_prof_end(ctx, tk);
     }
     // z = M^-1 Q y = Z32 (Rs^-1 y): no further BILU(0) apply
@@ -736,7 +768,7 @@ isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, doubl
                                last ? nullptr : w2, ctx->partial);
             hipLaunchKernelGGL(reduce_rows_dcgs, dim3(last ? j + 1 : 2 * (j + 1)), dim3(256), 0, ctx->stream,
                                ctx->partial, nb2, j, red);
-            hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(1), 0, ctx->stream, hs, dc, j, last ? 1 : 0, red);
+            hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(64), 0, ctx->stream, hs, dc, j, last ? 1 : 0, red);
             ISC_HIP(hipMemcpyAsync(ctx->hscratch, hs.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
             ISC_HIP(hipEventRecord(ev, ctx->stream));
             if (!last)   // speculative: unused if the estimate below ends the cycle
