@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(256) zero_kernel(int64_t len, double* __restri
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) y[t] = 0.0;
 }
 
-// Small dense state of one GMRES cycle (device, one thread):
+// Small dense state of one GMRES cycle (device memory, updated by single-wavefront kernels):
 //   H[(m+1) x m] column-major by iteration, cs[m], sn[m], g[m+1], y[m]
 struct Hess {
     double* H; double* cs; double* sn; double* g; double* y; double* scal;
@@ -120,14 +120,27 @@ struct Hess {
 };
 // scal: [0] beta, [2] residual estimate of the current column count, [4] breakdown flag
 
-// y = R^-1 g for the leading k x k triangle
-__global__ void gmres_solve_small(Hess hs, int k) {
-    for (int i = k - 1; i >= 0; --i) {
-        double s = hs.g[i];
-        for (int l = i + 1; l < k; ++l) s -= hs.H[(size_t)l * (hs.m + 1) + i] * hs.y[l];
-        const double d = hs.H[(size_t)i * (hs.m + 1) + i];
-        hs.y[i] = d != 0.0 ? s / d : 0.0;
+// x = R^-1 rhs for the leading k x k upper triangle of R (column-major,
+// leading dimension ld, k <= MAXV), on one wavefront: lane i owns row i,
+// holding its rhs entry on entry and its x entry on return.  Column by
+// column from the last: the lane of the column divides by the diagonal (a
+// zero diagonal gives 0) and the entry, broadcast, is taken off the rows
+// above.
+__device__ __forceinline__ double upper_solve_wave(const double* __restrict__ R, int ld, int k, double rhs) {
+    const int i = threadIdx.x;
+    double r[MAXV];
+#pragma unroll
+    for (int l = 0; l < MAXV; ++l) r[l] = (i < k && l >= i && l < k) ? R[(size_t)l * ld + i] : 0.0;
+    double s = i < k ? rhs : 0.0;
+    double xi = 0.0;
+#pragma unroll
+    for (int c = MAXV - 1; c >= 0; --c) {
+        if (c >= k) continue;
+        if (i == c) xi = r[c] != 0.0 ? s / r[c] : 0.0;
+        const double xc = __shfl(xi, c);
+        if (i < c) s -= r[c] * xc;
     }
+    return xi;
 }
 
 // ------------------------------------------------------------------ DCGS2
@@ -340,17 +353,16 @@ __global__ void dcgs2_probe(Hess hs, Dcgs d, int j, const double* __restrict__ n
     hs.scal[5] = fabs(sn * hs.g[j - 1]);
 }
 
-// Flexible variant: the stored vectors are zt_j = P(u_j) = omega_j z_j +
-// Z_j s_j, i.e. Zt = Z Rs with Rs upper triangular, so Z y = Zt (Rs^-1 y);
-// y (k entries, from gmres_solve_small) is replaced by Rs^-1 y.
-__global__ void dcgs2_solve_rs(Hess hs, Dcgs d, int k) {
+// Coefficients of a cycle's solution, one wavefront.  y = R^-1 g for the
+// leading k x k triangle of the rotated Hessenberg matrix; the stored vectors
+// are zt_j = P(u_j) = omega_j z_j + Z_j s_j, i.e. Zt = Z Rs with Rs upper
+// triangular, so the solution Z y becomes Zt (Rs^-1 y): hs.y = Rs^-1 R^-1 g.
+__global__ void __launch_bounds__(64) cycle_coefficients(Hess hs, Dcgs d, int k) {
     const int ld = hs.m + 1;
-    for (int i = k - 1; i >= 0; --i) {
-        double s = hs.y[i];
-        for (int j = i + 1; j < k; ++j) s -= d.Rs[(size_t)j * ld + i] * hs.y[j];
-        const double dd = d.Rs[(size_t)i * ld + i];
-        hs.y[i] = dd != 0.0 ? s / dd : 0.0;
-    }
+    const int i = threadIdx.x;
+    double t = upper_solve_wave(hs.H, ld, k, i < k ? hs.g[i] : 0.0);
+    t = upper_solve_wave(d.Rs, ld, k, t);
+    if (i < k) hs.y[i] = t;
 }
 
 // One pass: q_j = (u - Q_j s) / omega  and  u <- (w - Q_j z - zeta q_j) / omega
@@ -582,8 +594,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
         // x += M^-1 Q_k y = Z_k (Rs^-1 y): the preconditioned lagged vectors are
         // at hand, so no further BILU(0) apply
         if (k > 0) {
-            hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hs, k);
-            hipLaunchKernelGGL(dcgs2_solve_rs, dim3(1), dim3(1), 0, ctx->stream, hs, dc, k);
+            hipLaunchKernelGGL(cycle_coefficients, dim3(1), dim3(64), 0, ctx->stream, hs, dc, k);
             hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->Z, ldv, k,
                                hs.y, x, 1);
         }
@@ -677,8 +688,7 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
         isc_prof_end(ctx, tk);
     }
     // z = M^-1 Q y = Z32 (Rs^-1 y): no further BILU(0) apply
-    hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hi, m_in);
-    hipLaunchKernelGGL(dcgs2_solve_rs, dim3(1), dim3(1), 0, ctx->stream, hi, di, m_in);
+    hipLaunchKernelGGL(cycle_coefficients, dim3(1), dim3(64), 0, ctx->stream, hi, di, m_in);
     hipLaunchKernelGGL((lincomb<float, float>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->Z32, len, m_in, hi.y,
                        ctx->t32, 0);
     hipLaunchKernelGGL(to_f64, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->t32, z);
@@ -801,8 +811,7 @@ isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, doubl
             }
         }
         if (k > 0) {   // x += Zt (Rs^-1 R^-1 g)
-            hipLaunchKernelGGL(gmres_solve_small, dim3(1), dim3(1), 0, ctx->stream, hs, k);
-            hipLaunchKernelGGL(dcgs2_solve_rs, dim3(1), dim3(1), 0, ctx->stream, hs, dc, k);
+            hipLaunchKernelGGL(cycle_coefficients, dim3(1), dim3(64), 0, ctx->stream, hs, dc, k);
             hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->Z, ldv, k,
                                hs.y, x, 1);
         }

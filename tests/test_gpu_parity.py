@@ -409,6 +409,59 @@ def test_run_c1_matches_oracle_per_step():
         assert m.scaled_norm(F, dts_g[s]) <= 1e-10
 
 
+def _dense(m, Jd):
+    """The decoupled matrix as a dense array (unit diagonal blocks)."""
+    n = m.n
+    A = np.zeros((8 * n, 8 * n))
+    for i in range(n):
+        for b in range(m.row_ptr[i], m.row_ptr[i + 1]):
+            k = m.col_idx[b]
+            A[8 * i:8 * i + 8, 8 * k:8 * k + 8] = np.eye(8) if k == i else Jd[b]
+    return A
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", ["identity", "chain", "zero_rhs"])
+def test_solve_with_exact_preconditioner_and_zero_rhs(case, precision):
+    """Breakdown paths of the Krylov step.  With no off-diagonal blocks
+    (A = I) and on a one-cell-wide chain, BILU(0) is exact (M = A), so the
+    second basis vector is zero: omega = 0 flags the breakdown and the
+    one-column solution is already exact.  A zero right-hand side returns
+    x = 0 at once.  Checked against a dense solve."""
+    from paper_1811_11992_amd import isc
+    name = "tiny:9x1x1" if case == "chain" else "tiny:4x3x2"
+    wl, m, u, F, J = _decoupled_case(name, 41)
+    st, Jd, Fd, _ = m.decouple(J, F)
+    assert st == 0
+    Jd = Jd.copy()
+    for i in range(m.n):
+        for b in range(m.row_ptr[i], m.row_ptr[i + 1]):
+            if m.col_idx[b] == i:
+                Jd[b] = np.eye(8)
+            elif case == "identity":
+                Jd[b] = 0.0
+    b = np.zeros_like(Fd) if case == "zero_rhs" else -Fd
+    kw = dict(rtol=1e-8)
+    if precision == "mixed":
+        c = ctx_for(wl, inner_iters=6)
+        kw.update(precision=isc.ISC_MIXED, inner_iters=6)
+    else:
+        c = ctx_for(wl)
+    x, info, st = c.isc_solve(dev(Jd), dev(b), isc.solve_opts(**kw))
+    assert st == 0
+    xg = host(x)
+    if case == "zero_rhs":
+        assert info.iters == 0 and np.array_equal(xg, np.zeros_like(xg))
+        return
+    x_ref = np.linalg.solve(_dense(m, Jd), b.reshape(-1)).reshape(m.n, 8)
+    err = np.abs((xg - x_ref) / COL).max() / np.abs(x_ref / COL).max()
+    if precision == "fp64":   # one column is the exact solution, up to rounding
+        assert info.iters <= 2, info.iters
+        assert info.relres_true <= 1e-10 and err <= 1e-9, (info.relres_true, err)
+    else:                     # FP32 inner solves: each outer column gains about 7 digits
+        assert info.relres_true <= 1e-8 and err <= 1e-6, (info.relres_true, err)
+
+
 # ------------------------------------------------------------ precision form
 @pytest.mark.parametrize("name,seed", [("tiny:13x7x5", 31), ("C1", 32)])
 def test_mixed_solve_reaches_fp64_tolerance(name, seed):
