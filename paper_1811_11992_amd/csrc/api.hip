@@ -367,7 +367,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->V, nv * (ctx->mmax + 1));
     ALLOC(ctx->w, nv);
     ALLOC(ctx->tvec, nv);
-    ALLOC(ctx->tvec2, nv);
+    ALLOC(ctx->acc_old, nv);
     ALLOC(ctx->partial, (size_t)65 * isc::NPART);   // 64 rows of dot partials + one norm row
     ALLOC(ctx->small, (size_t)4096 + 32 * 32);   // scalars, Hessenberg, delayed-CGS2 state; Rs past 4096
     ALLOC(ctx->flags, (size_t)16);
@@ -483,7 +483,7 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->diag_pos, ctx->well_slot, ctx->perf, ctx->lvl_rows, ctx->lt_slot, ctx->b_slot, ctx->items_rank,
                     ctx->bpack64, ctx->spack64, ctx->bpack32, ctx->spack32, ctx->payload, ctx->F,
                     ctx->J,       ctx->Dinv,  ctx->du,      ctx->rhs,    ctx->V,       ctx->Z,
-                    ctx->w,       ctx->tvec,  ctx->tvec2,   ctx->partial, ctx->small,  ctx->flags,
+                    ctx->w,       ctx->tvec,  ctx->acc_old, ctx->partial, ctx->small,  ctx->flags,
                     ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,
                     ctx->small32, ctx->Z32, ctx->accJ,   ctx->qg,     ctx->qv,     ctx->rates,
                     ctx->perf_cell, ctx->well_off, ctx->bricks_fwd, ctx->bricks_bwd, ctx->sweep64,

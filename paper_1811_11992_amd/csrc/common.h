@@ -192,7 +192,7 @@ struct isc_ctx {
     double* Z = nullptr;            // [mmax][N*8] preconditioned lagged vectors z_j = P(u_j)
     double* w = nullptr;            // [N*8]
     double* tvec = nullptr;         // [N*8]
-    double* tvec2 = nullptr;        // [N*8]
+    double* acc_old = nullptr;      // [N][8] accumulation at the previous time level (property pass)
     double* partial = nullptr;      // [65][NPART] block partial sums
     double* small = nullptr;        // device scalars: reductions, Hessenberg, Givens, g, y, delayed-CGS2 state
     int32_t* flags = nullptr;       // device ints: [0] error/bad cell

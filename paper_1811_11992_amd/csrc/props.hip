@@ -254,10 +254,28 @@ __device__ __forceinline__ void put(double* rec, G1 x, int k) {
     if (k == 0) rec[0] = x.v;
 }
 
+// Accumulation at the previous time level (values only), one thread per
+// cell: acc_old[i][e].  The property pass reads it instead of evaluating it
+// on each of a cell's eight lanes.
+__global__ void __launch_bounds__(256) acc_old_kernel(int32_t n, const double* __restrict__ u_old,
+                                                      const double* __restrict__ poro,
+                                                      const isc_fluid* __restrict__ fl,
+                                                      double* __restrict__ acc_old) {
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n) return;
+    double uo[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) uo[q] = u_old[(size_t)q * n + i];
+    Cell<double> co;
+    cell_eval<double>(*fl, poro[i], uo, co);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc_old[(size_t)i * 8 + e] = co.acc[e];
+}
+
 // Eight lanes per cell (lane k of a cell carries d/du_k): local residual terms
 // with their derivatives and the flux payload.  vol_dt = V/dt, vol = V.
-__global__ void __launch_bounds__(256) props_kernel(
-    int32_t n, const double* __restrict__ u, const double* __restrict__ u_old, double vol_dt,
+__global__ void __launch_bounds__(256, 2) props_kernel(
+    int32_t n, const double* __restrict__ u, const double* __restrict__ acc_old_in, double vol_dt,
     double vol, const double* __restrict__ poro, const int32_t* __restrict__ well_slot,
     const double* __restrict__ perf, const isc_fluid* __restrict__ fl, double* __restrict__ payload) {
     const int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
@@ -267,17 +285,9 @@ __global__ void __launch_bounds__(256) props_kernel(
     const double phi_ref = poro[i];
     double* out = payload + (size_t)i * PL;
 
-    // accumulation at the previous time level (values only)
     double acc_old[8];
-    {
-        double uo[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) uo[q] = u_old[(size_t)q * n + i];
-        Cell<double> co;
-        cell_eval<double>(f, phi_ref, uo, co);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) acc_old[e] = co.acc[e];
-    }
+    for (int e = 0; e < 8; ++e) acc_old[e] = acc_old_in[(size_t)i * 8 + e];
 
     G1 ug[8];
 #pragma unroll
@@ -362,10 +372,12 @@ hipError_t isc_launch_accgrad(isc_ctx* ctx, const double* u) {
 
 hipError_t isc_launch_props(isc_ctx* ctx, const double* u, const double* u_old, double dt) {
     const double vol = ctx->g.dx * ctx->g.dy * ctx->g.dz;
+    hipLaunchKernelGGL(isc::acc_old_kernel, dim3((ctx->n + 255) / 256), dim3(256), 0, ctx->stream, ctx->n, u_old,
+                       ctx->poro, ctx->fluid_d, ctx->acc_old);
     const int threads = 256;                      // 32 cells x 8 lanes
     const int blocks = (int)(((int64_t)ctx->n * 8 + threads - 1) / threads);
     hipLaunchKernelGGL(isc::props_kernel, dim3(blocks), dim3(threads), 0, ctx->stream, ctx->n, u,
-                       u_old, vol / dt, vol, ctx->poro, ctx->well_slot, ctx->perf, ctx->fluid_d,
+                       ctx->acc_old, vol / dt, vol, ctx->poro, ctx->well_slot, ctx->perf, ctx->fluid_d,
                        ctx->payload);
     return hipGetLastError();
 }
