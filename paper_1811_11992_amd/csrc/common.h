@@ -29,6 +29,14 @@ constexpr int BRICK_THREADS = BRICK_X * BRICK_Y * BRICK_Z * 8;
 // (the work lists are padded for two)
 constexpr int MAX_BRICKS_PER_WG = 2;
 
+// Lane l's value, read into a scalar register (l the same on every lane).
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // The delayed Gram-Schmidt update of the previous GMRES iteration, done by
 // the forward sweep for its own rows before sweeping:
 //   q_{j-1} = (u - sum_{k<j-1} s_k Q_k) / omega,

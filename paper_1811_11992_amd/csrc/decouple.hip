@@ -7,7 +7,7 @@
 //
 // Mapping: one wavefront per block row; lane c holds augmented column c
 // (8 values), so a row exchange is a register swap inside each lane and the
-// pivot column is broadcast from lane k by shuffles.
+// pivot column is read from lane k into scalar registers.
 #include "common.h"
 
 namespace isc {
@@ -47,8 +47,8 @@ __global__ void __launch_bounds__(256) decouple_kernel(int32_t n, const int32_t*
     for (int k = 0; k < 8; ++k) {
         double col[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) col[r] = __shfl(a[r], k);
-        const double cm = __shfl(cmax, k);
+        for (int r = 0; r < 8; ++r) col[r] = read_lane(a[r], k);
+        const double cm = read_lane(cmax, k);
         int piv = k;
         double best = fabs(col[k]);
 #pragma unroll

@@ -595,14 +595,6 @@ __device__ __forceinline__ void spmv_lower_brick(int32_t rank, int32_t b, int32_
     if (act) w[(size_t)ii * NU + r] = (TV)acc;
 }
 
-// Lane l's value, read into a scalar register (l the same on every lane).
-__device__ __forceinline__ double read_lane(double v, int l) {
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
 // One row of the factor, one wavefront, lane (r, c): D_i = I - sum_k Lt_ik A_ki
 // with Lt_ik = A_ik D_k^-1 for the lower neighbours k (stored in sweep order),
 // then D_i^-1 by Gauss-Jordan with partial pivoting, a column per lane.  The
