@@ -34,6 +34,22 @@
  *   synchronise that stream before returning.  A context is not thread-safe.
  *   Errors: every function returns an isc_status; on error the outputs are
  *   undefined and isc_last_error() describes the failure.
+ *
+ * Schedules
+ *   The BILU(0) factor and the triangular sweeps of its apply run as single
+ *   launches in which each row (factor) or brick of cells (sweeps) waits for
+ *   the rows it depends on; every such wait is bounded in wall-clock time.  A
+ *   wait that runs out ends the launch early and the call returns ISC_ERR_HIP
+ *   ("a row waited too long"); the context stays usable.  Every schedule
+ *   computes the natural-order factorisation and its apply bit for bit alike.
+ *   Environment switches, read by isc_create:
+ *     ISC_LEVEL_SWEEPS=1      one launch per hyperplane ix+iy+iz = s instead;
+ *     ISC_SWEEP_COOP=0        workgroups take sweep work by ticket instead of
+ *                             the static cooperative order;
+ *     ISC_BRICKS_PER_WG=2     two bricks per workgroup (ticket order only);
+ *     ISC_FOLD_UPDATE=1       the FP64 GMRES does its Gram-Schmidt update inside
+ *                             the next forward sweep;
+ *     ISC_SWEEP_WAIT_TICKS=t  the wait limit in 100 MHz wall-clock ticks.
  */
 #ifndef ISC_H
 #define ISC_H
@@ -186,6 +202,9 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
 
 /* Component steps exposed for testing and profiling. */
 isc_status isc_spmv(isc_ctx* ctx, const double* Jdec, const double* x, double* y);
+/* D^-1 of the block ILU(0) of Jdec in natural cell order (D-ILU form:
+ * D_i = I - sum over lower neighbours k of A_ik D_k^-1 A_ki).  A singular D_i
+ * returns ISC_ERR_SINGULAR, naming the lowest such cell in the error text. */
 isc_status isc_bilu0(isc_ctx* ctx, const double* Jdec, double* Dinv /* [N][8][8] */);
 isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv, const double* r,
                            double* z);
