@@ -453,6 +453,7 @@ __device__ __forceinline__ void fwd_brick(int32_t pos, int32_t b, int32_t nbx, i
         const int buf = s & 1;
         L.v[buf][me] = yout;
         __syncthreads();
+        if (bc.step != s) continue;   // a wavefront with no cell on this step skips it
         double acc = rv;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
@@ -462,7 +463,7 @@ __device__ __forceinline__ void fwd_brick(int32_t pos, int32_t b, int32_t nbx, i
 #pragma unroll
             for (int c = 0; c < 8; ++c) acc -= arow[q][c] * x[c];
         }
-        if (bc.step == s) yout = acc;
+        yout = acc;
     }
     if (act) publish(y + (size_t)ii * NU + r, (TV)yout);
 }
@@ -519,6 +520,7 @@ __device__ __forceinline__ void bwd_brick(int32_t rank, int32_t b, int32_t nbx, 
         const int buf = s & 1;
         L.v[buf][me] = zout;
         __syncthreads();
+        if (mystep != s) continue;   // a wavefront with no cell on this step skips it
         // (U z)_i on its own: the fused SpMV reuses it without cancellation
         double su = 0.0;
 #pragma unroll
@@ -537,10 +539,8 @@ __device__ __forceinline__ void bwd_brick(int32_t rank, int32_t b, int32_t nbx, 
         double t = 0.0;
 #pragma unroll
         for (int c = 0; c < 8; ++c) t += drow[c] * a8[c];
-        if (mystep == s) {
-            zout = t;
-            uz = su;
-        }
+        zout = t;
+        uz = su;
         wave_lds_sync();
     }
     if (act) publish(z + (size_t)ii * NU + r, (TV)zout);
