@@ -154,7 +154,8 @@ struct isc_ctx {
     // brick cells + its index in the brick, so the sweep streams them
     int32_t* lt_slot = nullptr;
     // The backward sweep's blocks (U x+, U y+, U z+, D^-1) and the SpMV's lower
-    // blocks (z-, y-, x-) are copied, when the factor is formed, into packs in
+    // blocks (z-, y-, x-) are written by the factor (or copied for a factor
+    // given from outside) into packs in
     // backward-list order: cell i at slot b_slot[i] (its brick's position in
     // the backward list x brick cells + its index in the brick).  items_rank
     // gives each fused work item that position.

@@ -214,10 +214,14 @@ __global__ void __launch_bounds__(256) spmv_unitdiag(int32_t n, const int32_t* _
 }
 
 // ------------------------------------------------------------ sync-free sweeps
-// One kernel per triangular sweep.  The grid is cut into 2x2x2 bricks (one
-// wavefront each), the bricks are listed by brick level bx + by + bz, and each
-// workgroup takes a ticket in that order, so every brick a wavefront waits for
-// belongs to a wavefront that is already running or finished.  No flags: the
+// One kernel per triangular sweep.  The grid is cut into bricks of
+// BRICK_X x BRICK_Y x BRICK_Z cells (4x4x2: one workgroup of 256 threads, eight
+// per cell), the bricks are listed by brick level bx + by + bz, and the
+// workgroups take them in that order: statically under a cooperative launch
+// (workgroup b takes entries b, b + grid, ...) or by ticket, so every brick a
+// workgroup waits for belongs to one that is already running or finished.
+// Inside a brick the cells go through in wavefront steps dx + dy + dz over
+// LDS.  No flags: the
 // sweep's output buffer holds a NaN sentinel before the sweep, a row's result
 // is published with device-coherent 64-/32-bit stores, and a consumer lane
 // polls its element of each predecessor with device-coherent loads until the
@@ -765,7 +769,8 @@ __global__ void __launch_bounds__(256) bilu0_factor_syncfree(
                             bad, err, sm[w]);
 }
 
-// One workgroup per brick; workgroups take tickets in brick-list order.
+// One workgroup per group of BPW bricks, taken in brick-list order (statically
+// under a cooperative launch, else by ticket).
 template <class T, class TV, int BPW, bool STATIC>
 __global__ void __launch_bounds__(BRICK_THREADS * BPW) bilu0_fwd_syncfree(
     const int32_t* __restrict__ bricks, int32_t ngroup, int32_t nbx, int32_t nby, int32_t nx, int32_t ny, int32_t nz,
@@ -874,7 +879,7 @@ hipError_t isc_reset_sweep_buffers(isc_ctx* ctx) {
 // ------------------------------------------------------------------ launchers
 
 // One launch of each sync-free sweep kernel with `BPW` bricks per workgroup
-// (the context's choice); each workgroup takes one ticket.
+// (the context's choice); each workgroup takes one group of the list at a time.
 namespace {
 int32_t bricks_x(const isc_ctx* ctx) { return (ctx->g.nx + isc::BRICK_X - 1) / isc::BRICK_X; }
 int32_t bricks_y(const isc_ctx* ctx) { return (ctx->g.ny + isc::BRICK_Y - 1) / isc::BRICK_Y; }
