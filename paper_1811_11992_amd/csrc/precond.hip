@@ -22,6 +22,8 @@
 // products and a column-per-lane Gauss-Jordan inverse; sweeps - one workgroup
 // per brick, eight lanes per cell; SpMV - eight lanes per block row, lane r
 // owns output row r.
+#include <type_traits>
+
 #include "common.h"
 
 namespace isc {
@@ -609,11 +611,13 @@ __device__ __forceinline__ void spmv_lower_brick(int32_t rank, int32_t b, int32_
 // dependants finish, and reports itself through bad.  Same arithmetic either
 // way.  The row also writes the sweep packs (the layout of form_packs): its
 // lower blocks, the upper block of each lower neighbour that points at it,
-// and D_i^-1.  sm holds 12 tiles of 64 doubles.
-template <class T, bool SF>
+// and D_i^-1.  sm holds 12 tiles of 64 doubles.  The matrix may come in a
+// wider type TA than the factor's storage T: its blocks are then rounded to T
+// as they are loaded, the values a converted copy would hold.
+template <class TA, class T, bool SF>
 __device__ __forceinline__ void factor_row(int32_t i, int32_t nx, int32_t ny, int32_t nz,
                                            const int32_t* __restrict__ row_ptr,
-                                           const int32_t* __restrict__ diag_pos, const T* __restrict__ A, T* Dinv,
+                                           const int32_t* __restrict__ diag_pos, const TA* __restrict__ A, T* Dinv,
                                            T* __restrict__ Lt, const int32_t* __restrict__ lt_slot,
                                            const int32_t* __restrict__ b_slot, T* __restrict__ bpack,
                                            T* __restrict__ spack, int32_t* __restrict__ bad, int32_t* err,
@@ -630,8 +634,8 @@ __device__ __forceinline__ void factor_row(int32_t i, int32_t nx, int32_t ny, in
     for (int q = 0; q < 3; ++q) {
         av[q] = bv[q] = T(0);
         if (lower[q] < 0) continue;
-        av[q] = A[(size_t)blk * BS + lane];   // A_ik: the row's lower blocks come first, in this order
-        bv[q] = A[(size_t)upper_block(lower[q], ldir[q], nx, ny, nz, diag_pos) * BS + lane];   // A_ki
+        av[q] = (T)A[(size_t)blk * BS + lane];   // A_ik: the row's lower blocks come first, in this order
+        bv[q] = (T)A[(size_t)upper_block(lower[q], ldir[q], nx, ny, nz, diag_pos) * BS + lane];   // A_ki
         ++blk;
     }
     if constexpr (SF) {
@@ -745,8 +749,8 @@ __global__ void __launch_bounds__(256) bilu0_factor_level(
     const int w = threadIdx.x >> 6;
     const int32_t t = blockIdx.x * 4 + w;
     if (t >= cnt) return;
-    factor_row<T, false>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, b_slot, bpack, spack, bad,
-                         nullptr, sm[w]);
+    factor_row<T, T, false>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, b_slot, bpack, spack,
+                            bad, nullptr, sm[w]);
 }
 
 // The whole factor in one cooperative launch (every wavefront resident): the
@@ -755,18 +759,24 @@ __global__ void __launch_bounds__(256) bilu0_factor_level(
 // wavefront has finished its earlier rows, so it is working on that row, and
 // the rows it waits for lie on earlier hyperplanes: no deadlock.  Dinv must
 // hold the sentinel on entry.
-template <class T>
+template <class TA, class T>
 __global__ void __launch_bounds__(256) bilu0_factor_syncfree(
     const int32_t* __restrict__ rows, int32_t n, int32_t nx, int32_t ny, int32_t nz,
-    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const T* __restrict__ A, T* Dinv,
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos, const TA* __restrict__ A, T* Dinv,
     T* __restrict__ Lt, const int32_t* __restrict__ lt_slot, const int32_t* __restrict__ b_slot,
     T* __restrict__ bpack, T* __restrict__ spack, int32_t* __restrict__ bad, int32_t* err) {
     __shared__ double sm[4][12][64];
     const int w = threadIdx.x >> 6;
     const int32_t nwave = (int32_t)gridDim.x * 4;
     for (int32_t t = (int32_t)blockIdx.x * 4 + w; t < n; t += nwave)
-        factor_row<T, true>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, b_slot, bpack, spack,
-                            bad, err, sm[w]);
+        factor_row<TA, T, true>(rows[t], nx, ny, nz, row_ptr, diag_pos, A, Dinv, Lt, lt_slot, b_slot, bpack, spack,
+                                bad, err, sm[w]);
+}
+
+// b = a, element by element, in b's type
+template <class TA, class T>
+__global__ void __launch_bounds__(256) convert_copy(int64_t len, const TA* __restrict__ a, T* __restrict__ b) {
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) b[t] = (T)a[t];
 }
 
 // One workgroup per group of BPW bricks, taken in brick-list order (statically
@@ -963,8 +973,12 @@ void launch_bwd_spmv(isc_ctx* ctx, TV* v, TV* z, TV* w) {
 }
 }  // namespace
 
-template <class T>
-hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t* bad_dev) {
+// The factor of A (type TA) stored in T.  With TA wider than T, At receives A
+// converted to T only if the per-hyperplane schedule runs (its sweeps read
+// the converted matrix); the sync-free factor rounds the blocks as it loads
+// them and leaves At alone.
+template <class TA, class T>
+hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const TA* A, T* Dinv, int32_t* bad_dev, T* At) {
     bool done = false;
     if (ctx->syncfree) {   // one cooperative launch; Dinv starts as the sentinel
         const int64_t len = (int64_t)ctx->n * isc::BS;
@@ -975,7 +989,7 @@ hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t*
         else
             hipLaunchKernelGGL((isc::fill_bits<unsigned int>), dim3(nb), dim3(256), 0, ctx->stream, len,
                                reinterpret_cast<unsigned int*>(Dinv), (unsigned int)isc::SENTINEL32);
-        const void* k = reinterpret_cast<const void*>(&isc::bilu0_factor_syncfree<T>);
+        const void* k = reinterpret_cast<const void*>(&isc::bilu0_factor_syncfree<TA, T>);
         const int32_t cap = coresident(ctx, k, 256);
         if (cap > 0) {
             const int32_t rows_n = ctx->n;
@@ -998,11 +1012,19 @@ hipError_t isc_launch_bilu0_factor_t(isc_ctx* ctx, const T* A, T* Dinv, int32_t*
         }
     }
     if (!done) {
+        const T* Al;
+        if constexpr (std::is_same<TA, T>::value) {
+            Al = A;
+        } else {
+            const int64_t len = (int64_t)ctx->nnzb * isc::BS;
+            hipLaunchKernelGGL((isc::convert_copy<TA, T>), dim3(2048), dim3(256), 0, ctx->stream, len, A, At);
+            Al = At;
+        }
         for (int32_t s = 0; s < ctx->nlev; ++s) {
             const int32_t off = ctx->lvl_off_h[s], cnt = ctx->lvl_off_h[s + 1] - off;
             hipLaunchKernelGGL(isc::bilu0_factor_level<T>, dim3((cnt + 3) / 4), dim3(256), 0, ctx->stream,
                                ctx->lvl_rows + off, cnt, ctx->g.nx, ctx->g.ny, ctx->g.nz, ctx->row_ptr,
-                               ctx->diag_pos, A, Dinv, isc::lt_buffer<T>(ctx), ctx->lt_slot, ctx->b_slot,
+                               ctx->diag_pos, Al, Dinv, isc::lt_buffer<T>(ctx), ctx->lt_slot, ctx->b_slot,
                                isc::bpack_buffer<T>(ctx), isc::spack_buffer<T>(ctx), bad_dev);
         }
     }
@@ -1094,10 +1116,12 @@ hipError_t isc_launch_spmv_t(isc_ctx* ctx, const T* A, const TV* x, TV* y) {
 }
 
 hipError_t isc_launch_bilu0_factor(isc_ctx* ctx, const double* A, double* Dinv, int32_t* bad) {
-    return isc_launch_bilu0_factor_t<double>(ctx, A, Dinv, bad);
+    return isc_launch_bilu0_factor_t<double, double>(ctx, A, Dinv, bad, nullptr);
 }
-hipError_t isc_launch_bilu0_factor32(isc_ctx* ctx, const float* A, float* Dinv, int32_t* bad) {
-    return isc_launch_bilu0_factor_t<float>(ctx, A, Dinv, bad);
+// FP32 factor of the FP64 matrix A; A32 gets A in FP32 when the
+// per-hyperplane schedule needs it (see isc_launch_bilu0_factor_t).
+hipError_t isc_launch_bilu0_factor32_from64(isc_ctx* ctx, const double* A, float* A32, float* Dinv, int32_t* bad) {
+    return isc_launch_bilu0_factor_t<double, float>(ctx, A, Dinv, bad, A32);
 }
 // Lt of the context from a factor computed elsewhere (FP64).
 hipError_t isc_launch_form_ltilde(isc_ctx* ctx, const double* A, const double* Dinv) {

@@ -463,11 +463,15 @@ def test_solve_with_exact_preconditioner_and_zero_rhs(case, precision):
 
 
 # ------------------------------------------------------------ precision form
+@pytest.mark.parametrize("level", ["0", "1"])
 @pytest.mark.parametrize("name,seed", [("tiny:13x7x5", 31), ("C1", 32)])
-def test_mixed_solve_reaches_fp64_tolerance(name, seed):
+def test_mixed_solve_reaches_fp64_tolerance(name, seed, level, monkeypatch):
     """FP32 BILU(0) + FP32 inner GMRES inside FP64 FGMRES(30): the FP64 true
-    residual still meets 1e-8 and the solution matches a tight FP64 solve."""
+    residual still meets 1e-8 and the solution matches a tight FP64 solve.
+    Under both schedules: the sync-free factor rounds the FP64 blocks as it
+    loads them, the per-hyperplane one factors an FP32 copy of the matrix."""
     from paper_1811_11992_amd import isc
+    monkeypatch.setenv("ISC_LEVEL_SWEEPS", level)
     wl, m, u, F, J = _decoupled_case(name, seed)
     st, Jd, Fd, _ = m.decouple(J, F)
     b = -Fd
