@@ -328,6 +328,31 @@ def test_bilu0_is_exact_on_one_dimensional_grids(nx):
     assert info.iters == 1 and info.relres_true <= 1e-14
 
 
+def test_bilu0_reports_the_first_singular_pivot():
+    """A column of three cells with identity couplings: D_0 = I and
+    D_1 = I - A_10 D_0^-1 A_01 = I - I = 0, so the factor stops at cell 1 with
+    the singular status; with couplings 0.5 I instead, D_1 = 0.75 I and
+    D_2 = I - 0.25 D_1^-1 = (2/3) I (closed forms)."""
+    wl = I.make_workload("tiny:1x1x3")
+    m = O.Model(wl)
+    nnzb = m.row_ptr[-1]
+    Jd = np.zeros((nnzb, 8, 8))
+    Jd[:] = np.eye(8)
+    st, LU, Dinv = m.bilu0(Jd)
+    assert st == -4
+    Jd[:] = 0.5 * np.eye(8)
+    for i in range(m.n):
+        for b in range(m.row_ptr[i], m.row_ptr[i + 1]):
+            if m.col_idx[b] == i:
+                Jd[b] = np.eye(8)
+    st, LU, Dinv = m.bilu0(Jd)
+    assert st == 0
+    Dinv = Dinv.reshape(m.n, 8, 8)
+    assert np.allclose(Dinv[0], np.eye(8), rtol=0, atol=1e-15)
+    assert np.allclose(Dinv[1], np.eye(8) / 0.75, rtol=1e-15, atol=0)
+    assert np.allclose(Dinv[2], np.eye(8) * 1.5, rtol=1e-15, atol=1e-15)
+
+
 def test_bilu0_factors_reproduce_matrix_on_pattern():
     """ILU(0): (L + I) U equals A on every stored block."""
     wl = I.make_workload("tiny:4x3x2")
