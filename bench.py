@@ -233,6 +233,39 @@ def adjoint_cost(name="C4", nsteps=20, every=5):
             "gradient_finite": ok}
 
 
+def bicgstab_cost(name="C3", reps=2):
+    """The paper's Krylov method beside GMRES(30) on the benchmark's first
+    linear system: the decoupled system of the first Newton iteration, both
+    with BILU(0) (factor included), FP64, to 1e-8.  Iterations, true relative
+    residual and wall time of the last of `reps` solves of each.  Not part of
+    the default run; call it as bench.bicgstab_cost()."""
+    import torch
+    from paper_1811_11992_amd import inputs as I
+    from paper_1811_11992_amd import isc
+    wl = I.make_workload(name)
+    ctx = isc.Context(wl)
+    u = torch.tensor(wl.u0, dtype=torch.float64, device="cuda")
+    F, J = ctx.isc_assemble(u, u, wl.dt)
+    ctx.isc_decouple(J, F)
+    b = -F
+    out = {"workload": f"{name}: {wl.nx}x{wl.ny}x{wl.nz}, first Newton iteration's decoupled system",
+           "cells": wl.ncell}
+    for label in ("gmres30", "bicgstab"):
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if label == "gmres30":
+                x, info, st = ctx.isc_solve(J, b, isc.solve_opts(rtol=1e-8))
+            else:
+                x, info, st = ctx.isc_solve_bicgstab(J, b, rtol=1e-8)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        out[label] = {"iters": info.iters, "relres_true": info.relres_true, "ms": round((t1 - t0) * 1e3, 2)}
+    del ctx
+    gc.collect()
+    return out
+
+
 def launch_bytes(nbytes, prof, vec, n):
     """Algorithmic bytes per launch of each class: the fixed pattern plus
     the average number of extra full-length vectors per launch that the

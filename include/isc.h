@@ -193,6 +193,21 @@ isc_status isc_decouple(isc_ctx* ctx, double* Jval, double* F, int32_t* bad_cell
 isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* x,
                      const isc_solve_opts* opts_h, isc_solve_info* info_h);
 
+/* Solve Jdec x = b (decoupled matrix, unit diagonal blocks) with
+ * right-preconditioned BiCGSTAB and block ILU(0) from x0 = 0: the
+ * stabilised bi-conjugate gradient method of the paper's experiments
+ * (Section 4, where it runs with RAS or CPR-PF preconditioning).  Stops when
+ * the updated residual meets ||r||_2 <= rtol ||b||_2, then checks the true
+ * residual and, if it is still above, restarts from it.  b, x: [N][8]
+ * (distinct).  Uses seven of the context's Krylov vectors (max restart >= 6).
+ * info_h (may be NULL): iters = iterations (two preconditioned products
+ * each), restarts, relres_est = the last updated residual / ||b||,
+ * relres_true.  Returns ISC_ERR_LINEAR_NOCONV after max_iters iterations or a
+ * breakdown (rho = 0, (r~, v) = 0, (t, t) = 0 or omega = 0) unless the true
+ * residual already meets the tolerance; ISC_ERR_SINGULAR from the factor. */
+isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b, double* x,
+                              int32_t max_iters, double rtol, isc_solve_info* info_h);
+
 /* One Newton iteration at (u, u_old, dt): assemble, scaled-norm test (if
  * res <= tol: converged = 1, u unchanged), else decouple, BILU(0), GMRES and
  * the safeguarded update of u in place (saturation halving rule of the PER

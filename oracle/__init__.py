@@ -74,6 +74,8 @@ def lib():
         L.orc_spmv.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
         L.orc_gmres.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_double, ctypes.POINTER(SolveInfo)]
+        L.orc_bicgstab.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.POINTER(SolveInfo)]
         L.orc_scaled_norm.restype = ctypes.c_double
         L.orc_scaled_norm.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
         L.orc_update.argtypes = [ctypes.c_void_p, _dp, _dp]
@@ -199,6 +201,13 @@ class Model:
         info = SolveInfo()
         st = lib().orc_gmres(self.h, _p(np.ascontiguousarray(Jdec)), _p(np.ascontiguousarray(b, np.float64)),
                              _p(x), restart, max_restarts, rtol, ctypes.byref(info))
+        return st, x, info
+
+    def bicgstab(self, Jdec, b, max_iters=1000, rtol=1e-8):
+        x = np.zeros((self.n, 8))
+        info = SolveInfo()
+        st = lib().orc_bicgstab(self.h, _p(np.ascontiguousarray(Jdec)), _p(np.ascontiguousarray(b, np.float64)),
+                                _p(x), max_iters, rtol, ctypes.byref(info))
         return st, x, info
 
     def scaled_norm(self, F, dt):

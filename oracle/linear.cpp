@@ -295,6 +295,96 @@ int orc_gmres(orc_model* m, const double* A, const double* b, double* x, int32_t
     return status;
 }
 
+/* Right-preconditioned BiCGSTAB (van der Vorst's stabilised bi-conjugate
+ * gradients; the Krylov method of the paper's experiments) with block ILU(0),
+ * x0 = 0.  Each iteration applies A M^-1 twice:
+ *   p = r + beta (p - omega v),  p^ = M^-1 p,  v = A p^,  alpha = rho / (r~, v),
+ *   s = r - alpha v,  s^ = M^-1 s,  t = A s^,  omega = (t, s) / (t, t),
+ *   x += alpha p^ + omega s^,  r = s - omega t,  rho' = (r~, r),
+ *   beta' = (rho' / rho) (alpha / omega),
+ * with the shadow vector r~ = the starting residual.  The iteration stops once
+ * the updated residual (s at the half step, else r) satisfies
+ * ||.|| <= rtol ||b||; then the true residual b - A x is formed, and if it is
+ * still above the tolerance the iteration starts again from it.  Returns 0,
+ * or -6 (no convergence within max_iters, or a breakdown: rho = 0,
+ * (r~, v) = 0, (t, t) = 0 or omega = 0). */
+int orc_bicgstab(orc_model* m, const double* A, const double* b, double* x, int32_t max_iters, double rtol,
+                 orc_solve_info* info) {
+    const size_t N = (size_t)m->n * 8;
+    std::vector<double> LU((size_t)m->row_ptr[m->n] * 64), Dinv((size_t)m->n * 64);
+    int st = orc_bilu0(m, A, LU.data(), Dinv.data());
+    if (st) return st;
+    std::vector<double> bb(b, b + N), r(N), rs(N), p(N), v(N), s(N), t(N), ph(N), sh(N), tmp(N);
+    std::fill(x, x + N, 0.0);
+    const double bnorm = nrm2(bb);
+    orc_solve_info inf;
+    std::memset(&inf, 0, sizeof(inf));
+    if (bnorm == 0.0) {
+        if (info) *info = inf;
+        return 0;
+    }
+    const double tol = rtol * bnorm;
+    int status = -6, it = 0, starts = 0;
+    while (it < max_iters) {
+        orc_spmv(m, A, x, tmp.data());
+        for (size_t k = 0; k < N; ++k) r[k] = bb[k] - tmp[k];
+        const double rn0 = nrm2(r);
+        inf.relres_true = rn0 / bnorm;
+        if (rn0 <= tol) { status = 0; break; }
+        inf.restarts = starts++;
+        rs = r;
+        std::fill(p.begin(), p.end(), 0.0);
+        std::fill(v.begin(), v.end(), 0.0);
+        double rho_old = 1.0, alpha = 1.0, omega = 1.0, rho = dot(rs, r);
+        bool converged = false;
+        while (it < max_iters) {
+            if (rho == 0.0 || !std::isfinite(rho)) break;
+            const double beta = (rho / rho_old) * (alpha / omega);
+            for (size_t k = 0; k < N; ++k) p[k] = r[k] + beta * (p[k] - omega * v[k]);
+            orc_bilu0_apply(m, LU.data(), Dinv.data(), p.data(), ph.data());
+            orc_spmv(m, A, ph.data(), v.data());
+            const double rv = dot(rs, v);
+            if (rv == 0.0 || !std::isfinite(rv)) break;
+            alpha = rho / rv;
+            for (size_t k = 0; k < N; ++k) s[k] = r[k] - alpha * v[k];
+            ++it;
+            const double sn = nrm2(s);
+            inf.relres_est = sn / bnorm;
+            if (sn <= tol) {
+                for (size_t k = 0; k < N; ++k) x[k] += alpha * ph[k];
+                converged = true;
+                break;
+            }
+            orc_bilu0_apply(m, LU.data(), Dinv.data(), s.data(), sh.data());
+            orc_spmv(m, A, sh.data(), t.data());
+            const double tt = dot(t, t);
+            if (tt == 0.0 || !std::isfinite(tt)) break;
+            omega = dot(t, s) / tt;
+            for (size_t k = 0; k < N; ++k) {
+                x[k] += alpha * ph[k] + omega * sh[k];
+                r[k] = s[k] - omega * t[k];
+            }
+            const double rn = nrm2(r);
+            inf.relres_est = rn / bnorm;
+            if (rn <= tol) { converged = true; break; }
+            if (omega == 0.0) break;
+            rho_old = rho;
+            rho = dot(rs, r);
+        }
+        if (!converged) break;
+    }
+    if (status != 0) {
+        orc_spmv(m, A, x, tmp.data());
+        double q = 0.0;
+        for (size_t k = 0; k < N; ++k) q += (bb[k] - tmp[k]) * (bb[k] - tmp[k]);
+        inf.relres_true = std::sqrt(q) / bnorm;
+        if (inf.relres_true <= rtol) status = 0;
+    }
+    inf.iters = it;
+    if (info) *info = inf;
+    return status;
+}
+
 /* Convergence measure: max over cells and rows of |F| / s, with
  * s = V phi_ref rho_ref,W / dt for molar and coke rows and
  * s = V (1 - phi_ref) cp_rock (1 K) / dt for the energy row. */

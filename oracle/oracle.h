@@ -103,6 +103,9 @@ void orc_bilu0_apply(orc_model* m, const double* LU, const double* Dinv, const d
 void orc_spmv(orc_model* m, const double* J, const double* x, double* y);
 int orc_gmres(orc_model* m, const double* Jdec, const double* b, double* x, int32_t restart,
               int32_t max_restarts, double rtol, orc_solve_info* info);
+/* right-preconditioned BiCGSTAB with block ILU(0), x0 = 0; returns 0 or -6 */
+int orc_bicgstab(orc_model* m, const double* Jdec, const double* b, double* x, int32_t max_iters, double rtol,
+                 orc_solve_info* info);
 /* scaled max-norm of F for convergence */
 double orc_scaled_norm(orc_model* m, const double* F, double dt);
 /* Newton update with the saturation/fraction safeguards; returns 0 or -5 (non-finite) */

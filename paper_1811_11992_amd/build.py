@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libisc.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["props.hip", "assemble.hip", "decouple.hip", "precond.hip", "krylov.hip", "newton.hip",
+SOURCES = ["props.hip", "assemble.hip", "decouple.hip", "precond.hip", "krylov.hip", "bicgstab.hip", "newton.hip",
            "mixed.hip", "adjoint.hip", "api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (hipcc's host pass warns about the

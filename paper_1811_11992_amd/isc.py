@@ -66,6 +66,8 @@ def lib():
         L.isc_assemble.argtypes = [_vp, _vp, _vp, _f64, _vp, _vp]
         L.isc_decouple.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_i32)]
         L.isc_solve.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveInfo)]
+        L.isc_solve_bicgstab.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_double,
+                                         ctypes.POINTER(SolveInfo)]
         L.isc_newton_step.argtypes = [_vp, _vp, _vp, _f64, ctypes.POINTER(NewtonOpts), ctypes.POINTER(NewtonInfo)]
         L.isc_spmv.argtypes = [_vp, _vp, _vp, _vp]
         L.isc_bilu0.argtypes = [_vp, _vp, _vp]
@@ -81,7 +83,7 @@ def lib():
         L.isc_last_error.argtypes = [_vp]
         L.isc_last_error.restype = ctypes.c_char_p
         for name in ("isc_create", "isc_destroy", "isc_set_params", "isc_bcsr_pattern", "isc_assemble",
-                     "isc_decouple", "isc_solve", "isc_newton_step", "isc_spmv", "isc_bilu0",
+                     "isc_decouple", "isc_solve", "isc_solve_bicgstab", "isc_newton_step", "isc_spmv", "isc_bilu0",
                      "isc_bilu0_apply", "isc_bilu0_apply_spmv", "isc_update", "isc_scaled_norm", "isc_adjoint",
                      "isc_profile", "isc_profile_vectors", "isc_oil_rate"):
             getattr(L, name).restype = _i32
@@ -169,6 +171,14 @@ class Context:
         info = SolveInfo()
         st = lib().isc_solve(self.h, _ptr(Jdec), _ptr(b), _ptr(x), ctypes.byref(opts or solve_opts()),
                              ctypes.byref(info))
+        if check:
+            self._check(st)
+        return x, info, st
+
+    def isc_solve_bicgstab(self, Jdec, b, max_iters=1000, rtol=1e-8, x=None, check=True):
+        x = torch.empty_like(b) if x is None else x
+        info = SolveInfo()
+        st = lib().isc_solve_bicgstab(self.h, _ptr(Jdec), _ptr(b), _ptr(x), max_iters, rtol, ctypes.byref(info))
         if check:
             self._check(st)
         return x, info, st

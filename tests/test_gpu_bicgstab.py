@@ -1,0 +1,80 @@
+"""BiCGSTAB with block ILU(0) (the Krylov method of the paper's experiments)
+through the C-ABI, against the oracle's BiCGSTAB and a tight oracle solve.
+
+Tolerances: the true residual of the GPU solution, recomputed by the oracle,
+<= 1.01 rtol; distance to a 1e-13 oracle GMRES solution <= 1e-5 (the systems'
+conditioning, as for the GMRES solve); iteration count within a factor two
+(plus five) of the oracle's BiCGSTAB, whose inner products round differently.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1811_11992_amd import inputs as I
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+COL = np.array([1e6, 1.0, 1.0, 1.0, 100.0, 1.0, 1.0, 1000.0])   # unit size of each unknown
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _system(name, seed):
+    wl = I.make_workload(name)
+    m = O.Model(wl)
+    u = I.random_states(wl, seed)
+    F, J = m.assemble(u, wl.u0, wl.dt)
+    st, Jd, Fd, _ = m.decouple(J, F)
+    assert st == 0
+    return wl, m, Jd, -Fd
+
+
+@pytest.mark.parametrize("level", ["0", "1"])
+@pytest.mark.parametrize("name,seed", [("tiny:13x7x5", 21), ("C1", 22)])
+def test_bicgstab_matches_oracle(name, seed, level, monkeypatch):
+    from paper_1811_11992_amd import isc
+    monkeypatch.setenv("ISC_LEVEL_SWEEPS", level)
+    wl, m, Jd, b = _system(name, seed)
+    c = isc.Context(wl)
+    x, info, st = c.isc_solve_bicgstab(_dev(Jd), _dev(b), rtol=1e-8)
+    assert st == 0 and info.relres_true <= 1e-8
+    xg = _host(x)
+    assert np.linalg.norm(b - m.spmv(Jd, xg)) <= 1.01e-8 * np.linalg.norm(b)
+    st_o, x_o, inf_o = m.bicgstab(Jd, b, rtol=1e-8)
+    assert st_o == 0
+    assert info.iters <= 2 * inf_o.iters + 5, (info.iters, inf_o.iters)
+    st, x_ref, _ = m.gmres(Jd, b, rtol=1e-13, max_restarts=60)
+    err = np.abs((xg - x_ref) / COL).max(axis=0)
+    assert np.all(err <= 1e-5 * np.abs(x_ref / COL).max()), err
+
+
+def test_bicgstab_exact_preconditioner_and_zero_rhs():
+    """On a one-cell-wide chain BILU(0) is exact: one iteration, the dense
+    solution to rounding.  A zero right-hand side returns zero at once."""
+    from paper_1811_11992_amd import isc
+    wl, m, Jd, b = _system("tiny:9x1x1", 41)
+    c = isc.Context(wl)
+    x, info, st = c.isc_solve_bicgstab(_dev(Jd), _dev(b), rtol=1e-8)
+    assert st == 0 and info.iters == 1 and info.relres_true <= 1e-12
+    st_o, x_o, _ = m.bicgstab(Jd, b, rtol=1e-8)
+    xg = _host(x)
+    assert np.abs((xg - x_o) / COL).max() <= 1e-9 * np.abs(x_o / COL).max()
+    x, info, st = c.isc_solve_bicgstab(_dev(Jd), _dev(np.zeros_like(b)), rtol=1e-8)
+    assert st == 0 and info.iters == 0 and not torch.any(x).item()
+
+
+def test_bicgstab_reports_no_convergence():
+    from paper_1811_11992_amd import isc
+    wl, m, Jd, b = _system("C1", 22)
+    c = isc.Context(wl)
+    x, info, st = c.isc_solve_bicgstab(_dev(Jd), _dev(b), max_iters=2, rtol=1e-8, check=False)
+    assert st == isc.ISC_ERR_LINEAR_NOCONV and info.iters == 2
+    assert info.relres_true > 1e-8 and np.isfinite(info.relres_true)

@@ -353,6 +353,39 @@ def test_bilu0_reports_the_first_singular_pivot():
     assert np.allclose(Dinv[2], np.eye(8) * 1.5, rtol=1e-15, atol=1e-15)
 
 
+def test_bicgstab_reaches_the_dense_solution():
+    """BiCGSTAB with BILU(0) against a direct dense solve: at rtol 1e-12 the
+    solution agrees to 1e-9 in every variable (scaled by its unit size)."""
+    wl = I.make_workload("tiny:4x3x2")
+    m = O.Model(wl)
+    u = I.random_states(wl, 5)
+    F, J = m.assemble(u, wl.u0, wl.dt)
+    st, Jd, Fd, _ = m.decouple(J, F)
+    D = _dense(m, Jd)
+    for i in range(m.n):
+        D[8 * i:8 * i + 8, 8 * i:8 * i + 8] = np.eye(8)
+    x_ref = np.linalg.solve(D, -Fd.reshape(-1)).reshape(m.n, 8)
+    st, x, info = m.bicgstab(Jd, -Fd, rtol=1e-12)
+    assert st == 0 and info.relres_true <= 1e-12
+    scale = np.array([1e6, 1.0, 1.0, 1.0, 100.0, 1.0, 1.0, 1000.0])
+    assert np.abs((x - x_ref) / scale).max() <= 1e-9 * np.abs(x_ref / scale).max()
+
+
+def test_bicgstab_special_cases():
+    """An exact preconditioner (BILU(0) on a one-cell-wide chain) makes
+    A M^-1 = I: alpha = 1 and s = 0 after one iteration.  A zero right-hand
+    side returns x = 0 without iterating."""
+    wl = I.make_workload("tiny:9x1x1")
+    m = O.Model(wl)
+    u = I.random_states(wl, 41)
+    F, J = m.assemble(u, wl.u0, wl.dt)
+    st, Jd, Fd, _ = m.decouple(J, F)
+    st, x, info = m.bicgstab(Jd, -Fd, rtol=1e-8)
+    assert st == 0 and info.iters == 1 and info.relres_true <= 1e-13
+    st, x, info = m.bicgstab(Jd, np.zeros_like(Fd), rtol=1e-8)
+    assert st == 0 and info.iters == 0 and not np.any(x)
+
+
 def test_bilu0_factors_reproduce_matrix_on_pattern():
     """ILU(0): (L + I) U equals A on every stored block."""
     wl = I.make_workload("tiny:4x3x2")
