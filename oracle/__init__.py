@@ -65,6 +65,8 @@ def lib():
         L.orc_diag.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_zfactor.restype = ctypes.c_double
         L.orc_zfactor.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+        L.orc_gas_viscosity.restype = ctypes.c_double
+        L.orc_gas_viscosity.argtypes = [ctypes.c_void_p, ctypes.c_double, _dp]
         L.orc_residual.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _dp]
         L.orc_assemble.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_double, _dp, _dp]
         L.orc_sources.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
@@ -252,3 +254,9 @@ def zfactor(fluid, p, T, y):
     pcm = ctypes.c_double()
     z = lib().orc_zfactor(ctypes.byref(fluid), p, T, _p(y), ctypes.byref(tcm), ctypes.byref(pcm))
     return z, tcm.value, pcm.value
+
+
+def gas_viscosity(fluid, T, y):
+    """Gas-phase viscosity (Pa s) of composition y[6] at T (K)."""
+    y = np.ascontiguousarray(y, np.float64)
+    return lib().orc_gas_viscosity(ctypes.byref(fluid), T, _p(y))

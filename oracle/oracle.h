@@ -89,6 +89,9 @@ void orc_diag(const orc_model* m, const double* u, double* out);
 /* Z-factor of a gas of composition y[6] at (p, T); also returns pseudo-criticals */
 double orc_zfactor(const orc_fluid* fl, double p, double T, const double* y, double* Tcm, double* pcm);
 
+/* gas-phase viscosity of composition y[6] at T (Pa s) */
+double orc_gas_viscosity(const orc_fluid* fl, double T, const double* y);
+
 /* hot-path steps */
 int orc_residual(orc_model* m, const double* u, const double* u_old, double dt, double* F);
 int orc_assemble(orc_model* m, const double* u, const double* u_old, double dt,

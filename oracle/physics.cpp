@@ -122,6 +122,19 @@ template <class S> S gas_enthalpy(const orc_fluid& f, int c, const S& T) {
     return h;
 }
 
+/* gas-phase viscosity (viscosity subsection): component viscosities
+ * avg_c T^bvg_c mixed with weights y_c sqrt(M_c) */
+template <class S> S gas_viscosity(const orc_fluid& f, const S& T, const S* y) {
+    S num(0.0), den(0.0);
+    for (int c = 0; c < 6; ++c) {
+        double sm = std::sqrt(f.M[c]);
+        S mgc = f.avg[c] * pow(T, f.bvg[c]);
+        num = num + mgc * y[c] * sm;
+        den = den + y[c] * sm;
+    }
+    return num / den;
+}
+
 template <class S> S vap_heat(const orc_fluid& f, int c, const S& T) {
     if (val(T) < f.Tc[c]) return f.hvr[c] * pow(f.Tc[c] - T, f.ev[c]);
     return S(0.0);
@@ -167,14 +180,7 @@ template <class S> void props(const orc_fluid& f, double phi_ref, const S* u, Pr
     S lnLO = std::log(f.avisc[1]) + f.bvisc[1] / T;
     S lnHO = std::log(f.avisc[2]) + f.bvisc[2] / T;
     P.mu[1] = exp(xLO * lnLO + P.xHO * lnHO);
-    S num(0.0), den(0.0);
-    for (int c = 0; c < 6; ++c) {
-        double sm = std::sqrt(f.M[c]);
-        S mgc = f.avg[c] * pow(T, f.bvg[c]);
-        num = num + mgc * P.y[c] * sm;
-        den = den + P.y[c] * sm;
-    }
-    P.mu[2] = num / den;
+    P.mu[2] = gas_viscosity(f, T, P.y);
 
     /* porosity */
     P.phi = phi_ref * (1.0 + f.cpor * (p - f.p_ref));
@@ -623,6 +629,10 @@ double orc_zfactor(const orc_fluid* fl, double p, double T, const double* y, dou
     if (Tcm) *Tcm = tcm;
     if (pcm) *pcm = pcm_;
     return zroot(A, B);
+}
+
+double orc_gas_viscosity(const orc_fluid* fl, double T, const double* y) {
+    return gas_viscosity(*fl, T, y);
 }
 
 int orc_residual(orc_model* m, const double* u, const double* u_old, double dt, double* F) {

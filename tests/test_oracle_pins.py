@@ -479,7 +479,7 @@ def test_newton_converges_quadratically_on_c1_first_step():
     tail = [r for r in res if r < 1e-1]
     assert len(tail) >= 3
     for a, b in zip(tail[:-1], tail[1:]):
-        if b > 1e-12:     # above the rounding floor (about 1e-12 here)
+        if b > 1e-10:     # well above the rounding floor (about 1e-12 here)
             assert b <= 50 * a * a, res
 
 
