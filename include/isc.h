@@ -232,6 +232,29 @@ isc_status isc_bilu0_apply_spmv(isc_ctx* ctx, const double* Jdec, const double* 
 isc_status isc_update(isc_ctx* ctx, double* u, const double* du /* [N][8] */);
 isc_status isc_scaled_norm(isc_ctx* ctx, const double* F, double dt, double* res_h);
 
+/* Allocation-free variant of isc_scaled_norm, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  It needs no context: grid_h and fluid_h
+ * (host) give the cell volume, rho_ref[0] and cp_rock; poro [N] and F [N][8]
+ * are device arrays; *res (device, one double) receives max over cells and
+ * rows of |F_e,i| / s_e,i with the scales of isc_scaled_norm.  The call only
+ * enqueues two kernels on hip_stream (a stream of the current device, NULL =
+ * default) and returns; it calls no allocating routine.  Its partial maxima
+ * live in a fixed device array of ISC_NOALLOC_MAX_CELLS / 2048 doubles
+ * (64 KiB) that each device holds until the process ends, so grids above
+ * ISC_NOALLOC_MAX_CELLS cells are rejected with ISC_ERR_ARG.  All calls on one
+ * device share that array: calls that overlap in time on one device (on
+ * different streams, or from several threads) race and must be serialised by
+ * the caller.  Every partial read is written by the same call first, so
+ * nothing needs clearing between calls.  The first call on a device resolves
+ * the array's address (hipGetSymbolAddress); a caller that captures graphs
+ * makes one call before capturing.  Errors: ISC_ERR_ARG (null pointer,
+ * dt <= 0, invalid or too large grid), ISC_ERR_HIP; isc_last_error(NULL)
+ * returns the message of the last failed context-free call on the thread. */
+enum { ISC_NOALLOC_MAX_CELLS = 16777216 };
+isc_status isc_scaled_norm_noalloc(const isc_grid* grid_h, const isc_fluid* fluid_h, const double* poro,
+                                   const double* F, double dt, double* res, void* hip_stream);
+
 /* Differentiation form.  Objective J_obj = sum_n dt_n q_oil(u^n) with
  * q_oil(u) = sum over producer perforations of WI lambda_o (p - p_wf) for
  * p > p_wf (oil-phase molar rate, mol/s); parameters m = (ln k per cell,

@@ -154,7 +154,11 @@ isc_status reset_flags(isc_ctx* ctx) {
 
 isc_status check_ctx(const isc_ctx* ctx) { return ctx ? ISC_OK : ISC_ERR_ARG; }
 
+thread_local std::string g_noctx_err;   // last error of a context-free call on this thread
+
 }  // namespace
+
+void isc_set_noctx_error(const char* msg) { g_noctx_err = msg; }
 
 extern "C" {
 
@@ -791,6 +795,9 @@ isc_status isc_profile_vectors(isc_ctx* ctx, double* vec_h) {
     return ISC_OK;
 }
 
-const char* isc_last_error(const isc_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* isc_last_error(const isc_ctx* ctx) {
+    if (ctx) return ctx->err.c_str();
+    return g_noctx_err.empty() ? "null context" : g_noctx_err.c_str();
+}
 
 }  // extern "C"

@@ -283,6 +283,10 @@ inline void isc_prof_drain(isc_ctx* ctx) {
 
 hipError_t isc_reset_sweep_buffers(isc_ctx* ctx);
 
+// Error text of the last failed context-free call on this thread (returned by
+// isc_last_error(NULL)).
+void isc_set_noctx_error(const char* msg);
+
 // Slot of ctx->flags raised when a sync-free triangular sweep gave up waiting;
 // the two slots after it hold the wait limit (uint64, wall-clock ticks).
 constexpr int ISC_FLAG_SWEEP = 3;

@@ -75,6 +75,7 @@ def lib():
         L.isc_bilu0_apply_spmv.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.isc_update.argtypes = [_vp, _vp, _vp]
         L.isc_scaled_norm.argtypes = [_vp, _vp, _f64, ctypes.POINTER(_f64)]
+        L.isc_scaled_norm_noalloc.argtypes = [_vp, _vp, _vp, _vp, _f64, _vp, _vp]
         L.isc_adjoint.argtypes = [_vp, _vp, _vp, _f64, _vp, _f64, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
                                   ctypes.POINTER(SolveInfo)]
         L.isc_oil_rate.argtypes = [_vp, _vp, ctypes.POINTER(_f64)]
@@ -85,7 +86,7 @@ def lib():
         for name in ("isc_create", "isc_destroy", "isc_set_params", "isc_bcsr_pattern", "isc_assemble",
                      "isc_decouple", "isc_solve", "isc_solve_bicgstab", "isc_newton_step", "isc_spmv", "isc_bilu0",
                      "isc_bilu0_apply", "isc_bilu0_apply_spmv", "isc_update", "isc_scaled_norm", "isc_adjoint",
-                     "isc_profile", "isc_profile_vectors", "isc_oil_rate"):
+                     "isc_profile", "isc_profile_vectors", "isc_oil_rate", "isc_scaled_norm_noalloc"):
             getattr(L, name).restype = _i32
         _LIB = L
     return _LIB
@@ -232,6 +233,19 @@ class Context:
         q = _f64()
         self._check(lib().isc_oil_rate(self.h, _ptr(u), ctypes.byref(q)))
         return q.value
+
+
+NOALLOC_MAX_CELLS = 16777216   # ISC_NOALLOC_MAX_CELLS
+
+
+def isc_scaled_norm_noalloc(grid: I.Grid, fluid: I.Fluid, poro: torch.Tensor, F: torch.Tensor, dt: float,
+                            res: torch.Tensor, stream: "torch.cuda.Stream | None" = None) -> int:
+    """Context-free, allocation-free scaled max-norm of F into res[0] (device),
+    enqueued on `stream` (default: the current stream).  Returns the status;
+    on error lib().isc_last_error(None) holds the message."""
+    s = stream if stream is not None else torch.cuda.current_stream(res.device)
+    return lib().isc_scaled_norm_noalloc(ctypes.byref(grid), ctypes.byref(fluid), _ptr(poro), _ptr(F), dt,
+                                         _ptr(res), ctypes.c_void_p(s.cuda_stream))
 
 
 PROF_CLASSES = ("spmv", "ilu_apply", "assemble", "decouple", "ilu_factor", "krylov", "ilu_apply32", "spmv32",
