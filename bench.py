@@ -195,6 +195,7 @@ def run_newton(wl, precision, inner, warmup, steps):
     stats = {"gmres_its_per_newton": round((drv.lin_its - lin0) / max(1, drv.ni - ni0), 2),
              "inner_its_per_newton": round((drv.inner_its - inner0) / max(1, drv.ni - ni0), 2),
              "timesteps_completed": drv.steps_done, "step_cuts": drv.cuts, "nnzb": ctx.nnzb}
+    ctx.close()
     del drv, ctx
     gc.collect()
     torch.cuda.synchronize()
@@ -224,7 +225,8 @@ def adjoint_cost(name="C4", nsteps=20, every=5):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ok = bool(torch.isfinite(logk.grad).all()) and bool(torch.isfinite(lnA.grad).all())
-    del ctx
+    ctx.close()
+    del ctx, J
     gc.collect()
     return {"workload": f"{name}: {wl.nx}x{wl.ny}x{wl.nz}, {nsteps} steps, checkpoints every {every}",
             "forward_ms_per_step": round((t1 - t0) / nsteps * 1e3, 2),
@@ -261,6 +263,7 @@ def bicgstab_cost(name="C3", reps=2):
             torch.cuda.synchronize()
             t1 = time.perf_counter()
         out[label] = {"iters": info.iters, "relres_true": info.relres_true, "ms": round((t1 - t0) * 1e3, 2)}
+    ctx.close()
     del ctx
     gc.collect()
     return out
@@ -342,6 +345,10 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_layers)
     print(json.dumps(out), flush=True)
+    # every context is destroyed by now; let the device drain before the
+    # interpreter's own teardown
+    import torch
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

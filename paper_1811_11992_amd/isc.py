@@ -130,10 +130,17 @@ class Context:
         self._check(L.isc_bcsr_pattern(self.h, ctypes.byref(rp), ctypes.byref(ci), ctypes.byref(nn)))
         self.nnzb = nn.value
 
-    def __del__(self):
+    def close(self):
+        """Destroy the context now (waits for its stream, frees its workspace).
+        Programs that end soon after should call it rather than leave the
+        destruction to interpreter shutdown, when the HIP runtime may already
+        be going away."""
         if getattr(self, "h", None) is not None and _LIB is not None:
             _LIB.isc_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        self.close()
 
     def _check(self, st):
         if st != ISC_OK:

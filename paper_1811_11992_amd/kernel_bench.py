@@ -58,6 +58,8 @@ def main(argv=None):
     print(json.dumps({"workload": wl.name, "cells": c.n, "reps": a.reps, "bilu0_apply_ms": round(t_apply, 4),
                       "spmv_ms": round(t_spmv, 4), "apply_spmv_ms": round(t_fused, 4), "copy_ms": round(t_copy, 4),
                       "copy_bytes_each_way": vec_bytes, "apply_finite": bool(torch.isfinite(z).all())}), flush=True)
+    c.close()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
