@@ -38,6 +38,9 @@ class StepInfo(ctypes.Structure):
                 ("res_final", ctypes.c_double)]
 
 
+CPR_P_ITERS, CPR_NU, CPR_CF = 6, 2, 1.5   # defaults of the CPR preconditioner
+CPR_COARSEST = 64
+
 DIAG = dict(So=0, xHO=1, y0=2, Z=8, rho_w=9, rho_o=10, rho_g=11, mu_w=12, mu_o=13, mu_g=14,
             phi=15, phif=16, krw=17, kro=18, krg=19, Hw=20, Ho=21, Hg=22, KT=23, r0=24,
             acc0=28, K_W=36, K_LO=37, K_HO=38, Hv_W=39, Hg_O2=40)
@@ -87,6 +90,18 @@ def lib():
         L.orc_run.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                               ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                               ctypes.POINTER(StepInfo), _dp]
+        L.orc_cpr_create.restype = ctypes.c_void_p
+        L.orc_cpr_create.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
+        L.orc_cpr_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_cpr_nlevels.argtypes = [ctypes.c_void_p]
+        L.orc_cpr_level_dims.argtypes = [ctypes.c_void_p, ctypes.c_int32, _ip]
+        L.orc_cpr_level_dense.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp]
+        L.orc_cpr_smooth.argtypes = [ctypes.c_void_p, ctypes.c_int32, _dp, _dp, ctypes.c_int32]
+        L.orc_cpr_vcycle.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_cpr_pressure.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_cpr_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_fgmres_cpr.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(SolveInfo)]
         if hasattr(L, "orc_adjoint_step"):
             L.orc_oil_rate.restype = ctypes.c_double
             L.orc_oil_rate.argtypes = [ctypes.c_void_p, _dp]
@@ -212,6 +227,14 @@ class Model:
                                 _p(x), max_iters, rtol, ctypes.byref(info))
         return st, x, info
 
+    def fgmres_cpr(self, Jdec, b, restart=30, max_restarts=20, rtol=1e-8, p_iters=CPR_P_ITERS, nu=CPR_NU,
+                   cf=CPR_CF):
+        x = np.zeros((self.n, 8))
+        info = SolveInfo()
+        st = lib().orc_fgmres_cpr(self.h, _p(np.ascontiguousarray(Jdec)), _p(np.ascontiguousarray(b, np.float64)),
+                                  _p(x), restart, max_restarts, rtol, p_iters, nu, cf, ctypes.byref(info))
+        return st, x, info
+
     def scaled_norm(self, F, dt):
         return lib().orc_scaled_norm(self.h, _p(np.ascontiguousarray(F, np.float64)), dt)
 
@@ -246,6 +269,54 @@ class Model:
                            steps, _p(hist))
         return st, u, [dict(newton=s.newton_its, lin=s.lin_its, cuts=s.cuts, dt=s.dt_used,
                             res=s.res_final) for s in steps], hist
+
+
+class CPR:
+    """The oracle's CPR preconditioner of one decoupled matrix."""
+
+    def __init__(self, model: Model, Jdec, p_iters=CPR_P_ITERS, nu=CPR_NU, cf=CPR_CF):
+        self.model = model
+        self._J = np.ascontiguousarray(Jdec, np.float64)
+        self.h = lib().orc_cpr_create(model.h, _p(self._J), p_iters, nu, cf)
+        if not self.h:
+            raise RuntimeError("oracle CPR: singular factor")
+        self.nlevels = lib().orc_cpr_nlevels(self.h)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _LIB is not None and callable(lib):
+            _LIB.orc_cpr_destroy(self.h)
+            self.h = None
+
+    def level_dims(self, l):
+        d = np.zeros(3, np.int32)
+        n = lib().orc_cpr_level_dims(self.h, l, _ip_(d))
+        return tuple(int(v) for v in d), n
+
+    def level_dense(self, l):
+        _, n = self.level_dims(l)
+        out = np.zeros((n, n))
+        lib().orc_cpr_level_dense(self.h, l, _p(out))
+        return out
+
+    def smooth(self, l, b, x, first):
+        x = np.array(x, dtype=np.float64, order="C")
+        lib().orc_cpr_smooth(self.h, l, _p(np.ascontiguousarray(b, np.float64)), _p(x), first)
+        return x
+
+    def vcycle(self, b):
+        x = np.zeros(self.model.n)
+        lib().orc_cpr_vcycle(self.h, _p(np.ascontiguousarray(b, np.float64)), _p(x))
+        return x
+
+    def pressure(self, rp):
+        e = np.zeros(self.model.n)
+        lib().orc_cpr_pressure(self.h, _p(np.ascontiguousarray(rp, np.float64)), _p(e))
+        return e
+
+    def apply(self, r):
+        z = np.zeros((self.model.n, 8))
+        lib().orc_cpr_apply(self.h, _p(np.ascontiguousarray(r, np.float64)), _p(z))
+        return z
 
 
 def zfactor(fluid, p, T, y):

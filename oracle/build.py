@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["physics.cpp", "linear.cpp", "adjoint.cpp"]
+SOURCES = ["physics.cpp", "linear.cpp", "adjoint.cpp", "cpr.cpp"]
 OUT = os.path.join(HERE, "liboracle.so")
 
 

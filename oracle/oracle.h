@@ -131,6 +131,25 @@ int orc_run(orc_model* m, double* u, double dt, int32_t nsteps, double tol, int3
             int32_t restart, int32_t max_restarts, double rtol, orc_step_info* steps,
             double* u_hist /* [nsteps+1][8][N] or NULL */);
 
+/* CPR two-stage preconditioner of a decoupled matrix (see oracle/cpr.cpp):
+ * stage 1 an approximate solve of the pressure equation (p_iters GMRES steps
+ * preconditioned by an aggregation multigrid V-cycle with nu red-black
+ * Gauss-Seidel sweeps before and after a coarse correction scaled by cf),
+ * stage 2 block ILU(0) on the remaining residual. */
+enum { ORC_CPR_COARSEST = 64 };
+typedef struct orc_cpr orc_cpr;
+orc_cpr* orc_cpr_create(orc_model* m, const double* Jdec, int32_t p_iters, int32_t nu, double cf);
+void orc_cpr_destroy(orc_cpr* c);
+int32_t orc_cpr_nlevels(const orc_cpr* c);
+int32_t orc_cpr_level_dims(const orc_cpr* c, int32_t l, int32_t* dims);
+void orc_cpr_level_dense(const orc_cpr* c, int32_t l, double* out);
+void orc_cpr_smooth(const orc_cpr* c, int32_t l, const double* b, double* x, int32_t first);
+void orc_cpr_vcycle(const orc_cpr* c, const double* b, double* x);
+void orc_cpr_pressure(const orc_cpr* c, const double* rp, double* e);
+void orc_cpr_apply(const orc_cpr* c, const double* r, double* z);
+int orc_fgmres_cpr(orc_model* m, const double* Jdec, const double* b, double* x, int32_t restart,
+                   int32_t max_restarts, double rtol, int32_t p_iters, int32_t nu, double cf, orc_solve_info* info);
+
 /* discrete adjoint (see oracle/adjoint.cpp) */
 double orc_oil_rate(orc_model* m, const double* u);
 int orc_adjoint_step(orc_model* m, const double* u_n, const double* u_nm1, double dt_n,
