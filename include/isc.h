@@ -121,12 +121,23 @@ typedef struct {
 } isc_well;
 
 enum { ISC_FP64 = 0, ISC_MIXED = 1 };
+enum { ISC_PC_BILU0 = 0, ISC_PC_CPR = 1 };
 typedef struct {
     int32_t restart;       /* GMRES restart length m (<= max_opts.restart) */
     int32_t max_restarts;  /* cycles before ISC_ERR_LINEAR_NOCONV */
     int32_t precision;     /* ISC_FP64, or ISC_MIXED: FP32 preconditioner and
                               inner SpMV inside an FP64 flexible GMRES */
     int32_t inner_iters;   /* ISC_MIXED: FP32 inner GMRES iterations per outer one */
+    int32_t precond;       /* ISC_PC_BILU0: block ILU(0) (right-preconditioned
+                              GMRES, or the inner solver of ISC_MIXED);
+                              ISC_PC_CPR (FP64 only): the two-stage CPR
+                              preconditioner (Section 4.3, Example 2) inside an
+                              FP64 flexible GMRES -- stage 1 a pressure solve,
+                              stage 2 block ILU(0) on the remaining residual */
+    int32_t p_iters;       /* ISC_PC_CPR: GMRES steps of the pressure solve, each
+                              preconditioned by one V-cycle of the pressure
+                              multigrid (0: the V-cycle alone); at most
+                              max_opts.p_iters */
     double rtol;           /* stop when ||b - A x||_2 <= rtol ||b||_2 */
 } isc_solve_opts;
 
@@ -134,7 +145,8 @@ typedef struct {
     int32_t iters;               /* outer Krylov iterations (columns of the solutions formed) */
     int32_t inner_iters_total;   /* ISC_MIXED: inner iterations executed, including the one
                                     preconditioner application per cycle whose residual test
-                                    ended the cycle (its column is not used) */
+                                    ended the cycle (its column is not used); ISC_PC_CPR: the
+                                    pressure GMRES steps executed */
     int32_t restarts;
     int32_t reserved;
     double relres_est;           /* Arnoldi residual estimate / ||b|| */
@@ -160,7 +172,9 @@ typedef struct isc_ctx isc_ctx;
  * kz = kv_over_kh * kh; poro: reference porosity per cell (device, [N]);
  * wells_h: host array of nwells wells.  max_opts fixes the largest restart
  * length and inner iteration count the context will be asked for (workspace
- * is sized from it).  hip_stream: a hipStream_t (NULL = default stream). */
+ * is sized from it; max_opts.precond = ISC_PC_CPR also allocates the CPR
+ * preconditioner for up to max_opts.p_iters <= 16 pressure steps).
+ * hip_stream: a hipStream_t (NULL = default stream). */
 isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const double* logk,
                       double kv_over_kh, const double* poro, const isc_well* wells_h,
                       int32_t nwells, const isc_solve_opts* max_opts_h, void* hip_stream,
@@ -188,8 +202,23 @@ isc_status isc_assemble(isc_ctx* ctx, const double* u, const double* u_old, doub
 isc_status isc_decouple(isc_ctx* ctx, double* Jval, double* F, int32_t* bad_cell_h);
 
 /* Solve Jdec x = b for a decoupled matrix (unit diagonal blocks, as left by
- * isc_decouple) with block-ILU(0) (natural cell order) right-preconditioned
- * restarted GMRES from x0 = 0.  b, x: [N][8].  info_h may be NULL. */
+ * isc_decouple) from x0 = 0.  b, x: [N][8].  info_h may be NULL.
+ * opts->precond = ISC_PC_BILU0: block-ILU(0) (natural cell order)
+ * right-preconditioned restarted GMRES (FP64), or with ISC_MIXED the FP64
+ * flexible GMRES around FP32 inner GMRES.  ISC_PC_CPR: FP64 flexible GMRES
+ * with the two-stage CPR preconditioner.  Stage 1 takes the pressure equation
+ * of the decoupled system, the scalar matrix A_p of the (pressure row,
+ * pressure column) entries (Jdec_ij)[0][0], and solves it for the pressure
+ * part of the residual by opts->p_iters GMRES steps (from 0, no restart), each
+ * preconditioned by one V-cycle of a multigrid on the grid: levels lump 2x2x2
+ * boxes, the coarse matrices are the Galerkin products P^T A P for
+ * piecewise-constant P, smoothing is two red-black Gauss-Seidel sweeps before
+ * and after a coarse correction scaled by 1.5, and the coarsest level (at
+ * most 64 cells) is solved with its inverse.  Stage 2 applies block ILU(0) to
+ * what the pressure correction leaves of the residual:
+ *   z = E e_p + M^-1 (r - A E e_p),  e_p ~= A_p^-1 (E^T r),
+ * E^T r the pressure components of r.  ISC_ERR_SINGULAR if the factor or the
+ * coarsest matrix is singular. */
 isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* x,
                      const isc_solve_opts* opts_h, isc_solve_info* info_h);
 
@@ -209,8 +238,9 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
                               int32_t max_iters, double rtol, isc_solve_info* info_h);
 
 /* One Newton iteration at (u, u_old, dt): assemble, scaled-norm test (if
- * res <= tol: converged = 1, u unchanged), else decouple, BILU(0), GMRES and
- * the safeguarded update of u in place (saturation halving rule of the PER
+ * res <= tol: converged = 1, u unchanged), else decouple, the preconditioner
+ * set-up and the linear solve of opts->lin (as isc_solve), and the
+ * safeguarded update of u in place (saturation halving rule of the PER
  * subsection plus per-variable step limits). */
 isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double dt,
                            const isc_newton_opts* opts_h, isc_newton_info* info_h);
@@ -229,6 +259,14 @@ isc_status isc_bilu0_apply(isc_ctx* ctx, const double* Jdec, const double* Dinv,
  * r, z, w: [N][8], pairwise distinct. */
 isc_status isc_bilu0_apply_spmv(isc_ctx* ctx, const double* Jdec, const double* Dinv, const double* r,
                                 double* z, double* w);
+/* CPR components (the preconditioner of isc_solve with ISC_PC_CPR), for
+ * testing: each call factors Jdec and builds the pressure multigrid first
+ * (the context must have been created for CPR with max p_iters >= p_iters).
+ * isc_cpr_pressure_solve: e [N] = the stage-1 pressure solve of rp [N] (the
+ * p_iters V-cycle-preconditioned GMRES steps on A_p e = rp).
+ * isc_cpr_apply: z = CPR r and w = Jdec z (r, z, w: [N][8], distinct). */
+isc_status isc_cpr_pressure_solve(isc_ctx* ctx, const double* Jdec, int32_t p_iters, const double* rp, double* e);
+isc_status isc_cpr_apply(isc_ctx* ctx, const double* Jdec, int32_t p_iters, const double* r, double* z, double* w);
 isc_status isc_update(isc_ctx* ctx, double* u, const double* du /* [N][8] */);
 isc_status isc_scaled_norm(isc_ctx* ctx, const double* F, double dt, double* res_h);
 
@@ -281,12 +319,15 @@ isc_status isc_oil_rate(isc_ctx* ctx, const double* u, double* q_h);
  * 0 SpMV, 1 BILU(0) apply (one forward plus one backward sweep), 2 assembly
  * (property pass + face assembly), 3 decoupling, 4 BILU(0) factor (all
  * levels), 5 Krylov vector work (orthogonalisation, updates, norms, in both
- * precisions), 6 and 7 no longer used (FP32 apply and SpMV as separate
- * kernels), 8 BILU(0) apply fused with the SpMV (z = M^-1 r, w = A z; the
- * FP64 GMRES iteration, with its folded Gram-Schmidt update), 9 the same in
- * FP32 (the inner GMRES iteration of the precision form). */
+ * precisions), 6 the CPR pressure stage (pressure extraction of the
+ * residual, the V-cycles, the pressure SpMV and GMRES vector work, the stage-1
+ * correction A E e_p and the combination of the stages), 7 the CPR set-up
+ * (pressure stencil and block-column pack, coarse matrices, coarsest
+ * inverse), 8 BILU(0) apply fused with the SpMV (z = M^-1 r, w = A z; the
+ * FP64 GMRES iteration, with its folded Gram-Schmidt update, and stage 2 of
+ * CPR), 9 the same in FP32 (the inner GMRES iteration of the precision form). */
 enum { ISC_PROF_SPMV = 0, ISC_PROF_ILU_APPLY, ISC_PROF_ASSEMBLE, ISC_PROF_DECOUPLE, ISC_PROF_ILU_FACTOR,
-       ISC_PROF_KRYLOV, ISC_PROF_ILU_APPLY32, ISC_PROF_SPMV32, ISC_PROF_ILU_SPMV, ISC_PROF_ILU_SPMV32,
+       ISC_PROF_KRYLOV, ISC_PROF_CPR_PRESSURE, ISC_PROF_CPR_SETUP, ISC_PROF_ILU_SPMV, ISC_PROF_ILU_SPMV32,
        ISC_PROF_NCLASS = 10 };
 isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* count_h);
 

@@ -258,9 +258,10 @@ isc_status isc_adjoint_impl(isc_ctx* ctx, const double* u_n, const double* u_nm1
         ctx->err = "isc_adjoint: invalid argument";
         return ISC_ERR_ARG;
     }
-    const isc_solve_opts def{30, 200, ISC_FP64, 0, 1e-12};
+    const isc_solve_opts def{30, 200, ISC_FP64, 0, ISC_PC_BILU0, 0, 1e-12};
     isc_solve_opts opts = o ? *o : def;
     opts.precision = ISC_FP64;
+    opts.precond = ISC_PC_BILU0;
     if (opts.restart < 1 || opts.restart > ctx->mmax) opts.restart = ctx->mmax;
     const int32_t n = ctx->n;
     const double V = ctx->g.dx * ctx->g.dy * ctx->g.dz;

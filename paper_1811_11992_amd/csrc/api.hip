@@ -22,9 +22,11 @@ hipError_t isc_launch_scaled_norm(isc_ctx*, const double* F, double dt, double* 
 hipError_t isc_launch_negate(isc_ctx*, const double* x, double* y);
 isc_status isc_gmres_fp64(isc_ctx*, const double* A, const double* Dinv, const double* b, double* x,
                           const isc_solve_opts* o, isc_solve_info* info);
-isc_status isc_solve_mixed(isc_ctx*, const double* A, const double* b, double* x, const isc_solve_opts* o,
-                           isc_solve_info* info);
+isc_status isc_fgmres(isc_ctx*, const double* A, const double* b, double* x, const isc_solve_opts* o,
+                      isc_solve_info* info);
 isc_status isc_prepare_mixed_dev(isc_ctx*, const double* A, int32_t* bad_dev);
+void isc_cpr_pressure_gmres(isc_ctx*, const double* rp, double* e, int k);
+void isc_cpr_apply_w(isc_ctx*, const double* A, const double* u, double* z, double* w, int k);
 isc_status isc_adjoint_impl(isc_ctx*, const double* u_n, const double* u_nm1, double dt_n,
                             const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
                             double* g_A_h, const isc_solve_opts* o, isc_solve_info* info_h);
@@ -154,6 +156,28 @@ isc_status reset_flags(isc_ctx* ctx) {
 
 isc_status check_ctx(const isc_ctx* ctx) { return ctx ? ISC_OK : ISC_ERR_ARG; }
 
+// the preconditioner and precision options against what the context holds
+isc_status check_precond(isc_ctx* ctx, const isc_solve_opts* o, const char* who) {
+    if (o->precond != ISC_PC_BILU0 && o->precond != ISC_PC_CPR) {
+        ctx->err = std::string(who) + ": unknown preconditioner";
+        return ISC_ERR_ARG;
+    }
+    if (o->precond == ISC_PC_CPR) {
+        if (o->precision != ISC_FP64) {
+            ctx->err = std::string(who) + ": the CPR preconditioner runs in FP64 only";
+            return ISC_ERR_ARG;
+        }
+        if (ctx->cpr_kmax < 0 || o->p_iters < 0 || o->p_iters > ctx->cpr_kmax) {
+            ctx->err = std::string(who) + ": CPR needs a context created for it with max p_iters >= p_iters >= 0";
+            return ISC_ERR_ARG;
+        }
+    } else if (o->precision == ISC_MIXED && (o->inner_iters < 1 || o->inner_iters > ctx->inner_max)) {
+        ctx->err = std::string(who) + ": mixed precision needs 1 <= inner_iters <= the context's maximum";
+        return ISC_ERR_ARG;
+    }
+    return ISC_OK;
+}
+
 thread_local std::string g_noctx_err;   // last error of a context-free call on this thread
 
 }  // namespace
@@ -198,7 +222,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         ctx->err = "no HIP device";
         return fail(ISC_ERR_HIP);
     }
-    isc_solve_opts mo{30, 20, ISC_FP64, 0, 1e-8};
+    isc_solve_opts mo{30, 20, ISC_FP64, 0, ISC_PC_BILU0, 0, 1e-8};
     if (max_opts_h) mo = *max_opts_h;
     if (mo.restart < 1 || mo.restart > 31) {
         ctx->err = "max restart must be in [1, 31]";
@@ -206,6 +230,10 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     }
     if (mo.inner_iters < 0 || mo.inner_iters > 31) {
         ctx->err = "max inner_iters must be in [0, 31]";
+        return fail(ISC_ERR_ARG);
+    }
+    if (mo.precond == ISC_PC_CPR && (mo.p_iters < 0 || mo.p_iters > ISC_CPR_MAX_K)) {
+        ctx->err = "max p_iters must be in [0, 16]";
         return fail(ISC_ERR_ARG);
     }
     ctx->mmax = mo.restart;
@@ -408,6 +436,45 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         ALLOC(ctx->small32, (size_t)4096 + 32 * 32);   // as small: Rs past 4096
         ALLOC(ctx->Z32, nv * ctx->inner_max);
     }
+    if (mo.precond == ISC_PC_CPR) {   // CPR: multigrid levels and stage-1 buffers
+        isc_cpr_plan(ctx);
+        size_t words = 0;
+        for (size_t l = 0; l < ctx->mg.size(); ++l) words += (size_t)ctx->mg[l].n * (l == 0 ? 7 : 9);
+        ALLOC(ctx->mg_store, words);
+        double* p = ctx->mg_store;
+        for (size_t l = 0; l < ctx->mg.size(); ++l) {
+            isc_ctx::MgLevel& L = ctx->mg[l];
+            L.co = p;
+            p += (size_t)7 * L.n;
+            if (l > 0) {
+                L.x = p;
+                p += L.n;
+                L.b = p;
+                p += L.n;
+            }
+        }
+        ctx->cpr_kmax = mo.p_iters;
+        ctx->cpr_npad = (n + 7) & ~7;
+        const size_t np = (size_t)ctx->cpr_npad;
+        ALLOC(ctx->mg_cinv, (size_t)ISC_CPR_COARSEST * ISC_CPR_COARSEST);
+        ALLOC(ctx->cpr_pc, (size_t)ctx->nnzb * 8);
+        ALLOC(ctx->cpr_V, np * (ctx->cpr_kmax + 1));
+        ALLOC(ctx->cpr_Z, np * std::max(ctx->cpr_kmax, 1));
+        ALLOC(ctx->cpr_w, np);
+        ALLOC(ctx->cpr_rp, np);
+        ALLOC(ctx->cpr_ep, np);
+        ALLOC(ctx->cpr_w1, nv);
+        ALLOC(ctx->cpr_r2, nv);
+        ALLOC(ctx->small_p, (size_t)4096 + 32 * 32);
+        // the pressure vectors' padding is read by the Gram-Schmidt passes and must stay zero
+        double* zero_bufs[] = {ctx->cpr_V, ctx->cpr_Z, ctx->cpr_w, ctx->cpr_rp, ctx->cpr_ep};
+        const size_t zero_len[] = {np * (ctx->cpr_kmax + 1), np * std::max(ctx->cpr_kmax, 1), np, np, np};
+        for (int k = 0; k < 5; ++k)
+            if (hipMemsetAsync(zero_bufs[k], 0, zero_len[k] * sizeof(double), ctx->stream) != hipSuccess) {
+                ctx->err = "clearing the CPR buffers failed";
+                return fail(ISC_ERR_HIP);
+            }
+    }
 #undef ALLOC
     if (hipHostMalloc((void**)&ctx->hscratch, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&ctx->hflags, 16 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
@@ -491,7 +558,9 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->J32,     ctx->Dinv32, ctx->V32,    ctx->w32,    ctx->t32,
                     ctx->small32, ctx->Z32, ctx->accJ,   ctx->qg,     ctx->qv,     ctx->rates,
                     ctx->perf_cell, ctx->well_off, ctx->bricks_fwd, ctx->bricks_bwd, ctx->sweep64,
-                    ctx->sweep32, ctx->ticket, ctx->Lt, ctx->Lt32, ctx->items_bwd_spmv};
+                    ctx->sweep32, ctx->ticket, ctx->Lt, ctx->Lt32, ctx->items_bwd_spmv,
+                    ctx->mg_store, ctx->mg_cinv, ctx->cpr_pc, ctx->cpr_V, ctx->cpr_Z, ctx->cpr_w,
+                    ctx->cpr_rp, ctx->cpr_ep, ctx->cpr_w1, ctx->cpr_r2, ctx->small_p};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (ctx->hscratch) hipHostFree(ctx->hscratch);
@@ -617,11 +686,20 @@ isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* 
         ctx->err = "isc_solve: restart must be in [1, max restart of the context], max_restarts >= 1, rtol > 0";
         return ISC_ERR_ARG;
     }
-    if (o->precision == ISC_MIXED) {
-        if (o->inner_iters < 1 || o->inner_iters > ctx->inner_max) {
-            ctx->err = "isc_solve: mixed precision needs 1 <= inner_iters <= the context's maximum";
-            return ISC_ERR_ARG;
+    TRY(check_precond(ctx, o, "isc_solve"));
+    if (o->precond == ISC_PC_CPR) {
+        TRY(isc_bilu0(ctx, Jdec, ctx->Dinv));
+        TRY(reset_flags(ctx));
+        ISC_HIP(isc_cpr_setup(ctx, Jdec, ctx->flags + FLAG_BAD));
+        int32_t bad;
+        TRY(read_flag(ctx, FLAG_BAD, &bad));
+        if (bad != INT32_MAX) {
+            ctx->err = "CPR: the coarsest pressure matrix is singular";
+            return ISC_ERR_SINGULAR;
         }
+        return isc_fgmres(ctx, Jdec, b, x, o, info_h);
+    }
+    if (o->precision == ISC_MIXED) {
         TRY(reset_flags(ctx));
         TRY(isc_prepare_mixed_dev(ctx, Jdec, ctx->flags + FLAG_BAD));
         int32_t bad;
@@ -630,10 +708,52 @@ isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* 
             ctx->err = "block ILU(0) (FP32): singular pivot block at cell " + std::to_string(bad);
             return ISC_ERR_SINGULAR;
         }
-        return isc_solve_mixed(ctx, Jdec, b, x, o, info_h);
+        return isc_fgmres(ctx, Jdec, b, x, o, info_h);
     }
     TRY(isc_bilu0(ctx, Jdec, ctx->Dinv));
     return isc_gmres_fp64(ctx, Jdec, ctx->Dinv, b, x, o, info_h);
+}
+
+// factor + CPR set-up for Jdec (component entry points below)
+static isc_status cpr_prepare(isc_ctx* ctx, const double* Jdec, int32_t p_iters, const char* who) {
+    isc_solve_opts o{1, 1, ISC_FP64, 0, ISC_PC_CPR, p_iters, 1e-8};
+    TRY(check_precond(ctx, &o, who));
+    TRY(isc_bilu0(ctx, Jdec, ctx->Dinv));
+    TRY(reset_flags(ctx));
+    ISC_HIP(isc_cpr_setup(ctx, Jdec, ctx->flags + FLAG_BAD));
+    int32_t bad;
+    TRY(read_flag(ctx, FLAG_BAD, &bad));
+    if (bad != INT32_MAX) {
+        ctx->err = std::string(who) + ": the coarsest pressure matrix is singular";
+        return ISC_ERR_SINGULAR;
+    }
+    return ISC_OK;
+}
+
+isc_status isc_cpr_pressure_solve(isc_ctx* ctx, const double* Jdec, int32_t p_iters, const double* rp, double* e) {
+    TRY(check_ctx(ctx));
+    if (!Jdec || !rp || !e) {
+        ctx->err = "isc_cpr_pressure_solve: null argument";
+        return ISC_ERR_ARG;
+    }
+    TRY(cpr_prepare(ctx, Jdec, p_iters, "isc_cpr_pressure_solve"));
+    ISC_HIP(hipMemcpyAsync(ctx->cpr_rp, rp, (size_t)ctx->n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    isc_cpr_pressure_gmres(ctx, ctx->cpr_rp, ctx->cpr_ep, p_iters);
+    ISC_HIP(hipMemcpyAsync(e, ctx->cpr_ep, (size_t)ctx->n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    ISC_HIP(hipStreamSynchronize(ctx->stream));
+    return isc_check_sweeps(ctx);
+}
+
+isc_status isc_cpr_apply(isc_ctx* ctx, const double* Jdec, int32_t p_iters, const double* r, double* z, double* w) {
+    TRY(check_ctx(ctx));
+    if (!Jdec || !r || !z || !w || r == z || r == w || z == w) {
+        ctx->err = "isc_cpr_apply: null or aliased arrays";
+        return ISC_ERR_ARG;
+    }
+    TRY(cpr_prepare(ctx, Jdec, p_iters, "isc_cpr_apply"));
+    isc_cpr_apply_w(ctx, Jdec, r, z, w, p_iters);
+    ISC_HIP(hipGetLastError());
+    return isc_check_sweeps(ctx);
 }
 
 isc_status isc_update(isc_ctx* ctx, double* u, const double* du) {
@@ -696,11 +816,9 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
     ISC_HIP(isc_launch_negate(ctx, ctx->F, ctx->rhs));
     ISC_HIP(hipEventRecord(ev[2], ctx->stream));
     isc_status st;
-    if (o->lin.precision == ISC_MIXED) {
-        if (o->lin.inner_iters < 1 || o->lin.inner_iters > ctx->inner_max) {
-            ctx->err = "isc_newton_step: mixed precision needs 1 <= inner_iters <= the context's maximum";
-            return ISC_ERR_ARG;
-        }
+    TRY(check_precond(ctx, &o->lin, "isc_newton_step"));
+    const bool cpr = o->lin.precond == ISC_PC_CPR;
+    if (o->lin.precision == ISC_MIXED && !cpr) {
         tk = isc_prof_begin(ctx, ISC_PROF_ILU_FACTOR);
         TRY(isc_prepare_mixed_dev(ctx, ctx->J, ctx->flags + FLAG_BAD));
         isc_prof_end(ctx, tk);
@@ -708,6 +826,11 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
         tk = isc_prof_begin(ctx, ISC_PROF_ILU_FACTOR);
         ISC_HIP(isc_launch_bilu0_factor(ctx, ctx->J, ctx->Dinv, ctx->flags + FLAG_BAD));
         isc_prof_end(ctx, tk);
+        if (cpr) {   // a singular coarsest pressure matrix reports cell 0
+            tk = isc_prof_begin(ctx, ISC_PROF_CPR_SETUP);
+            ISC_HIP(isc_cpr_setup(ctx, ctx->J, ctx->flags + FLAG_BAD));
+            isc_prof_end(ctx, tk);
+        }
     }
     ISC_HIP(hipEventRecord(ev[3], ctx->stream));
     int32_t bad;
@@ -722,8 +845,8 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
         ctx->err = "isc_newton_step: restart exceeds the context's maximum";
         return ISC_ERR_ARG;
     }
-    if (o->lin.precision == ISC_MIXED)
-        st = isc_solve_mixed(ctx, ctx->J, ctx->rhs, ctx->du, &o->lin, &inf.lin);
+    if (o->lin.precision == ISC_MIXED || cpr)
+        st = isc_fgmres(ctx, ctx->J, ctx->rhs, ctx->du, &o->lin, &inf.lin);
     else
         st = isc_gmres_fp64(ctx, ctx->J, ctx->Dinv, ctx->rhs, ctx->du, &o->lin, &inf.lin);
     ISC_HIP(hipEventRecord(ev[4], ctx->stream));

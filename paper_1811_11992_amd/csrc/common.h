@@ -213,6 +213,29 @@ struct isc_ctx {
     float* t32 = nullptr;
     double* small32 = nullptr;
     float* Z32 = nullptr;           // [inner][N*8] the inner solver's z_j = P(u_j)
+    // CPR preconditioner (cpr.hip): the levels of the pressure multigrid and
+    // the stage-1 buffers; allocated when the context's maximum options ask
+    // for CPR (cpr_kmax = the most pressure GMRES steps, -1 = not allocated)
+    struct MgLevel {
+        int32_t nx, ny, nz, n;
+        double* co;     // [7][n] stencil
+        double* x;      // [n] (levels >= 1; level 0 uses the caller's vectors)
+        double* b;      // [n]
+    };
+    std::vector<MgLevel> mg;
+    int32_t cpr_kmax = -1;
+    int32_t cpr_npad = 0;          // pressure vector length, padded to a multiple of 8
+    double* mg_store = nullptr;    // all levels' stencils and vectors
+    double* mg_cinv = nullptr;     // [nc][nc] inverse of the coarsest matrix
+    double* cpr_pc = nullptr;      // [nnzb][8] column 0 of every block of the decoupled matrix
+    double* cpr_V = nullptr;       // pressure GMRES basis [(kmax + 1)][npad]
+    double* cpr_Z = nullptr;       // [kmax][npad] its preconditioned vectors
+    double* cpr_w = nullptr;       // [npad]
+    double* cpr_rp = nullptr;      // [npad] pressure part of the residual
+    double* cpr_ep = nullptr;      // [npad] stage-1 pressure correction
+    double* cpr_w1 = nullptr;      // [N][8] A E e_p
+    double* cpr_r2 = nullptr;      // [N][8] stage-2 residual
+    double* small_p = nullptr;     // small dense state of the pressure GMRES
     // adjoint workspace
     double* accJ = nullptr;         // [N][64] accumulation Jacobian
     double* qg = nullptr;           // [N][8]  producer oil-rate gradient
@@ -242,6 +265,21 @@ constexpr int PERF_W = 12;  // kind, wi, bhp, q[7], qE, q_total
 #endif
 constexpr int NPART = ISC_NPART;  // partial sums per reduction (block count of the reducing kernels)
 }
+
+// CPR pressure multigrid: smoothing sweeps before and after the coarse
+// correction, its scale, and the size at which coarsening stops
+#define ISC_CPR_NU 2
+#define ISC_CPR_CF 1.5
+#define ISC_CPR_COARSEST 64
+#define ISC_CPR_MAX_K 16      // most GMRES steps of the pressure solve
+
+void isc_cpr_plan(isc_ctx* ctx);
+hipError_t isc_cpr_setup(isc_ctx* ctx, const double* A, int32_t* bad_dev);
+void isc_cpr_vcycle(isc_ctx* ctx, const double* b, double* x);
+void isc_cpr_pressure_apply(isc_ctx* ctx, const double* x, double* y);
+void isc_cpr_gather(isc_ctx* ctx, const double* u, double* rp);
+void isc_cpr_stage1(isc_ctx* ctx, const double* ep, const double* u, double* w1, double* r2);
+void isc_cpr_combine(isc_ctx* ctx, const double* ep, double* z, double* w, const double* w1);
 
 // Profiling helpers (host).  prof_begin/prof_end bracket a kernel class on the
 // context stream; prof_drain converts finished pairs to milliseconds and must

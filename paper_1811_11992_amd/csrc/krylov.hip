@@ -694,18 +694,89 @@ static void inner_gmres32(isc_ctx* ctx, const float* A32, const float* D32, cons
     hipLaunchKernelGGL(to_f64, dim3(nb), dim3(256), 0, ctx->stream, len, ctx->t32, z);
 }
 
+// e = the CPR stage-1 pressure solve of rp (vectors of ctx->cpr_npad doubles,
+// the entries past the cell count zero): k steps of FP64 GMRES from 0 on
+// A_p e = rp, right-preconditioned by one V-cycle of the pressure multigrid,
+// orthogonalised by the same delayed CGS2; no host synchronisation (k is
+// fixed; a breakdown leaves zero vectors and zero Hessenberg columns, which
+// the triangular solves skip).  k = 0: e = one V-cycle applied to rp.
+static void pressure_gmres(isc_ctx* ctx, const double* rp, double* e, int k) {
+    if (k == 0) {
+        isc_cpr_vcycle(ctx, rp, e);
+        return;
+    }
+    const int64_t len = ctx->cpr_npad;
+    const int64_t len2 = len / 2;
+    const int nb = nblocks(len);
+    const int nb2 = nblocks(len2);
+    Hess hp = hess_at(ctx->small_p, ctx->cpr_kmax);
+    Dcgs dp = dcgs_at(ctx->small_p, ctx->cpr_kmax);
+    dp.Rs = ctx->small_p + RS_OFF;   // u_j = Q_j s_j + omega_j q_j, to form the result from Z
+    double* red = ctx->small_p + RED_OFF;
+    double2* Q2 = reinterpret_cast<double2*>(ctx->cpr_V);
+    double* u = ctx->cpr_V + (size_t)k * len;   // the lagged vector
+    double2* u2 = reinterpret_cast<double2*>(u);
+    const double2* w2 = reinterpret_cast<const double2*>(ctx->cpr_w);
+    (void)hipMemcpyAsync(u, rp, (size_t)len * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+    for (int j = 0; j <= k; ++j) {
+        const bool last = j == k;
+        if (j > 0)   // q_{j-1} and u_j
+            hipLaunchKernelGGL(dcgs2_update<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, len2, j - 1,
+                               red, dp.omz, u2, w2, (double*)nullptr);
+        if (!last) {   // z_j = V-cycle(u_j) (kept), w = A_p z_j
+            double* Zj = ctx->cpr_Z + (size_t)j * len;
+            isc_cpr_vcycle(ctx, u, Zj);
+            isc_cpr_pressure_apply(ctx, Zj, ctx->cpr_w);
+        }
+        hipLaunchKernelGGL(dcgs2_dots<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, len2, j, u2,
+                           last ? nullptr : w2, ctx->partial);
+        hipLaunchKernelGGL(reduce_rows_dcgs, dim3(last ? j + 1 : 2 * (j + 1)), dim3(256), 0, ctx->stream,
+                           ctx->partial, nb2, j, red);
+        hipLaunchKernelGGL(dcgs2_step, dim3(1), dim3(64), 0, ctx->stream, hp, dp, j, last ? 1 : 0, red);
+    }
+    hipLaunchKernelGGL(cycle_coefficients, dim3(1), dim3(64), 0, ctx->stream, hp, dp, k);
+    hipLaunchKernelGGL((lincomb<double, double>), dim3(nb), dim3(256), 0, ctx->stream, len, ctx->cpr_Z, len, k, hp.y,
+                       e, 0);
+}
+
+// z = CPR(u) and w = A z (FP64): the pressure solve, the stage-1 correction
+// (w1 = A E e_p, r2 = u - w1), block ILU(0) on r2 fused with the SpMV
+// (z2, w2 = A z2), then z = z2 + E e_p and w = w2 + w1.  ctx->Dinv and the
+// sweep packs must hold the factor of A, and the CPR set-up must be done.
+static void cpr_apply_w(isc_ctx* ctx, const double* A, const double* u, double* z, double* w, int k) {
+    int tk = isc_prof_begin(ctx, ISC_PROF_CPR_PRESSURE);
+    isc_cpr_gather(ctx, u, ctx->cpr_rp);
+    pressure_gmres(ctx, ctx->cpr_rp, ctx->cpr_ep, k);
+    isc_cpr_stage1(ctx, ctx->cpr_ep, u, ctx->cpr_w1, ctx->cpr_r2);
+    isc_prof_end(ctx, tk);
+    tk = isc_prof_begin(ctx, ISC_PROF_ILU_SPMV);
+    isc_launch_bilu0_apply_spmv(ctx, A, ctx->Dinv, ctx->cpr_r2, z, w);
+    isc_prof_end(ctx, tk);
+    tk = isc_prof_begin(ctx, ISC_PROF_CPR_PRESSURE);
+    isc_cpr_combine(ctx, ctx->cpr_ep, z, w, ctx->cpr_w1);
+    isc_prof_end(ctx, tk);
+}
+
 }  // namespace isc
 
-// FP64 flexible GMRES(m) whose preconditioner is the FP32 inner GMRES above,
+void isc_cpr_pressure_gmres(isc_ctx* ctx, const double* rp, double* e, int k) { isc::pressure_gmres(ctx, rp, e, k); }
+void isc_cpr_apply_w(isc_ctx* ctx, const double* A, const double* u, double* z, double* w, int k) {
+    isc::cpr_apply_w(ctx, A, u, z, w, k);
+}
+
+// FP64 flexible GMRES(m) whose preconditioner is either the FP32 inner GMRES
+// above (ISC_MIXED) or the CPR preconditioner (ISC_PC_CPR),
 // with the same delayed CGS2 as the FP64 solver.  Iteration j stores
 // zt_j = P(u_j) for the lagged vector u_j; since u_j = omega_j q_j + Q_j s_j,
 // zt_j = omega_j z_j + Z_j s_j for the vectors z_j that satisfy the flexible
 // Arnoldi relation A Z = Q H, so the update x += Z y is done as
 // x += Zt (Rs^-1 y) with the small triangular Rs of the (s_j, omega_j).
-// ctx->J32 / ctx->Dinv32 must hold the FP32 matrix and factor.
-isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, double* x, const isc_solve_opts* o,
-                           isc_solve_info* info) {
+// ISC_MIXED: ctx->J32 / ctx->Dinv32 must hold the FP32 matrix and factor;
+// ISC_PC_CPR: ctx->Dinv the FP64 factor and the CPR set-up done.
+isc_status isc_fgmres(isc_ctx* ctx, const double* A, const double* b, double* x, const isc_solve_opts* o,
+                      isc_solve_info* info) {
     using namespace isc;
+    const bool cpr = o->precond == ISC_PC_CPR;
     const int64_t len = (int64_t)ctx->n * NU;
     const int64_t ldv = len;
     const int64_t len2 = len / 2, ldv2 = ldv / 2;
@@ -768,10 +839,14 @@ isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, doubl
             }
             if (!last) {
                 double* Zj = ctx->Z + (size_t)j * ldv;
-                inner_gmres32(ctx, ctx->J32, ctx->Dinv32, u, Zj, m_in);
-                const int tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
-                isc_launch_spmv(ctx, A, Zj, ctx->w);
-                isc_prof_end(ctx, tk);
+                if (cpr) {
+                    cpr_apply_w(ctx, A, u, Zj, ctx->w, o->p_iters);
+                } else {
+                    inner_gmres32(ctx, ctx->J32, ctx->Dinv32, u, Zj, m_in);
+                    const int tk = isc_prof_begin(ctx, ISC_PROF_SPMV);
+                    isc_launch_spmv(ctx, A, Zj, ctx->w);
+                    isc_prof_end(ctx, tk);
+                }
             }
             const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
             hipLaunchKernelGGL(dcgs2_dots<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, u2,
@@ -795,7 +870,7 @@ isc_status isc_solve_mixed(isc_ctx* ctx, const double* A, const double* b, doubl
                 ctx->err = "isc_solve: FGMRES breakdown (non-finite residual estimate)";
                 return ISC_ERR_NONFINITE;
             }
-            if (!last) inf.inner_iters_total += m_in;
+            if (!last) inf.inner_iters_total += cpr ? o->p_iters : m_in;
             if (j == 0) {
                 if (breakdown) {
                     k = 0;

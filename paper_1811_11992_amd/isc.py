@@ -21,6 +21,8 @@ _LIB = None
 ISC_OK, ISC_ERR_ARG, ISC_ERR_HIP, ISC_ERR_OOM = 0, -1, -2, -3
 ISC_ERR_SINGULAR, ISC_ERR_NONFINITE, ISC_ERR_LINEAR_NOCONV, ISC_ERR_NEWTON_NOCONV = -4, -5, -6, -7
 ISC_FP64, ISC_MIXED = 0, 1
+ISC_PC_BILU0, ISC_PC_CPR = 0, 1
+CPR_P_ITERS = 6     # default GMRES steps of the CPR pressure solve
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -29,7 +31,7 @@ _f64 = ctypes.c_double
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", _i32), ("max_restarts", _i32), ("precision", _i32), ("inner_iters", _i32),
-                ("rtol", _f64)]
+                ("precond", _i32), ("p_iters", _i32), ("rtol", _f64)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -74,6 +76,8 @@ def lib():
         L.isc_bilu0_apply.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.isc_bilu0_apply_spmv.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.isc_update.argtypes = [_vp, _vp, _vp]
+        L.isc_cpr_pressure_solve.argtypes = [_vp, _vp, _i32, _vp, _vp]
+        L.isc_cpr_apply.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
         L.isc_scaled_norm.argtypes = [_vp, _vp, _f64, ctypes.POINTER(_f64)]
         L.isc_scaled_norm_noalloc.argtypes = [_vp, _vp, _vp, _vp, _f64, _vp, _vp]
         L.isc_adjoint.argtypes = [_vp, _vp, _vp, _f64, _vp, _f64, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
@@ -86,7 +90,8 @@ def lib():
         for name in ("isc_create", "isc_destroy", "isc_set_params", "isc_bcsr_pattern", "isc_assemble",
                      "isc_decouple", "isc_solve", "isc_solve_bicgstab", "isc_newton_step", "isc_spmv", "isc_bilu0",
                      "isc_bilu0_apply", "isc_bilu0_apply_spmv", "isc_update", "isc_scaled_norm", "isc_adjoint",
-                     "isc_profile", "isc_profile_vectors", "isc_oil_rate", "isc_scaled_norm_noalloc"):
+                     "isc_profile", "isc_profile_vectors", "isc_oil_rate", "isc_scaled_norm_noalloc",
+                     "isc_cpr_pressure_solve", "isc_cpr_apply"):
             getattr(L, name).restype = _i32
         _LIB = L
     return _LIB
@@ -99,15 +104,21 @@ def _ptr(t: torch.Tensor | None):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def solve_opts(restart=30, max_restarts=20, precision=ISC_FP64, inner_iters=0, rtol=1e-8) -> SolveOpts:
-    return SolveOpts(restart, max_restarts, precision, inner_iters, rtol)
+def solve_opts(restart=30, max_restarts=20, precision=ISC_FP64, inner_iters=0, rtol=1e-8, precond=ISC_PC_BILU0,
+               p_iters=0) -> SolveOpts:
+    return SolveOpts(restart, max_restarts, precision, inner_iters, precond, p_iters, rtol)
+
+
+def cpr_opts(p_iters=CPR_P_ITERS, restart=30, max_restarts=20, rtol=1e-8) -> SolveOpts:
+    """FP64 flexible GMRES with the CPR preconditioner."""
+    return solve_opts(restart=restart, max_restarts=max_restarts, rtol=rtol, precond=ISC_PC_CPR, p_iters=p_iters)
 
 
 class Context:
     """One ``isc_ctx``: a grid, its physics card, rock, wells and workspace."""
 
     def __init__(self, wl: I.Workload, fluid: I.Fluid | None = None, restart: int = 30,
-                 inner_iters: int = 0, device: str = "cuda"):
+                 inner_iters: int = 0, device: str = "cuda", cpr_p_iters: int | None = None):
         L = lib()
         self.wl = wl
         self.n = wl.ncell
@@ -118,6 +129,9 @@ class Context:
         self.logk = torch.tensor(wl.logk, dtype=torch.float64, device=self.device)
         self.poro = torch.tensor(wl.poro, dtype=torch.float64, device=self.device)
         self.max_opts = solve_opts(restart=restart, inner_iters=inner_iters)
+        if cpr_p_iters is not None:   # also allocate the CPR preconditioner
+            self.max_opts.precond = ISC_PC_CPR
+            self.max_opts.p_iters = cpr_p_iters
         self.stream = torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
         st = L.isc_create(ctypes.byref(self._grid), ctypes.byref(self.fluid), _ptr(self.logk), wl.kv_over_kh,
@@ -218,6 +232,17 @@ class Context:
         self._check(lib().isc_bilu0_apply_spmv(self.h, _ptr(Jdec), _ptr(Dinv), _ptr(r), _ptr(z), _ptr(w)))
         return z, w
 
+    def isc_cpr_pressure_solve(self, Jdec, rp, p_iters=CPR_P_ITERS, e=None):
+        e = torch.empty_like(rp) if e is None else e
+        self._check(lib().isc_cpr_pressure_solve(self.h, _ptr(Jdec), p_iters, _ptr(rp), _ptr(e)))
+        return e
+
+    def isc_cpr_apply(self, Jdec, r, p_iters=CPR_P_ITERS, z=None, w=None):
+        z = torch.empty_like(r) if z is None else z
+        w = torch.empty_like(r) if w is None else w
+        self._check(lib().isc_cpr_apply(self.h, _ptr(Jdec), p_iters, _ptr(r), _ptr(z), _ptr(w)))
+        return z, w
+
     def isc_update(self, u, du):
         return lib().isc_update(self.h, _ptr(u), _ptr(du))
 
@@ -255,7 +280,7 @@ def isc_scaled_norm_noalloc(grid: I.Grid, fluid: I.Fluid, poro: torch.Tensor, F:
                                          _ptr(res), ctypes.c_void_p(s.cuda_stream))
 
 
-PROF_CLASSES = ("spmv", "ilu_apply", "assemble", "decouple", "ilu_factor", "krylov", "ilu_apply32", "spmv32",
+PROF_CLASSES = ("spmv", "ilu_apply", "assemble", "decouple", "ilu_factor", "krylov", "cpr_pressure", "cpr_setup",
                 "ilu_spmv", "ilu_spmv32")
 
 
