@@ -12,6 +12,12 @@ cost of the differentiation form (forward and backward ms per step of the
 adjoint of cumulative oil production on the 60x60x10 grid).
 
     python bench.py [--steps K] [--warmup W] [--workload C3] [--precision fp64|mixed]
+                    [--precond bilu0|cpr] [--p-iters 8]
+
+Unless --no-forms, a third leg runs the FP64 solve with the CPR two-stage
+preconditioner (pressure multigrid + BILU(0), in FP64 flexible GMRES) on the
+same workload and window.  The default window (5 warm-up, 20 timed Newton
+iterations) is the one the benchmark is quoted on.
 """
 from __future__ import annotations
 
@@ -33,11 +39,13 @@ UNIT = "cells·Newton-its/s"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
+    ap.add_argument("--precond", default="bilu0", choices=("bilu0", "cpr"))
     ap.add_argument("--inner", type=int, default=12, help="FP32 inner iterations (mixed)")
+    ap.add_argument("--p-iters", type=int, default=8, help="pressure GMRES steps per CPR application")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision and the adjoint-cost legs")
@@ -120,6 +128,7 @@ class Driver:
         self.inner_its = 0
         self.steps_done = 0
         self.cuts = 0
+        self.lin_each = []       # Krylov iterations of every solving Newton iteration
 
     def newton_iteration(self):
         from paper_1811_11992_amd import isc
@@ -136,6 +145,7 @@ class Driver:
                 self.ni_in_step += 1
                 self.lin_its += info.lin.iters
                 self.inner_its += info.lin.inner_iters_total
+                self.lin_each.append(info.lin.iters)
                 return info
             # failed step: restore and halve the step
             self.u.copy_(self.u_old)
@@ -144,6 +154,20 @@ class Driver:
             self.ni_in_step = 0
             if self.cuts > 40:
                 raise RuntimeError(f"too many step cuts (status {st})")
+
+
+def host_cpu():
+    """The host's CPU model and logical core count (the oracle uses one)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_logical_cpus": os.cpu_count()}
 
 
 def cpu_baseline(wl, layers):
@@ -162,27 +186,32 @@ def cpu_baseline(wl, layers):
     t0 = time.perf_counter()
     st, u, info = m.newton_step(sub.u0, sub.u0, sub.dt)
     el = time.perf_counter() - t0
-    return {"value": n / el, "unit": UNIT, "cores": 1, "kind": "oracle",
+    return {"value": n / el, "unit": UNIT, "cores": 1, "kind": "oracle", **host_cpu(),
             "sample": f"one Newton iteration (assemble, decouple, BILU(0)-GMRES(30) to 1e-8, update) of the "
                       f"serial FP64 oracle on the top {layers} layers of {wl.name} ({n} cells), first step "
                       f"from the initial state; {info.iters_lin} GMRES iterations, {el:.1f} s",
             "status": int(st)}
 
 
-def run_newton(wl, precision, inner, warmup, steps):
+def run_newton(wl, precision, inner, warmup, steps, precond="bilu0", p_iters=8):
     """Times `steps` solving Newton iterations; returns (rate, seconds,
     statistics, class profile, extra-vector tally)."""
     import torch
     from paper_1811_11992_amd import isc
     mixed = precision == "mixed"
-    ctx = isc.Context(wl, restart=30, inner_iters=inner if mixed else 0)
-    lin = isc.solve_opts(restart=30, max_restarts=20, rtol=1e-8,
-                         precision=isc.ISC_MIXED if mixed else isc.ISC_FP64, inner_iters=inner if mixed else 0)
+    cpr = precond == "cpr"
+    ctx = isc.Context(wl, restart=30, inner_iters=inner if mixed else 0, cpr_p_iters=p_iters if cpr else None)
+    if cpr:
+        lin = isc.cpr_opts(p_iters=p_iters, restart=30, max_restarts=20, rtol=1e-8)
+    else:
+        lin = isc.solve_opts(restart=30, max_restarts=20, rtol=1e-8,
+                             precision=isc.ISC_MIXED if mixed else isc.ISC_FP64, inner_iters=inner if mixed else 0)
     drv = Driver(ctx, wl, lin)
     for _ in range(warmup):
         drv.newton_iteration()
     torch.cuda.synchronize()
     ni0, lin0, inner0 = drv.ni, drv.lin_its, drv.inner_its
+    steps0 = drv.steps_done
     isc.isc_profile(ctx, 1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -194,7 +223,9 @@ def run_newton(wl, precision, inner, warmup, steps):
     vec = isc.isc_profile_vectors(ctx)
     stats = {"gmres_its_per_newton": round((drv.lin_its - lin0) / max(1, drv.ni - ni0), 2),
              "inner_its_per_newton": round((drv.inner_its - inner0) / max(1, drv.ni - ni0), 2),
-             "timesteps_completed": drv.steps_done, "step_cuts": drv.cuts, "nnzb": ctx.nnzb}
+             "gmres_its_each": drv.lin_each[ni0:],
+             "timesteps_completed": drv.steps_done, "timesteps_completed_in_window": drv.steps_done - steps0,
+             "step_cuts": drv.cuts, "nnzb": ctx.nnzb}
     ctx.close()
     del drv, ctx
     gc.collect()
@@ -314,7 +345,10 @@ def main():
 
     wl = I.make_workload(a.workload)
     n = wl.ncell
-    value, el, stats, prof, vec = run_newton(wl, a.precision, a.inner, a.warmup, a.steps)
+    if a.precond == "cpr" and a.precision != "fp64":
+        print("the CPR preconditioner runs in FP64 only", file=sys.stderr)
+        sys.exit(2)
+    value, el, stats, prof, vec = run_newton(wl, a.precision, a.inner, a.warmup, a.steps, a.precond, a.p_iters)
     base_bytes = algorithmic_bytes(n, stats["nnzb"])
     nbytes = launch_bytes(base_bytes, prof, vec, n)
     mixed = a.precision == "mixed"
@@ -325,13 +359,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.nx}x{wl.ny}x{wl.nz} cells, "
                                + ("FP32 BILU(0) + inner SpMV in FP64 FGMRES(30)" if mixed
-                                  else "FP64 BILU(0)-GMRES(30)") + " to 1e-8, Newton 1e-10",
+                                  else f"FP64 CPR (pressure multigrid, {a.p_iters} steps) + BILU(0) in FGMRES(30)"
+                                  if a.precond == "cpr" else "FP64 BILU(0)-GMRES(30)") + " to 1e-8, Newton 1e-10",
                    "cells": n, "precision": a.precision, "newton_its_timed": a.steps,
                    **{k: v for k, v in stats.items() if k != "nnzb"}},
         "roofline": roofline(prof, nbytes, wl.name),
         "kernel_classes": classes_of(prof, nbytes),
     }
-    if not a.no_forms:
+    if not a.no_forms and a.precond == "bilu0":
         other = "fp64" if mixed else "mixed"
         v2, el2, st2, prof2, vec2 = run_newton(wl, other, a.inner, a.warmup, a.steps)
         nbytes2 = launch_bytes(base_bytes, prof2, vec2, n)
@@ -342,6 +377,14 @@ def main():
             "mixed_over_fp64": (v2 / value) if not mixed else (value / v2),
         }
         out["adjoint"] = adjoint_cost()
+        v3, el3, st3, prof3, vec3 = run_newton(wl, "fp64", a.inner, a.warmup, a.steps, "cpr", a.p_iters)
+        nbytes3 = launch_bytes(base_bytes, prof3, vec3, n)
+        out["preconditioners"] = {
+            "cpr": {"value": v3, "ms_per_step": el3 / a.steps * 1e3, "p_iters": a.p_iters,
+                    **{k: v for k, v in st3.items() if k != "nnzb"},
+                    "roofline": roofline(prof3, nbytes3, wl.name), "kernel_classes": classes_of(prof3, nbytes3)},
+            "cpr_over_bilu0_fp64": v3 / (v2 if mixed else value),
+        }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_layers)
     print(json.dumps(out), flush=True)
