@@ -267,6 +267,13 @@ isc_status isc_bilu0_apply_spmv(isc_ctx* ctx, const double* Jdec, const double* 
  * isc_cpr_apply: z = CPR r and w = Jdec z (r, z, w: [N][8], distinct). */
 isc_status isc_cpr_pressure_solve(isc_ctx* ctx, const double* Jdec, int32_t p_iters, const double* rp, double* e);
 isc_status isc_cpr_apply(isc_ctx* ctx, const double* Jdec, int32_t p_iters, const double* r, double* z, double* w);
+/* The precision form's product z = M32^-1 r, w = A32 z, as its inner
+ * iteration runs it (block ILU(0) factored from the FP32-rounded blocks of
+ * Jdec, FP32 storage of the factor, the matrix data and the vectors; the
+ * backward sweep fused with the SpMV), for testing: r, z, w are FP64 [N][8],
+ * rounded to FP32 on entry and widened on exit.  Needs a context with max
+ * inner_iters >= 1; ISC_ERR_SINGULAR for a singular pivot block. */
+isc_status isc_bilu0_apply_spmv32(isc_ctx* ctx, const double* Jdec, const double* r, double* z, double* w);
 isc_status isc_update(isc_ctx* ctx, double* u, const double* du /* [N][8] */);
 isc_status isc_scaled_norm(isc_ctx* ctx, const double* F, double dt, double* res_h);
 

@@ -26,6 +26,7 @@ isc_status isc_fgmres(isc_ctx*, const double* A, const double* b, double* x, con
                       isc_solve_info* info);
 isc_status isc_prepare_mixed_dev(isc_ctx*, const double* A, int32_t* bad_dev);
 void isc_cpr_pressure_gmres(isc_ctx*, const double* rp, double* e, int k);
+void isc_apply_spmv32_from64(isc_ctx*, const double* r, double* z, double* w);
 void isc_cpr_apply_w(isc_ctx*, const double* A, const double* u, double* z, double* w, int k);
 isc_status isc_adjoint_impl(isc_ctx*, const double* u_n, const double* u_nm1, double dt_n,
                             const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
@@ -662,6 +663,25 @@ isc_status isc_bilu0_apply_spmv(isc_ctx* ctx, const double* Jdec, const double* 
     }
     ISC_HIP(isc_launch_form_ltilde(ctx, Jdec, Dinv));
     ISC_HIP(isc_launch_bilu0_apply_spmv(ctx, Jdec, Dinv, r, z, w));
+    return isc_check_sweeps(ctx);
+}
+
+isc_status isc_bilu0_apply_spmv32(isc_ctx* ctx, const double* Jdec, const double* r, double* z, double* w) {
+    TRY(check_ctx(ctx));
+    if (!Jdec || !r || !z || !w || r == z || r == w || z == w) {
+        ctx->err = "isc_bilu0_apply_spmv32: null or aliased arrays";
+        return ISC_ERR_ARG;
+    }
+    TRY(reset_flags(ctx));
+    TRY(isc_prepare_mixed_dev(ctx, Jdec, ctx->flags + FLAG_BAD));
+    int32_t bad;
+    TRY(read_flag(ctx, FLAG_BAD, &bad));
+    if (bad != INT32_MAX) {
+        ctx->err = "block ILU(0) (FP32): singular pivot block at cell " + std::to_string(bad);
+        return ISC_ERR_SINGULAR;
+    }
+    isc_apply_spmv32_from64(ctx, r, z, w);
+    ISC_HIP(hipGetLastError());
     return isc_check_sweeps(ctx);
 }
 

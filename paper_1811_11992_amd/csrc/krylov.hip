@@ -621,6 +621,22 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
 
 // ---------------------------------------------------------------- precision form
 hipError_t isc_launch_bilu0_apply_spmv32(isc_ctx*, const float*, const float*, const float*, float*, float*);
+hipError_t isc_launch_bilu0_factor32_from64(isc_ctx*, const double*, float*, float*, int32_t*);
+
+// Set-up of the precision form: the block ILU(0) factor of the decoupled
+// matrix rounded to FP32 (computed in FP64 arithmetic from the FP32-rounded
+// blocks, stored in FP32, with the sweeps' FP32 packs).  The FP32 copy of the
+// matrix itself is made only for the per-hyperplane schedule, whose sweeps
+// read it.  Launches only (no host synchronisation); a singular pivot block
+// is reported through bad_dev like the FP64 factor.
+isc_status isc_prepare_mixed_dev(isc_ctx* ctx, const double* A, int32_t* bad_dev) {
+    if (!ctx->J32) {
+        ctx->err = "mixed precision needs a context created with max inner_iters >= 1";
+        return ISC_ERR_ARG;
+    }
+    ISC_HIP(isc_launch_bilu0_factor32_from64(ctx, A, ctx->J32, ctx->Dinv32, bad_dev));
+    return ISC_OK;
+}
 hipError_t isc_launch_update_apply_spmv32(isc_ctx*, const float*, const float*, const isc::LagUpdateT<float>&, float*,
                                           float*);
 
@@ -760,6 +776,21 @@ static void cpr_apply_w(isc_ctx* ctx, const double* A, const double* u, double* 
 }  // namespace isc
 
 void isc_cpr_pressure_gmres(isc_ctx* ctx, const double* rp, double* e, int k) { isc::pressure_gmres(ctx, rp, e, k); }
+
+// z = M32^-1 r and w = A32 z with the FP32 factor and matrix data prepared by
+// isc_prepare_mixed_dev (the inner iteration's product, without its folded
+// Gram-Schmidt update); r, z, w FP64, rounded to and from FP32 storage.
+void isc_apply_spmv32_from64(isc_ctx* ctx, const double* r, double* z, double* w) {
+    using namespace isc;
+    const int64_t len = (int64_t)ctx->n * NU;
+    const int nb = nblocks(len);
+    float* r32 = ctx->V32;
+    float* z32 = ctx->Z32;
+    hipLaunchKernelGGL(narrow_f32, dim3(nb), dim3(256), 0, ctx->stream, len, r, r32);
+    isc_launch_bilu0_apply_spmv32(ctx, ctx->J32, ctx->Dinv32, r32, z32, ctx->w32);
+    hipLaunchKernelGGL(to_f64, dim3(nb), dim3(256), 0, ctx->stream, len, (const float*)z32, z);
+    hipLaunchKernelGGL(to_f64, dim3(nb), dim3(256), 0, ctx->stream, len, (const float*)ctx->w32, w);
+}
 void isc_cpr_apply_w(isc_ctx* ctx, const double* A, const double* u, double* z, double* w, int k) {
     isc::cpr_apply_w(ctx, A, u, z, w, k);
 }

@@ -76,6 +76,7 @@ def lib():
         L.isc_bilu0_apply.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.isc_bilu0_apply_spmv.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
         L.isc_update.argtypes = [_vp, _vp, _vp]
+        L.isc_bilu0_apply_spmv32.argtypes = [_vp, _vp, _vp, _vp, _vp]
         L.isc_cpr_pressure_solve.argtypes = [_vp, _vp, _i32, _vp, _vp]
         L.isc_cpr_apply.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
         L.isc_scaled_norm.argtypes = [_vp, _vp, _f64, ctypes.POINTER(_f64)]
@@ -91,7 +92,7 @@ def lib():
                      "isc_decouple", "isc_solve", "isc_solve_bicgstab", "isc_newton_step", "isc_spmv", "isc_bilu0",
                      "isc_bilu0_apply", "isc_bilu0_apply_spmv", "isc_update", "isc_scaled_norm", "isc_adjoint",
                      "isc_profile", "isc_profile_vectors", "isc_oil_rate", "isc_scaled_norm_noalloc",
-                     "isc_cpr_pressure_solve", "isc_cpr_apply"):
+                     "isc_cpr_pressure_solve", "isc_cpr_apply", "isc_bilu0_apply_spmv32"):
             getattr(L, name).restype = _i32
         _LIB = L
     return _LIB
@@ -230,6 +231,12 @@ class Context:
         z = torch.empty_like(r) if z is None else z
         w = torch.empty_like(r) if w is None else w
         self._check(lib().isc_bilu0_apply_spmv(self.h, _ptr(Jdec), _ptr(Dinv), _ptr(r), _ptr(z), _ptr(w)))
+        return z, w
+
+    def isc_bilu0_apply_spmv32(self, Jdec, r, z=None, w=None):
+        z = torch.empty_like(r) if z is None else z
+        w = torch.empty_like(r) if w is None else w
+        self._check(lib().isc_bilu0_apply_spmv32(self.h, _ptr(Jdec), _ptr(r), _ptr(z), _ptr(w)))
         return z, w
 
     def isc_cpr_pressure_solve(self, Jdec, rp, p_iters=CPR_P_ITERS, e=None):
