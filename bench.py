@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=("fp64", "mixed"))
     ap.add_argument("--precond", default="bilu0", choices=("bilu0", "cpr"))
     ap.add_argument("--inner", type=int, default=12, help="FP32 inner iterations (mixed)")
-    ap.add_argument("--p-iters", type=int, default=8, help="pressure GMRES steps per CPR application")
+    ap.add_argument("--p-iters", type=int, default=12, help="pressure GMRES steps per CPR application")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision and the adjoint-cost legs")

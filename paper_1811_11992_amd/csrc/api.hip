@@ -439,23 +439,33 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     }
     if (mo.precond == ISC_PC_CPR) {   // CPR: multigrid levels and stage-1 buffers
         isc_cpr_plan(ctx);
+        if (ctx->mg.back().n > ISC_CPR_COARSEST) {
+            ctx->err = "grid too large for the pressure multigrid's level count";
+            return fail(ISC_ERR_ARG);
+        }
         size_t words = 0;
-        for (size_t l = 0; l < ctx->mg.size(); ++l) words += (size_t)ctx->mg[l].n * (l == 0 ? 7 : 9);
+        for (size_t l = 0; l < ctx->mg.size(); ++l) words += (size_t)2 * ctx->mg[l].lh * (l == 0 ? 7 : 9);
         ALLOC(ctx->mg_store, words);
+        // the holes of the colour-split order stay zero in every stencil and vector
+        if (hipMemsetAsync(ctx->mg_store, 0, words * sizeof(double), ctx->stream) != hipSuccess) {
+            ctx->err = "clearing the CPR levels failed";
+            return fail(ISC_ERR_HIP);
+        }
         double* p = ctx->mg_store;
         for (size_t l = 0; l < ctx->mg.size(); ++l) {
             isc_ctx::MgLevel& L = ctx->mg[l];
+            const size_t ns = (size_t)2 * L.lh;
             L.co = p;
-            p += (size_t)7 * L.n;
+            p += 7 * ns;
             if (l > 0) {
                 L.x = p;
-                p += L.n;
+                p += ns;
                 L.b = p;
-                p += L.n;
+                p += ns;
             }
         }
         ctx->cpr_kmax = mo.p_iters;
-        ctx->cpr_npad = (n + 7) & ~7;
+        ctx->cpr_npad = (int32_t)((2 * (int64_t)ctx->mg[0].lh + 7) & ~7);
         const size_t np = (size_t)ctx->cpr_npad;
         ALLOC(ctx->mg_cinv, (size_t)ISC_CPR_COARSEST * ISC_CPR_COARSEST);
         ALLOC(ctx->cpr_pc, (size_t)ctx->nnzb * 8);
@@ -757,9 +767,9 @@ isc_status isc_cpr_pressure_solve(isc_ctx* ctx, const double* Jdec, int32_t p_it
         return ISC_ERR_ARG;
     }
     TRY(cpr_prepare(ctx, Jdec, p_iters, "isc_cpr_pressure_solve"));
-    ISC_HIP(hipMemcpyAsync(ctx->cpr_rp, rp, (size_t)ctx->n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    isc_cpr_to_split(ctx, rp, ctx->cpr_rp);
     isc_cpr_pressure_gmres(ctx, ctx->cpr_rp, ctx->cpr_ep, p_iters);
-    ISC_HIP(hipMemcpyAsync(e, ctx->cpr_ep, (size_t)ctx->n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    isc_cpr_from_split(ctx, ctx->cpr_ep, e);
     ISC_HIP(hipStreamSynchronize(ctx->stream));
     return isc_check_sweeps(ctx);
 }

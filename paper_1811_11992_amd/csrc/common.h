@@ -218,13 +218,15 @@ struct isc_ctx {
     // for CPR (cpr_kmax = the most pressure GMRES steps, -1 = not allocated)
     struct MgLevel {
         int32_t nx, ny, nz, n;
-        double* co;     // [7][n] stencil
-        double* x;      // [n] (levels >= 1; level 0 uses the caller's vectors)
-        double* b;      // [n]
+        int32_t hx, lh;   // colour-split order: positions per row and colour, per colour
+        double* co;       // [7][2 lh] stencil
+        double* x;        // [2 lh] (levels >= 1; level 0 uses the caller's vectors)
+        double* b;        // [2 lh]
     };
     std::vector<MgLevel> mg;
     int32_t cpr_kmax = -1;
-    int32_t cpr_npad = 0;          // pressure vector length, padded to a multiple of 8
+    int32_t mg_fused_first = 0;    // levels from this one down run in one workgroup launch
+    int32_t cpr_npad = 0;          // pressure vector length (colour-split order), padded to a multiple of 8
     double* mg_store = nullptr;    // all levels' stencils and vectors
     double* mg_cinv = nullptr;     // [nc][nc] inverse of the coarsest matrix
     double* cpr_pc = nullptr;      // [nnzb][8] column 0 of every block of the decoupled matrix
@@ -272,6 +274,8 @@ constexpr int NPART = ISC_NPART;  // partial sums per reduction (block count of 
 #define ISC_CPR_CF 1.5
 #define ISC_CPR_COARSEST 64
 #define ISC_CPR_MAX_K 16      // most GMRES steps of the pressure solve
+#define ISC_CPR_MAXLEV 16     // most multigrid levels
+#define ISC_CPR_FUSED_MAX 8192   // levels of at most this many positions are cycled by one workgroup
 
 void isc_cpr_plan(isc_ctx* ctx);
 hipError_t isc_cpr_setup(isc_ctx* ctx, const double* A, int32_t* bad_dev);
@@ -280,6 +284,8 @@ void isc_cpr_pressure_apply(isc_ctx* ctx, const double* x, double* y);
 void isc_cpr_gather(isc_ctx* ctx, const double* u, double* rp);
 void isc_cpr_stage1(isc_ctx* ctx, const double* ep, const double* u, double* w1, double* r2);
 void isc_cpr_combine(isc_ctx* ctx, const double* ep, double* z, double* w, const double* w1);
+void isc_cpr_to_split(isc_ctx* ctx, const double* nat, double* split);
+void isc_cpr_from_split(isc_ctx* ctx, const double* split, double* nat);
 
 // Profiling helpers (host).  prof_begin/prof_end bracket a kernel class on the
 // context stream; prof_drain converts finished pairs to milliseconds and must

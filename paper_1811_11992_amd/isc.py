@@ -22,7 +22,7 @@ ISC_OK, ISC_ERR_ARG, ISC_ERR_HIP, ISC_ERR_OOM = 0, -1, -2, -3
 ISC_ERR_SINGULAR, ISC_ERR_NONFINITE, ISC_ERR_LINEAR_NOCONV, ISC_ERR_NEWTON_NOCONV = -4, -5, -6, -7
 ISC_FP64, ISC_MIXED = 0, 1
 ISC_PC_BILU0, ISC_PC_CPR = 0, 1
-CPR_P_ITERS = 6     # default GMRES steps of the CPR pressure solve
+CPR_P_ITERS = 12    # default GMRES steps of the CPR pressure solve
 
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
