@@ -1,6 +1,6 @@
 """Times the linear-algebra kernels of one Newton iteration on a workload.
 
-    python -m paper_1811_11992_amd.kernel_bench [--workload C3] [--reps 20]
+    python -m paper_1811_11992_amd.kernel_bench [--workload C3] [--reps 20] [--only linear|assemble]
 
 Builds the decoupled Jacobian at the workload's initial state (assemble,
 decouple, BILU(0) factor through the C-ABI), then times ``isc_bilu0_apply``,
@@ -23,13 +23,38 @@ from . import inputs as I
 from . import isc
 
 
+def assemble_only(wl, c, reps):
+    """Times the property pass + face assembly alone (isc_assemble) at a state
+    one Newton step away from the initial one, so that the reactions and the
+    upstream choices are those of a burning front."""
+    u0 = torch.tensor(wl.u0, dtype=torch.float64, device="cuda")
+    u = u0.clone()
+    st, info = c.isc_newton_step(u, u0, wl.dt)
+    F, J = c.isc_assemble(u, u0, wl.dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        c.isc_assemble(u, u0, wl.dt, F, J)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    print(json.dumps({"workload": wl.name, "cells": c.n, "reps": reps, "assemble_ms": round(ms, 4),
+                      "finite": bool(torch.isfinite(F).all())}), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--only", choices=("linear", "assemble"), default="linear",
+                    help="time the linear-algebra kernels (default) or the assembly alone")
     a = ap.parse_args(argv)
     wl = I.make_workload(a.workload)
     c = isc.Context(wl)
+    if a.only == "assemble":
+        assemble_only(wl, c, a.reps)
+        c.close()
+        torch.cuda.synchronize()
+        return
     u = torch.tensor(wl.u0, dtype=torch.float64, device="cuda")
     F, J = c.isc_assemble(u, u, wl.dt)
     c.isc_decouple(J, F)
