@@ -185,6 +185,14 @@ isc_status isc_destroy(isc_ctx* ctx);
  * (host [4], or NULL); transmissibilities and well indices are recomputed. */
 isc_status isc_set_params(isc_ctx* ctx, const double* logk, const double* A_h);
 
+/* A heat source of rate_W watts in the energy balance of one cell, as the
+ * ignition heater of the combustion tube (Section 4.1, well table: "heat
+ * rate" and "heat stop time"), independent of the state; it enters every
+ * later residual until changed.  cell < 0 or rate_W = 0 removes it.  The
+ * caller switches it off at the stop time.  ISC_ERR_ARG for a cell outside
+ * the grid or a non-finite rate. */
+isc_status isc_set_heater(isc_ctx* ctx, int32_t cell, double rate_W);
+
 /* Block CSR pattern (device pointers owned by the context) and its size. */
 isc_status isc_bcsr_pattern(const isc_ctx* ctx, const int32_t** row_ptr, const int32_t** col_idx,
                             int32_t* nnzb_h);

@@ -64,6 +64,7 @@ def lib():
         L.orc_nnzb.restype = ctypes.c_int32
         L.orc_pattern.argtypes = [ctypes.c_void_p, _ip, _ip]
         L.orc_set_params.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.orc_set_heater.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double]
         L.orc_perf_info.argtypes = [ctypes.c_void_p, _ip, _ip, _dp, _dp]
         L.orc_diag.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_zfactor.restype = ctypes.c_double
@@ -154,6 +155,9 @@ class Model:
         lk = None if logk is None else np.ascontiguousarray(logk, np.float64)
         a = None if A is None else np.ascontiguousarray(A, np.float64)
         lib().orc_set_params(self.h, _p(lk), _p(a))
+
+    def set_heater(self, cell, rate_W):
+        lib().orc_set_heater(self.h, int(cell), float(rate_W))
 
     def perf_info(self):
         npf = sum(len(w["cells"]) for w in self.wl.wells)

@@ -24,6 +24,8 @@ struct orc_model {
     std::vector<orc_perf> perfs;
     std::vector<orc_well> wells_in;        /* shallow copies for WI recompute */
     std::vector<std::vector<int32_t>> well_cells;
+    int32_t heater_cell = -1;     /* a heat source in one cell's energy balance (W), or none */
+    double heater_W = 0.0;
 };
 
 namespace orc {

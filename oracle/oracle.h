@@ -73,6 +73,9 @@ void orc_pattern(const orc_model* m, int32_t* row_ptr, int32_t* col_idx);
 /* replace ln k (may be NULL) and/or the frequency factors A_R (may be NULL) */
 void orc_set_params(orc_model* m, const double* logk, const double* A);
 void orc_perf_info(const orc_model* m, int32_t* cells, int32_t* kinds, double* wi, double* q);
+/* heat source rate_W (W) in the energy balance of one cell; cell < 0 or
+ * rate 0: none.  It counts with the well terms in orc_sources. */
+void orc_set_heater(orc_model* m, int32_t cell, double rate_W);
 
 /* diagnostics for the pins: per-cell secondary quantities at state u.
  * out[N][ORC_NDIAG], see ORC_DIAG_* */

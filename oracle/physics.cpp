@@ -420,6 +420,9 @@ static int assemble_impl(orc_model& m, const double* u, const double* u_old, dou
             F[(size_t)i * 8 + 6] -= W.qE;
         }
     }
+    /* heater: a fixed heat rate into one cell (the ignition heater of the
+     * combustion tube, Section 4.1), independent of the state */
+    if (m.heater_cell >= 0) F[(size_t)m.heater_cell * 8 + 6] -= m.heater_W;
     /* faces, each evaluated once with (lo, hi) = (min, max) cell index */
     const orc_grid& g = m.g;
     for (int32_t lo = 0; lo < n; ++lo) {
@@ -570,6 +573,11 @@ void orc_pattern(const orc_model* m, int32_t* row_ptr, int32_t* col_idx) {
     std::copy(m->col_idx.begin(), m->col_idx.end(), col_idx);
 }
 
+void orc_set_heater(orc_model* m, int32_t cell, double rate_W) {
+    m->heater_cell = (cell >= 0 && cell < m->n && rate_W != 0.0) ? cell : -1;
+    m->heater_W = m->heater_cell >= 0 ? rate_W : 0.0;
+}
+
 void orc_set_params(orc_model* m, const double* logk, const double* A) {
     if (logk) {
         m->logk.assign(logk, logk + m->n);
@@ -677,6 +685,7 @@ void orc_sources(orc_model* m, const double* u, double* wells_out, double* reac_
                 wells_out[(size_t)i * 8 + 6] += W.qE;
             }
         }
+        if (m->heater_cell >= 0) wells_out[(size_t)m->heater_cell * 8 + 6] += m->heater_W;
     }
 }
 

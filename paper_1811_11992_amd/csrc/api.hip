@@ -602,6 +602,18 @@ isc_status isc_set_params(isc_ctx* ctx, const double* logk, const double* A_h) {
     return ISC_OK;
 }
 
+isc_status isc_set_heater(isc_ctx* ctx, int32_t cell, double rate_W) {
+    TRY(check_ctx(ctx));
+    if (cell >= ctx->n || !std::isfinite(rate_W)) {
+        ctx->err = "isc_set_heater: cell outside the grid or rate not finite";
+        return ISC_ERR_ARG;
+    }
+    const bool on = cell >= 0 && rate_W != 0.0;
+    ctx->heater_cell = on ? cell : -1;
+    ctx->heater_W = on ? rate_W : 0.0;
+    return ISC_OK;
+}
+
 isc_status isc_bcsr_pattern(const isc_ctx* ctx, const int32_t** row_ptr, const int32_t** col_idx,
                             int32_t* nnzb_h) {
     if (!ctx) return ISC_ERR_ARG;

@@ -133,6 +133,8 @@ struct isc_ctx {
     std::vector<isc_well> wells;
     std::vector<std::vector<int32_t>> well_cells;
     int32_t npf = 0;
+    int32_t heater_cell = -1;       // heat source into one cell's energy balance (isc_set_heater)
+    double heater_W = 0.0;
     int32_t* well_slot = nullptr;   // [N] perforation index or -1
     double* perf = nullptr;         // [npf][PERF_W]
     std::vector<double> perf_h;

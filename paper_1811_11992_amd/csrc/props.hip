@@ -277,7 +277,8 @@ __global__ void __launch_bounds__(256) acc_old_kernel(int32_t n, const double* _
 __global__ void __launch_bounds__(256, 2) props_kernel(
     int32_t n, const double* __restrict__ u, const double* __restrict__ acc_old_in, double vol_dt,
     double vol, const double* __restrict__ poro, const int32_t* __restrict__ well_slot,
-    const double* __restrict__ perf, const isc_fluid* __restrict__ fl, double* __restrict__ payload) {
+    const double* __restrict__ perf, const isc_fluid* __restrict__ fl, double* __restrict__ payload,
+    int32_t heater_cell, double heater_W) {
     const int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
     const int k = threadIdx.x & 7;
     if (i >= n) return;
@@ -320,6 +321,8 @@ __global__ void __launch_bounds__(256, 2) props_kernel(
             loc[6].v -= pf[10];
         }
     }
+    // heater: a fixed heat rate into one cell's energy balance
+    if (i == heater_cell) loc[6].v -= heater_W;
 #pragma unroll
     for (int e = 0; e < 8; ++e) put(out + PL_LOCAL + 9 * e, loc[e], k);
 #pragma unroll
@@ -378,6 +381,6 @@ hipError_t isc_launch_props(isc_ctx* ctx, const double* u, const double* u_old, 
     const int blocks = (int)(((int64_t)ctx->n * 8 + threads - 1) / threads);
     hipLaunchKernelGGL(isc::props_kernel, dim3(blocks), dim3(threads), 0, ctx->stream, ctx->n, u,
                        ctx->acc_old, vol / dt, vol, ctx->poro, ctx->well_slot, ctx->perf, ctx->fluid_d,
-                       ctx->payload);
+                       ctx->payload, ctx->heater_cell, ctx->heater_W);
     return hipGetLastError();
 }

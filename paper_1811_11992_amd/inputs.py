@@ -35,6 +35,9 @@ BTU_LBMOL_R = 4.1868             # J/(mol K) per Btu/(lbmol R)
 DAY = 86400.0                    # s per day
 CP = 1.0e-3                      # Pa s per cP
 MD = 9.869233e-16                # m2 per millidarcy
+FT = 0.3048                      # m per ft
+BTU = 1055.05585262              # J per Btu (IT)
+R_GAS = 8.314462618              # J/(mol K)
 
 
 def degF_to_K(tf: float) -> float:
@@ -299,6 +302,9 @@ class Workload:
     dt: float                 # s
     nsteps: int
     seed: int
+    # a heat source in one cell's energy balance: dict(cell, rate_W, stop_s) -- on
+    # from time 0 until stop_s -- or None
+    heater: dict | None = None
 
     @property
     def ncell(self) -> int:
@@ -468,6 +474,44 @@ def make_workload(name: str, nsteps: int | None = None) -> Workload:
             ign = [cell_index(nx, ny, a, b, 0) for a, b in injxy]
         u0 = initial_state(nx, ny, nz, ign)
         steps = 10
+    elif name == "TUBE":
+        # The combustion tube of Section 4.1 (tables "Input data for tube model"):
+        # 0.1602 ft x 0.1602 ft x 2.6458 ft in 12 cells stacked vertically,
+        # k = 12,700 mD, phi = 0.4142; initially 2014.7 psi, 100 F, saturations
+        # (0.178, 0.654, 0.168), x_LO = 0.744 and air in the gas; air injected
+        # into the top cell at 0.554 ft3/hr at standard conditions (60 F,
+        # 14.696 psia) and 70 F, fluids produced from the bottom cell at a
+        # bottom-hole pressure of 2014.7 psi, both wells with the table's well
+        # index, and a heater of 4800 Btu/day in the top cell for the first
+        # 0.0208333 day.  One-minute steps; the heater's 30 minutes are the
+        # first 30.
+        seed, nx, ny, nz = 0, 1, 1, 12
+        dx = dy = 0.1602 * FT
+        dz = 2.6458 * FT / nz
+        n = nz
+        logk = np.full(n, math.log(12700.0 * MD))
+        kvkh = 1.0
+        poro = np.full(n, 0.4142)
+        t_std, p_std = degF_to_K(60.0), 14.696 * PSI
+        q_air = p_std * (0.554 * FT ** 3) / (R_GAS * t_std) / 3600.0      # mol/s
+        # The table's well index, 5.54 ft md, for both wells.  The wells take a
+        # Peaceman index 2 pi dz k / (ln(r_e / r_w) + skin); the skin that gives
+        # the table's value carries it (the tube's cells are narrower than a
+        # wellbore, so the geometric part alone does not apply).
+        wi = 5.54 * FT * MD
+        r_e = 0.14 * math.sqrt(dx * dx + dy * dy)
+        skin = 2 * math.pi * dz * 12700.0 * MD / wi - math.log(r_e / 0.1)
+        wells = [dict(kind=WELL_RATE_INJECTOR, cells=[0], target=q_air, T_inj=degF_to_K(70.0), z_inj=AIR,
+                      skin=skin),
+                 dict(kind=WELL_BHP_PRODUCER, cells=[n - 1], target=2014.7 * PSI, skin=skin)]
+        u0 = initial_state(nx, ny, nz, [])
+        u0[T] = degF_to_K(100.0)
+        dt = 60.0
+        steps = 40
+        heater = dict(cell=0, rate_W=4800.0 * BTU / DAY, stop_s=0.02083333333 * DAY)
+        return Workload(name=name, nx=nx, ny=ny, nz=nz, dx=dx, dy=dy, dz=dz, logk=logk, kv_over_kh=kvkh,
+                        poro=poro, wells=wells, u0=u0, dt=dt, nsteps=nsteps if nsteps is not None else steps,
+                        seed=seed, heater=heater)
     elif name.startswith("tiny:"):
         dims = name.split(":")[1]
         nx, ny, nz = (int(v) for v in dims.split("x"))

@@ -64,6 +64,7 @@ def lib():
         L.isc_create.argtypes = [_vp, _vp, _vp, _f64, _vp, _vp, _i32, _vp, _vp, ctypes.POINTER(_vp)]
         L.isc_destroy.argtypes = [_vp]
         L.isc_set_params.argtypes = [_vp, _vp, _vp]
+        L.isc_set_heater.argtypes = [_vp, _i32, _f64]
         L.isc_bcsr_pattern.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i32)]
         L.isc_assemble.argtypes = [_vp, _vp, _vp, _f64, _vp, _vp]
         L.isc_decouple.argtypes = [_vp, _vp, _vp, ctypes.POINTER(_i32)]
@@ -92,7 +93,7 @@ def lib():
                      "isc_decouple", "isc_solve", "isc_solve_bicgstab", "isc_newton_step", "isc_spmv", "isc_bilu0",
                      "isc_bilu0_apply", "isc_bilu0_apply_spmv", "isc_update", "isc_scaled_norm", "isc_adjoint",
                      "isc_profile", "isc_profile_vectors", "isc_oil_rate", "isc_scaled_norm_noalloc",
-                     "isc_cpr_pressure_solve", "isc_cpr_apply", "isc_bilu0_apply_spmv32"):
+                     "isc_cpr_pressure_solve", "isc_cpr_apply", "isc_bilu0_apply_spmv32", "isc_set_heater"):
             getattr(L, name).restype = _i32
         _LIB = L
     return _LIB
@@ -174,6 +175,9 @@ class Context:
         if logk is not None:
             self.logk = logk.to(self.device, torch.float64).contiguous()
         self._check(lib().isc_set_params(self.h, _ptr(logk if logk is None else self.logk), a))
+
+    def isc_set_heater(self, cell: int, rate_W: float):
+        self._check(lib().isc_set_heater(self.h, int(cell), float(rate_W)))
 
     def isc_assemble(self, u, u_old, dt, F=None, J=None):
         F = self.empty_F() if F is None else F
