@@ -235,13 +235,17 @@ isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* 
  * stabilised bi-conjugate gradient method of the paper's experiments
  * (Section 4, where it runs with RAS or CPR-PF preconditioning).  Stops when
  * the updated residual meets ||r||_2 <= rtol ||b||_2, then checks the true
- * residual and, if it is still above, restarts from it.  b, x: [N][8]
- * (distinct).  Uses seven of the context's Krylov vectors (max restart >= 6).
- * info_h (may be NULL): iters = iterations (two preconditioned products
- * each), restarts, relres_est = the last updated residual / ||b||,
- * relres_true.  Returns ISC_ERR_LINEAR_NOCONV after max_iters iterations or a
- * breakdown (rho = 0, (r~, v) = 0, (t, t) = 0 or omega = 0) unless the true
- * residual already meets the tolerance; ISC_ERR_SINGULAR from the factor. */
+ * residual and, if it is still above, restarts from it.  A breakdown --
+ * |(r~, r)| <= 1e-12 ||r~|| ||r||, |(r~, v)| <= 1e-12 ||r~|| ||v||, (t, t) = 0
+ * (after keeping the half step x += alpha p^, whose residual is s) or
+ * omega = 0 -- also restarts from the true residual, which becomes the new
+ * shadow vector r~, at most 8 times.  b, x: [N][8] (distinct).  Uses seven
+ * of the context's Krylov vectors (max restart >= 6).  info_h (may be NULL):
+ * iters = iterations (two preconditioned products each), restarts,
+ * relres_est = the last updated residual / ||b||, relres_true.  Returns
+ * ISC_ERR_LINEAR_NOCONV after max_iters iterations or a ninth breakdown
+ * unless the true residual already meets the tolerance; ISC_ERR_SINGULAR
+ * from the factor. */
 isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b, double* x,
                               int32_t max_iters, double rtol, isc_solve_info* info_h);
 

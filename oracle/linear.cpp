@@ -305,9 +305,12 @@ int orc_gmres(orc_model* m, const double* A, const double* b, double* x, int32_t
  * with the shadow vector r~ = the starting residual.  The iteration stops once
  * the updated residual (s at the half step, else r) satisfies
  * ||.|| <= rtol ||b||; then the true residual b - A x is formed, and if it is
- * still above the tolerance the iteration starts again from it.  Returns 0,
- * or -6 (no convergence within max_iters, or a breakdown: rho = 0,
- * (r~, v) = 0, (t, t) = 0 or omega = 0). */
+ * still above the tolerance the iteration starts again from it.  A breakdown
+ * -- |rho| <= 1e-12 ||r~|| ||r||, |(r~, v)| <= 1e-12 ||r~|| ||v||,
+ * (t, t) = 0 (after keeping the half step x += alpha p^, whose residual is s)
+ * or omega = 0 -- also starts again from the true residual, with it as the
+ * new shadow vector, at most 8 times.  Returns 0, or -6 (no convergence
+ * within max_iters, or a ninth breakdown). */
 int orc_bicgstab(orc_model* m, const double* A, const double* b, double* x, int32_t max_iters, double rtol,
                  orc_solve_info* info) {
     const size_t N = (size_t)m->n * 8;
@@ -324,7 +327,9 @@ int orc_bicgstab(orc_model* m, const double* A, const double* b, double* x, int3
         return 0;
     }
     const double tol = rtol * bnorm;
-    int status = -6, it = 0, starts = 0;
+    const double brk = 1e-12;        /* relative breakdown threshold */
+    const int max_breakdowns = 8;
+    int status = -6, it = 0, starts = 0, breakdowns = 0;
     while (it < max_iters) {
         orc_spmv(m, A, x, tmp.data());
         for (size_t k = 0; k < N; ++k) r[k] = bb[k] - tmp[k];
@@ -335,16 +340,16 @@ int orc_bicgstab(orc_model* m, const double* A, const double* b, double* x, int3
         rs = r;
         std::fill(p.begin(), p.end(), 0.0);
         std::fill(v.begin(), v.end(), 0.0);
-        double rho_old = 1.0, alpha = 1.0, omega = 1.0, rho = dot(rs, r);
-        bool converged = false;
+        double rho_old = 1.0, alpha = 1.0, omega = 1.0, rho = dot(rs, r), rn = rn0;
+        bool converged = false, breakdown = false;
         while (it < max_iters) {
-            if (rho == 0.0 || !std::isfinite(rho)) break;
+            if (!(std::fabs(rho) > brk * rn0 * rn) || !std::isfinite(rho)) { breakdown = true; break; }
             const double beta = (rho / rho_old) * (alpha / omega);
             for (size_t k = 0; k < N; ++k) p[k] = r[k] + beta * (p[k] - omega * v[k]);
             orc_bilu0_apply(m, LU.data(), Dinv.data(), p.data(), ph.data());
             orc_spmv(m, A, ph.data(), v.data());
             const double rv = dot(rs, v);
-            if (rv == 0.0 || !std::isfinite(rv)) break;
+            if (!(std::fabs(rv) > brk * rn0 * nrm2(v)) || !std::isfinite(rv)) { breakdown = true; break; }
             alpha = rho / rv;
             for (size_t k = 0; k < N; ++k) s[k] = r[k] - alpha * v[k];
             ++it;
@@ -358,19 +363,26 @@ int orc_bicgstab(orc_model* m, const double* A, const double* b, double* x, int3
             orc_bilu0_apply(m, LU.data(), Dinv.data(), s.data(), sh.data());
             orc_spmv(m, A, sh.data(), t.data());
             const double tt = dot(t, t);
-            if (tt == 0.0 || !std::isfinite(tt)) break;
+            if (!(tt > 0.0) || !std::isfinite(tt)) {
+                /* s is the residual of x + alpha p^: keep that half step */
+                for (size_t k = 0; k < N; ++k) x[k] += alpha * ph[k];
+                breakdown = true;
+                break;
+            }
             omega = dot(t, s) / tt;
             for (size_t k = 0; k < N; ++k) {
                 x[k] += alpha * ph[k] + omega * sh[k];
                 r[k] = s[k] - omega * t[k];
             }
-            const double rn = nrm2(r);
+            rn = nrm2(r);
             inf.relres_est = rn / bnorm;
             if (rn <= tol) { converged = true; break; }
-            if (omega == 0.0) break;
+            if (omega == 0.0) { breakdown = true; break; }
             rho_old = rho;
             rho = dot(rs, r);
         }
+        /* a breakdown restarts from the true residual, a bounded number of times */
+        if (breakdown && ++breakdowns <= max_breakdowns) continue;
         if (!converged) break;
     }
     if (status != 0) {

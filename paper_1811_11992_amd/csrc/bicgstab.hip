@@ -16,6 +16,11 @@ namespace isc {
 namespace bcg {
 
 constexpr int BCG_BLOCKS = 1024;   // blocks of the reducing kernels (at most NPART)
+// |(r~, r)| <= BCG_BREAKDOWN ||r~|| ||r|| or |(r~, v)| <= BCG_BREAKDOWN ||r~|| ||v||
+// is a breakdown; the solve restarts from its true residual at most
+// BCG_MAX_BREAKDOWNS times
+constexpr double BCG_BREAKDOWN = 1e-12;
+constexpr int BCG_MAX_BREAKDOWNS = 8;
 static_assert(BCG_BLOCKS <= NPART, "partial rows hold NPART entries");
 
 __device__ __forceinline__ double bcg_wave_sum(double x) {
@@ -76,6 +81,18 @@ __global__ void __launch_bounds__(256) bcg_dot(int64_t len, const double* __rest
     double a[1] = {0.0};
     BCG_LOOP(t) a[0] += a_[t] * b_[t];
     bcg_store<1>(a, partial);
+}
+
+// (a, b) and (b, b)
+__global__ void __launch_bounds__(256) bcg_dot2(int64_t len, const double* __restrict__ a_,
+                                                const double* __restrict__ b_, double* __restrict__ partial) {
+    double a[2] = {0.0, 0.0};
+    BCG_LOOP(t) {
+        const double bt = b_[t];
+        a[0] += a_[t] * bt;
+        a[1] += bt * bt;
+    }
+    bcg_store<2>(a, partial);
 }
 
 // s = r - alpha v, in place of r; (s, s)
@@ -207,10 +224,10 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
         return ISC_ERR_NONFINITE;
     }
     const double tol = rtol * bnorm;
-    int32_t it = 0, starts = 0;
+    int32_t it = 0, starts = 0, breakdowns = 0;
     bool done = false;
     while (it < max_iters) {
-        // (re)start from the true residual
+        // (re)start from the true residual, the shadow vector r~ = r
         ISC_HIP(isc_launch_spmv(ctx, Jdec, x, tv));
         hipLaunchKernelGGL(bcg_restart, grid, blk, 0, ctx->stream, len, b, tv, r, rs, p, v, B.partial);
         ISC_HIP(B.read(1, h));
@@ -222,16 +239,21 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
         }
         inf.restarts = starts++;
         double rho_old = 1.0, alpha = 1.0, omega = 1.0, rho = h[0];   // (r~, r) = (r, r) at a start
-        bool converged = false;
+        double rn = rn0;                                                 // ||r||
+        bool converged = false, breakdown = false;
         while (it < max_iters) {
-            if (rho == 0.0 || !std::isfinite(rho)) break;
+            // breakdown: r~ (nearly) orthogonal to r, or to v below
+            if (!(std::fabs(rho) > BCG_BREAKDOWN * rn0 * rn) || !std::isfinite(rho)) { breakdown = true; break; }
             const double beta = (rho / rho_old) * (alpha / omega);
             hipLaunchKernelGGL(bcg_p, grid, blk, 0, ctx->stream, len, r, v, beta, omega, p);
             ISC_HIP(isc_launch_bilu0_apply_spmv(ctx, Jdec, ctx->Dinv, p, ph, v));
-            hipLaunchKernelGGL(bcg_dot, grid, blk, 0, ctx->stream, len, rs, v, B.partial);
-            ISC_HIP(B.read(1, h));
+            hipLaunchKernelGGL(bcg_dot2, grid, blk, 0, ctx->stream, len, rs, v, B.partial);
+            ISC_HIP(B.read(2, h));
             const double rv = h[0];
-            if (rv == 0.0 || !std::isfinite(rv)) break;
+            if (!(std::fabs(rv) > BCG_BREAKDOWN * rn0 * std::sqrt(h[1])) || !std::isfinite(rv)) {
+                breakdown = true;
+                break;
+            }
             alpha = rho / rv;
             hipLaunchKernelGGL(bcg_s, grid, blk, 0, ctx->stream, len, r, v, alpha, B.partial);
             ISC_HIP(B.read(1, h));
@@ -247,21 +269,28 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
             hipLaunchKernelGGL(bcg_ts, grid, blk, 0, ctx->stream, len, tv, r, B.partial);
             ISC_HIP(B.read(2, h));
             const double tt = h[1];
-            if (tt == 0.0 || !std::isfinite(tt)) break;
+            if (!(tt > 0.0) || !std::isfinite(tt)) {
+                // s is the residual of x + alpha p^: keep that half step
+                hipLaunchKernelGGL(bcg_x_half, grid, blk, 0, ctx->stream, len, x, ph, alpha);
+                breakdown = true;
+                break;
+            }
             omega = h[0] / tt;
             hipLaunchKernelGGL(bcg_xr, grid, blk, 0, ctx->stream, len, x, ph, sh, alpha, omega, r, tv, rs,
                                B.partial);
             ISC_HIP(B.read(2, h));
-            const double rn = std::sqrt(h[1]);
+            rn = std::sqrt(h[1]);
             inf.relres_est = rn / bnorm;
             if (rn <= tol) {
                 converged = true;
                 break;
             }
-            if (omega == 0.0) break;
+            if (omega == 0.0) { breakdown = true; break; }
             rho_old = rho;
             rho = h[0];
         }
+        // a breakdown restarts from the true residual (a new shadow vector), a bounded number of times
+        if (breakdown && ++breakdowns <= BCG_MAX_BREAKDOWNS) continue;
         if (!converged) break;
     }
     const isc_status sw = isc_check_sweeps(ctx);

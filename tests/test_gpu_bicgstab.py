@@ -78,3 +78,22 @@ def test_bicgstab_reports_no_convergence():
     x, info, st = c.isc_solve_bicgstab(_dev(Jd), _dev(b), max_iters=2, rtol=1e-8, check=False)
     assert st == isc.ISC_ERR_LINEAR_NOCONV and info.iters == 2
     assert info.relres_true > 1e-8 and np.isfinite(info.relres_true)
+
+
+def test_bicgstab_breakdown_restarts_a_bounded_number_of_times():
+    """The oracle pin's breakdown system (b^T A M^-1 b = 0, so (r~, v) = 0 at the
+    first iteration) on the GPU: the same bounded restarts and the same error,
+    x left at zero; a nearby right-hand side converges."""
+    from test_oracle_pins import _synthetic_decoupled, _bicgstab_breakdown_rhs
+    from paper_1811_11992_amd import isc
+    wl, m, Jd = _synthetic_decoupled("tiny:2x2x1", 4, 0.6)
+    b = _bicgstab_breakdown_rhs(m, Jd)
+    c = isc.Context(wl)
+    x, info, st = c.isc_solve_bicgstab(_dev(Jd), _dev(b), max_iters=50, rtol=1e-8, check=False)
+    assert st == isc.ISC_ERR_LINEAR_NOCONV and info.iters == 0 and info.restarts == 8
+    assert np.all(_host(x) == 0.0)
+    b2 = b + 1e-3 * np.random.default_rng(1).standard_normal(b.shape)
+    x, info, st = c.isc_solve_bicgstab(_dev(Jd), _dev(b2), max_iters=200, rtol=1e-10)
+    assert st == 0 and info.relres_true <= 1e-10
+    r = b2 - m.spmv(Jd, _host(x))
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b2)

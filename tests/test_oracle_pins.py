@@ -506,3 +506,47 @@ def test_run_closes_component_balances():
         dmass = (acc1 - acc0) @ Mrow
         assert abs(dmass - dt * W.sum(axis=0) @ Mrow) <= 1e-9 * (inv @ Mrow)
         assert abs((acc1 - acc0)[6] - net[6]) <= 1e-9 * inv[6]
+
+
+def _synthetic_decoupled(name, seed, scale):
+    """A decoupled matrix on a workload's pattern: identity diagonal blocks,
+    random off-diagonal blocks."""
+    wl = I.make_workload(name)
+    m = O.Model(wl)
+    rng = np.random.default_rng(seed)
+    Jd = scale * rng.standard_normal((m.nnzb, 8, 8))
+    for i in range(m.n):
+        for b in range(m.row_ptr[i], m.row_ptr[i + 1]):
+            if m.col_idx[b] == i:
+                Jd[b] = np.eye(8)
+    return wl, m, Jd
+
+
+def _bicgstab_breakdown_rhs(m, Jd):
+    """A right-hand side b with b^T A M^-1 b = 0 (M the block ILU(0) of A), so
+    that the first BiCGSTAB iteration meets (r~, v) = 0: two eigenvectors of
+    the symmetric part of A M^-1 with eigenvalues of opposite sign, mixed."""
+    st, LU, Dinv = m.bilu0(Jd)
+    assert st == 0
+    n8 = m.n * 8
+    K = np.column_stack([m.spmv(Jd, m.bilu0_apply(LU, Dinv, e.reshape(m.n, 8))).ravel() for e in np.eye(n8)])
+    lam, Q = np.linalg.eigh(0.5 * (K + K.T))
+    assert lam[0] < 0 < lam[-1]
+    b = np.sqrt(lam[-1]) * Q[:, 0] + np.sqrt(-lam[0]) * Q[:, -1]
+    assert abs(b @ K @ b) <= 1e-12 * np.linalg.norm(K) * (b @ b)
+    return b.reshape(m.n, 8)
+
+
+def test_bicgstab_breakdown_restarts_a_bounded_number_of_times():
+    """(r~, v) = 0 at the first iteration: each restart from the true residual
+    meets the same breakdown (nothing has changed), so after eight restarts the
+    solve gives up with no convergence, x still zero, no overflow."""
+    wl, m, Jd = _synthetic_decoupled("tiny:2x2x1", 4, 0.6)
+    b = _bicgstab_breakdown_rhs(m, Jd)
+    st, x, info = m.bicgstab(Jd, b, max_iters=50, rtol=1e-8)
+    assert st == -6 and info.iters == 0 and info.restarts == 8
+    assert np.all(x == 0.0) and abs(info.relres_true - 1.0) <= 1e-15
+    # a slightly different right-hand side has no breakdown and converges
+    b2 = b + 1e-3 * np.random.default_rng(1).standard_normal(b.shape)
+    st, x, info = m.bicgstab(Jd, b2, max_iters=200, rtol=1e-10)
+    assert st == 0 and info.relres_true <= 1e-10
