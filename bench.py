@@ -249,7 +249,8 @@ def adjoint_cost(name="C4", nsteps=20, every=5):
     lnA = log_frequency_factors(fl).requires_grad_(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    J = OilProduction.apply(logk, lnA, ctx, u0, wl.dt, nsteps, every)
+    J = OilProduction.apply(logk, lnA, ctx, u0, dt, nsteps, every, 1e-10, progress,
+                            isc.cpr_opts(p_iters=p_iters))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     J.backward()
@@ -296,6 +297,79 @@ def bicgstab_cost(name="C3", reps=2):
         out[label] = {"iters": info.iters, "relres_true": info.relres_true, "ms": round((t1 - t0) * 1e3, 2)}
     ctx.close()
     del ctx
+    gc.collect()
+    return out
+
+
+def scale_leg(name="C5", nsteps=10, every=5, inner=12, dt_days=0.0125, p_iters=12):
+    """The precision and differentiation forms at the largest configured
+    size: `nsteps` implicit steps of `dt_days` of the precision form (FP32
+    BILU(0) and inner SpMV in FP64 FGMRES(30)), then the gradient of
+    cumulative oil production over those steps (checkpoints every `every`
+    steps; the forward steps and the recomputed segments solved in FP64 with
+    the CPR preconditioner, one FP64 adjoint solve per step).  Reports device
+    memory (the context, and the peak of the whole leg), wall time per step
+    of each pass and the Newton and Krylov counts.  Not part of the default
+    run; call it as bench.scale_leg()."""
+    import torch
+    from paper_1811_11992_amd import inputs as I
+    from paper_1811_11992_amd import isc
+    from paper_1811_11992_amd.adjoint import OilProduction, log_frequency_factors
+    wl = I.make_workload(name)
+    fl = I.physics_card()
+    torch.cuda.synchronize()
+    free0, total = torch.cuda.mem_get_info()
+    dt = dt_days * 86400.0
+    ctx = isc.Context(wl, fluid=fl, restart=30, inner_iters=inner, cpr_p_iters=p_iters)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    lin = isc.solve_opts(restart=30, max_restarts=20, rtol=1e-8, precision=isc.ISC_MIXED, inner_iters=inner)
+    sim = isc.Simulator(ctx, tol=1e-10, lin=lin)
+    u = torch.tensor(wl.u0, dtype=torch.float64, device="cuda")
+    steps = []
+    free_min = free1
+
+    def progress(msg):
+        print(f"{name}: {msg}", file=sys.stderr, flush=True)
+
+    progress(f"context holds {(free0 - free1) / 2**30:.1f} GiB")
+    for _ in range(nsteps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rec = sim.step(u, dt)
+        torch.cuda.synchronize()
+        steps.append({"ms": round((time.perf_counter() - t0) * 1e3, 1), "newton": rec["newton"],
+                      "outer": rec["lin"], "inner": rec["inner"], "cuts": rec["cuts"]})
+        free_min = min(free_min, torch.cuda.mem_get_info()[0])
+        progress(f"precision-form step {len(steps)}: {steps[-1]}")
+    # the differentiation form over the same steps (its forward pass runs the
+    # FP64 solver in parity mode, as the gradient needs)
+    logk = torch.tensor(wl.logk, dtype=torch.float64, device="cuda").requires_grad_(True)
+    lnA = log_frequency_factors(fl).requires_grad_(True)
+    u0 = torch.tensor(wl.u0, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = OilProduction.apply(logk, lnA, ctx, u0, dt, nsteps, every, 1e-10, progress,
+                            isc.cpr_opts(p_iters=p_iters))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    free_min = min(free_min, torch.cuda.mem_get_info()[0])
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    free_min = min(free_min, torch.cuda.mem_get_info()[0])
+    ok = bool(torch.isfinite(logk.grad).all()) and bool(torch.isfinite(lnA.grad).all())
+    out = {"workload": f"{name}: {wl.nx}x{wl.ny}x{wl.nz} ({wl.ncell} cells), {nsteps} steps of {dt_days} day",
+           "device_memory_GiB": {"context": round((free0 - free1) / 2**30, 2),
+                                 "peak_in_use": round((free0 - free_min) / 2**30, 2),
+                                 "device_total": round(total / 2**30, 1)},
+           "precision_form_steps": steps,
+           "precision_form_ms_per_step": round(sum(x["ms"] for x in steps) / nsteps, 1),
+           "adjoint": {"forward_ms_per_step": round((t1 - t0) / nsteps * 1e3, 1),
+                       "backward_ms_per_step": round((t2 - t1) / nsteps * 1e3, 1),
+                       "checkpoints_every": every, "gradient_finite": ok}}
+    ctx.close()
+    del ctx, J
     gc.collect()
     return out
 
