@@ -103,6 +103,17 @@ def lib():
         L.orc_cpr_apply.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.orc_fgmres_cpr.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(SolveInfo)]
+        L.orc_ncwell.restype = ctypes.c_int32
+        L.orc_ncwell.argtypes = [ctypes.c_void_p]
+        L.orc_well_state.argtypes = [ctypes.c_void_p, _dp, _ip]
+        L.orc_set_well_state.argtypes = [ctypes.c_void_p, _dp, _ip]
+        L.orc_well_controls.restype = ctypes.c_int32
+        L.orc_well_controls.argtypes = [ctypes.c_void_p, _dp]
+        L.orc_well_solve.restype = ctypes.c_int32
+        L.orc_well_solve.argtypes = [ctypes.c_void_p, _dp]
+        L.orc_well_border.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
+        L.orc_well_scaled_norm.restype = ctypes.c_double
+        L.orc_well_scaled_norm.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double]
         if hasattr(L, "orc_adjoint_step"):
             L.orc_oil_rate.restype = ctypes.c_double
             L.orc_oil_rate.argtypes = [ctypes.c_void_p, _dp]
@@ -167,6 +178,44 @@ class Model:
         q = np.zeros(npf)
         lib().orc_perf_info(self.h, _ip_(cells), _ip_(kinds), _p(wi), _p(q))
         return cells, kinds, wi, q
+
+    # ---- controlled wells (kinds 3, 4)
+    @property
+    def ncwell(self):
+        return lib().orc_ncwell(self.h)
+
+    @property
+    def ncperf(self):
+        return sum(len(w["cells"]) for w in self.wl.wells if w["kind"] in (I.WELL_PRODUCER, I.WELL_INJECTOR))
+
+    def well_state(self):
+        bhp = np.zeros(max(1, self.ncwell))
+        on = np.zeros(max(1, self.ncwell), np.int32)
+        lib().orc_well_state(self.h, _p(bhp), _ip_(on))
+        return bhp[:self.ncwell].copy(), on[:self.ncwell].copy()
+
+    def set_well_state(self, bhp, on_limit):
+        b = np.ascontiguousarray(np.resize(np.asarray(bhp, np.float64), max(1, self.ncwell)))
+        o = np.ascontiguousarray(np.resize(np.asarray(on_limit, np.int32), max(1, self.ncwell)))
+        lib().orc_set_well_state(self.h, _p(b), _ip_(o))
+
+    def well_controls(self, u):
+        return lib().orc_well_controls(self.h, _p(np.ascontiguousarray(u, np.float64)))
+
+    def well_solve(self, u):
+        return lib().orc_well_solve(self.h, _p(np.ascontiguousarray(u, np.float64)))
+
+    def well_border(self, u):
+        """(R[ncw], D[ncw], B[ncp][8], C[ncp][8]) at state u and the current well state."""
+        nw, npf = max(1, self.ncwell), max(1, self.ncperf)
+        R, D = np.zeros(nw), np.zeros(nw)
+        B, C = np.zeros((npf, 8)), np.zeros((npf, 8))
+        lib().orc_well_border(self.h, _p(np.ascontiguousarray(u, np.float64)), _p(R), _p(D), _p(B), _p(C))
+        return R[:self.ncwell], D[:self.ncwell], B[:self.ncperf], C[:self.ncperf]
+
+    def well_scaled_norm(self, R, dt):
+        r = np.ascontiguousarray(np.resize(np.asarray(R, np.float64), max(1, self.ncwell)))
+        return lib().orc_well_scaled_norm(self.h, _p(r), float(dt))
 
     # ---- diagnostics
     def diag(self, u):

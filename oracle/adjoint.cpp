@@ -49,6 +49,7 @@ double orc_oil_rate(orc_model* m, const double* u) {
 
 int orc_adjoint_step(orc_model* m, const double* u_n, const double* u_nm1, double dt_n, const double* lam_np1,
                      const double* /*u_np1_unused*/, double dt_np1, double* lam_n, double* g_logk, double* g_A) {
+    if (!m->cw.empty()) return -2;   /* the well rows of bhp unknowns are not in this adjoint */
     const int32_t n = m->n;
     const size_t N8 = (size_t)n * 8;
     const double V = cell_volume(*m);

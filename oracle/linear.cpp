@@ -209,11 +209,40 @@ void orc_bilu0_apply(orc_model* m, const double* LU, const double* Dinv, const d
     }
 }
 
+}  // extern "C"
+
+namespace {
+
+/* The well rows eliminated from a decoupled system: the operator becomes
+ * x -> A x - sum_w Bt_w (C_w . x) / D_w, with Bt = the decoupled B (rows
+ * scaled by the inverse diagonal blocks like the rest of the block row). */
+struct Border {
+    const double *Bt, *C, *D;   /* [ncp][8], [ncp][8], [ncw] */
+};
+
+void apply_op(orc_model* m, const double* A, const Border* bd, const double* x, double* y) {
+    orc_spmv(m, A, x, y);
+    if (!bd) return;
+    for (const orc_cwell& W : m->cw) {
+        double s = 0.0;
+        for (int32_t k = 0; k < W.np; ++k) {
+            const int32_t i = m->perfs[W.p0 + k].cell;
+            for (int v = 0; v < 8; ++v) s += bd->C[(size_t)(W.c0 + k) * 8 + v] * x[(size_t)i * 8 + v];
+        }
+        s /= bd->D[&W - m->cw.data()];
+        for (int32_t k = 0; k < W.np; ++k) {
+            const int32_t i = m->perfs[W.p0 + k].cell;
+            for (int e = 0; e < 8; ++e) y[(size_t)i * 8 + e] -= bd->Bt[(size_t)(W.c0 + k) * 8 + e] * s;
+        }
+    }
+}
+
 /* Right-preconditioned restarted GMRES(m) with modified Gram-Schmidt and
- * Givens rotations, x0 = 0, stop when ||b - A x|| <= rtol ||b||; the true
- * residual is recomputed at every restart and at exit. */
-int orc_gmres(orc_model* m, const double* A, const double* b, double* x, int32_t restart,
-              int32_t max_restarts, double rtol, orc_solve_info* info) {
+ * Givens rotations, x0 = 0, stop when ||b - Op x|| <= rtol ||b||; the true
+ * residual is recomputed at every restart and at exit.  Op = A, or A with
+ * the well rows eliminated; the preconditioner is block ILU(0) of A. */
+int gmres_impl(orc_model* m, const double* A, const Border* bd, const double* b, double* x, int32_t restart,
+               int32_t max_restarts, double rtol, orc_solve_info* info) {
     const size_t N = (size_t)m->n * 8;
     std::vector<double> LU((size_t)m->row_ptr[m->n] * 64), Dinv((size_t)m->n * 64);
     int st = orc_bilu0(m, A, LU.data(), Dinv.data());
@@ -231,7 +260,7 @@ int orc_gmres(orc_model* m, const double* A, const double* b, double* x, int32_t
     std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1);
     int status = -6;
     for (int cyc = 0; cyc < max_restarts; ++cyc) {
-        orc_spmv(m, A, x, tmp.data());
+        apply_op(m, A, bd, x, tmp.data());
         for (size_t k = 0; k < N; ++k) r[k] = bb[k] - tmp[k];
         double beta = nrm2(r);
         inf.relres_true = beta / bnorm;
@@ -243,7 +272,7 @@ int orc_gmres(orc_model* m, const double* A, const double* b, double* x, int32_t
         int jdone = 0;
         for (int j = 0; j < restart; ++j) {
             orc_bilu0_apply(m, LU.data(), Dinv.data(), V[j].data(), z.data());
-            orc_spmv(m, A, z.data(), w.data());
+            apply_op(m, A, bd, z.data(), w.data());
             for (int i = 0; i <= j; ++i) {
                 double h = dot(w, V[i]);
                 H[(size_t)i * restart + j] = h;
@@ -285,7 +314,7 @@ int orc_gmres(orc_model* m, const double* A, const double* b, double* x, int32_t
         for (size_t k = 0; k < N; ++k) x[k] += z[k];
     }
     if (status != 0) {
-        orc_spmv(m, A, x, tmp.data());
+        apply_op(m, A, bd, x, tmp.data());
         double s = 0.0;
         for (size_t k = 0; k < N; ++k) s += (bb[k] - tmp[k]) * (bb[k] - tmp[k]);
         inf.relres_true = std::sqrt(s) / bnorm;
@@ -293,6 +322,18 @@ int orc_gmres(orc_model* m, const double* A, const double* b, double* x, int32_t
     }
     if (info) *info = inf;
     return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+/* Right-preconditioned restarted GMRES(m) with modified Gram-Schmidt and
+ * Givens rotations, x0 = 0, stop when ||b - A x|| <= rtol ||b||; the true
+ * residual is recomputed at every restart and at exit. */
+int orc_gmres(orc_model* m, const double* A, const double* b, double* x, int32_t restart,
+              int32_t max_restarts, double rtol, orc_solve_info* info) {
+    return gmres_impl(m, A, nullptr, b, x, restart, max_restarts, rtol, info);
 }
 
 /* Right-preconditioned BiCGSTAB (van der Vorst's stabilised bi-conjugate
@@ -459,25 +500,73 @@ int orc_update(orc_model* m, double* u, const double* du) {
     return 0;
 }
 
+/* One Newton iteration.  With controlled wells the system is bordered by
+ * their rows (bhp unknowns, well-modelling subsection).  First each
+ * rate-controlled well's equation is solved on its own for bhp at the
+ * current cells (orc_well_solve); then the bordered system is assembled and
+ * its well rows eliminated:
+ *   (J - B D^-1 C) du = -(F - B D^-1 R),  dbhp = -D^-1 (R + C du),
+ * after decoupling J~ = C_L J, Bt = C_L B, F~ = C_L F; the reduced operator is
+ * applied as J~ x - Bt D^-1 (C x) and preconditioned with block ILU(0) of J~.
+ * bhp takes its whole Newton step. */
 int orc_newton_step(orc_model* m, double* u, const double* u_old, double dt, double tol,
                     int32_t restart, int32_t max_restarts, double rtol, orc_newton_info* info) {
     const size_t N = (size_t)m->n * 8;
     std::vector<double> F(N), J((size_t)m->row_ptr[m->n] * 64), du(N), rhs(N);
     orc_newton_info inf;
     std::memset(&inf, 0, sizeof(inf));
+    const size_t ncw = m->cw.size();
+    const size_t ncp = ncw ? (size_t)(m->cw.back().c0 + m->cw.back().np) : 0;
+    std::vector<double> R(ncw), D(ncw), B(ncp * 8), C(ncp * 8), Bt(ncp * 8);
+    if (ncw) orc_well_solve(m, u);
     orc_assemble(m, u, u_old, dt, F.data(), J.data());
     inf.res_scaled = orc_scaled_norm(m, F.data(), dt);
+    if (ncw) {
+        orc_well_border(m, u, R.data(), D.data(), B.data(), C.data());
+        const double rw = orc_well_scaled_norm(m, R.data(), dt);
+        if (!(rw <= inf.res_scaled)) inf.res_scaled = rw;
+    }
     if (!std::isfinite(inf.res_scaled)) { inf.status = -5; if (info) *info = inf; return -5; }
     if (inf.res_scaled <= tol) { inf.converged = 1; if (info) *info = inf; return 0; }
+    /* Bt = J_ii^-1 B at the perforated cells, before J is decoupled */
+    for (const orc_cwell& W : m->cw)
+        for (int32_t k = 0; k < W.np; ++k) {
+            const int32_t i = m->perfs[W.p0 + k].cell;
+            double inv[64];
+            if (!inv8(J.data() + (size_t)m->diag_pos[i] * 64, inv)) {
+                inf.status = -4;
+                if (info) *info = inf;
+                return -4;
+            }
+            matvec8(inv, B.data() + (size_t)(W.c0 + k) * 8, Bt.data() + (size_t)(W.c0 + k) * 8);
+        }
     int32_t bad;
     int st = orc_decouple(m, J.data(), F.data(), &bad);
     if (st) { inf.status = st; if (info) *info = inf; return st; }
     for (size_t k = 0; k < N; ++k) rhs[k] = -F[k];
+    for (size_t w = 0; w < ncw; ++w) {
+        const orc_cwell& W = m->cw[w];
+        for (int32_t k = 0; k < W.np; ++k) {
+            const int32_t i = m->perfs[W.p0 + k].cell;
+            for (int e = 0; e < 8; ++e) rhs[(size_t)i * 8 + e] += Bt[(size_t)(W.c0 + k) * 8 + e] * R[w] / D[w];
+        }
+    }
+    Border bd{Bt.data(), C.data(), D.data()};
     orc_solve_info si;
-    st = orc_gmres(m, J.data(), rhs.data(), du.data(), restart, max_restarts, rtol, &si);
+    st = gmres_impl(m, J.data(), ncw ? &bd : nullptr, rhs.data(), du.data(), restart, max_restarts, rtol, &si);
     inf.iters_lin = si.iters;
     inf.relres_true = si.relres_true;
     if (st) { inf.status = st; if (info) *info = inf; return st; }
+    for (size_t w = 0; w < ncw; ++w) {
+        orc_cwell& W = m->cw[w];
+        double s = R[w];
+        for (int32_t k = 0; k < W.np; ++k) {
+            const int32_t i = m->perfs[W.p0 + k].cell;
+            for (int v = 0; v < 8; ++v) s += C[(size_t)(W.c0 + k) * 8 + v] * du[(size_t)i * 8 + v];
+        }
+        W.bhp -= s / D[w];
+        if (!std::isfinite(W.bhp)) { inf.status = -5; if (info) *info = inf; return -5; }
+    }
     st = orc_update(m, u, du.data());
     inf.status = st;
     if (info) *info = inf;
@@ -493,6 +582,7 @@ int orc_run(orc_model* m, double* u, double dt, int32_t nsteps, double tol, int3
     if (u_hist) std::memcpy(u_hist, u, sizeof(double) * N);
     for (int32_t s = 0; s < nsteps; ++s) {
         std::memcpy(u_old.data(), u, sizeof(double) * N);
+        const std::vector<orc_cwell> cw_old = m->cw;
         double dts = dt;
         int cuts = 0;
         bool ok = false;
@@ -500,6 +590,7 @@ int orc_run(orc_model* m, double* u, double dt, int32_t nsteps, double tol, int3
         std::memset(&si, 0, sizeof(si));
         while (!ok && cuts <= 4) {
             int nit = 0, lin = 0;
+            orc_well_controls(m, u);
             orc_newton_info ni;
             for (; nit < max_newton + 1; ++nit) {
                 int st = orc_newton_step(m, u, u_old.data(), dts, tol, restart, max_restarts, rtol, &ni);
@@ -512,6 +603,7 @@ int orc_run(orc_model* m, double* u, double dt, int32_t nsteps, double tol, int3
             si.res_final = ni.res_scaled;
             if (!ok) {
                 std::memcpy(u, u_old.data(), sizeof(double) * N);
+                m->cw = cw_old;
                 dts *= 0.5;
                 ++cuts;
             }

@@ -6,12 +6,24 @@
 
 struct orc_perf {
     int32_t cell;
-    int32_t kind;     /* 1 producer, 2 injector */
+    int32_t kind;     /* 1 producer, 2 injector, 3 controlled producer, 4 controlled injector */
+    int32_t well;     /* kinds 3/4: index into orc_model::cw, else -1 */
     double wi;        /* Peaceman well index, m^3 */
     double bhp;       /* producer */
     double q[ORC_NSPEC];  /* injector molar rates per species, mol/s */
     double qE;        /* injector energy rate, W */
     double q_total;   /* injector total molar rate (for sensitivity) */
+};
+
+/* a well whose bottom-hole pressure is an unknown (kinds 3, 4) */
+struct orc_cwell {
+    int32_t kind, control;
+    double target, limit;
+    double z[ORC_NSPEC], Hinj;   /* injector: composition and molar enthalpy at T_inj */
+    int32_t p0 = 0, np = 0;      /* its perforations: perfs[p0 .. p0 + np) */
+    int32_t c0 = 0;              /* their first index among the controlled wells' perforations */
+    double bhp = 0.0;            /* state: bottom-hole pressure, Pa */
+    int32_t on_limit = 0;        /* state: rate control suspended at the BHP limit */
 };
 
 struct orc_model {
@@ -24,6 +36,7 @@ struct orc_model {
     std::vector<orc_perf> perfs;
     std::vector<orc_well> wells_in;        /* shallow copies for WI recompute */
     std::vector<std::vector<int32_t>> well_cells;
+    std::vector<orc_cwell> cw;            /* controlled wells, in input order */
     int32_t heater_cell = -1;     /* a heat source in one cell's energy balance (W), or none */
     double heater_W = 0.0;
 };

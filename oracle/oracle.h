@@ -44,14 +44,25 @@ typedef struct {
 
 typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } orc_grid;
 
+/* Kinds 1 and 2 are local sources (fixed BHP producer, fixed-rate injector
+ * split over the perforations by WI).  Kinds 3 and 4 make the bottom-hole
+ * pressure an unknown with a well equation of its own (well-modelling
+ * subsection): control 0 holds bhp = target; otherwise the well holds a
+ * molar rate, target mol/s -- for a producer the sum over perforations of the
+ * phases in the mask control (1 water, 2 oil, 4 gas; 7 = total), for an
+ * injector the injected total -- and falls back to its BHP limit `limit`
+ * (producer minimum, injector maximum) when the rate would need a bhp
+ * beyond it. */
 typedef struct {
-    int32_t kind;            /* 1 BHP producer, 2 rate injector */
+    int32_t kind;            /* 1 BHP producer, 2 rate injector, 3 controlled producer, 4 controlled injector */
     int32_t nperf;
     const int32_t* perf_cells;
-    double target;           /* producer: BHP (Pa); injector: total mol/s */
+    double target;           /* kind 1, kinds 3/4 at control 0: BHP (Pa); otherwise mol/s */
     double T_inj;
     double z_inj[ORC_NSPEC];
     double rw, skin;
+    int32_t control;         /* kinds 3/4: 0 BHP control, else rate control (producer: phase mask) */
+    double limit;            /* kinds 3/4 under rate control: BHP limit (Pa) */
 } orc_well;
 
 typedef struct {
@@ -95,6 +106,36 @@ double orc_zfactor(const orc_fluid* fl, double p, double T, const double* y, dou
 /* gas-phase viscosity of composition y[6] at T (Pa s) */
 double orc_gas_viscosity(const orc_fluid* fl, double T, const double* y);
 
+/* Wells of kinds 3 and 4 ("controlled wells", in the order given): their
+ * state is bhp (Pa) and on_limit (1 while a rate-controlled well is held at
+ * its BHP limit).  At creation bhp = target under BHP control, else the limit,
+ * and on_limit = 0. */
+int32_t orc_ncwell(const orc_model* m);
+void orc_well_state(const orc_model* m, double* bhp, int32_t* on_limit);
+void orc_set_well_state(orc_model* m, const double* bhp, const int32_t* on_limit);
+/* Control switching and the well equations alone.  orc_well_solve, before
+ * every Newton iteration assembles: with the cells at state u, a
+ * rate-controlled well's rate is piecewise linear and monotone in bhp; if it
+ * falls short of the target at the BHP limit the well is held at the limit
+ * for the rest of the time step, else bhp is set to the root of its rate
+ * equation.  orc_well_controls, at the start of a time step: a well held at
+ * its limit returns to its rate when, at state u, it would move more than
+ * the target there.  (Switching back only between steps keeps a Newton
+ * iteration from cycling between the two controls.)  Both return the number
+ * of wells switched. */
+int32_t orc_well_controls(orc_model* m, const double* u);
+int32_t orc_well_solve(orc_model* m, const double* u);
+/* The well rows at state u and the current well state (as orc_well_controls
+ * left it).  Per controlled well w: R[w] its equation's residual and D[w] =
+ * dR_w/dbhp_w; per perforation k of the controlled wells (in well order):
+ * B[k][8] = dF_cell/dbhp and C[k][8] = dR_w/du_cell.  Newton's system is
+ *   [J  B] [du  ]     [F]
+ *   [C  D] [dbhp] = - [R]. */
+void orc_well_border(orc_model* m, const double* u, double* R, double* D, double* B, double* C);
+/* |R_w| scaled like the cell rows: rate rows by V phi rho_ref,W / dt of the
+ * well's first perforated cell, BHP rows by the pressure held (at least 1 Pa) */
+double orc_well_scaled_norm(orc_model* m, const double* R, double dt);
+
 /* hot-path steps */
 int orc_residual(orc_model* m, const double* u, const double* u_old, double dt, double* F);
 int orc_assemble(orc_model* m, const double* u, const double* u_old, double dt,
@@ -121,11 +162,18 @@ typedef struct {
     int32_t converged, iters_lin, status;
     double res_scaled, relres_true;
 } orc_newton_info;
+/* One Newton iteration (assemble, converged if res <= tol, else decouple,
+ * GMRES, update).  With controlled wells: orc_well_solve first, the well
+ * rows count in res (orc_well_scaled_norm), and they are eliminated from the
+ * bordered system (Schur complement) before GMRES; bhp takes its Newton
+ * step with the cells. */
 int orc_newton_step(orc_model* m, double* u, const double* u_old, double dt, double tol,
                     int32_t restart, int32_t max_restarts, double rtol, orc_newton_info* info);
 
 /* time loop: u [8][N] in/out; per step records NI and linear iterations;
- * returns number of successful steps or a negative status */
+ * every attempt at a step starts with orc_well_controls; a failed step
+ * restores u and the well state and halves dt (at most four times); returns
+ * number of successful steps or a negative status */
 typedef struct {
     int32_t newton_its, lin_its, cuts;
     double dt_used, res_final;
@@ -153,7 +201,8 @@ void orc_cpr_apply(const orc_cpr* c, const double* r, double* z);
 int orc_fgmres_cpr(orc_model* m, const double* Jdec, const double* b, double* x, int32_t restart,
                    int32_t max_restarts, double rtol, int32_t p_iters, int32_t nu, double cf, orc_solve_info* info);
 
-/* discrete adjoint (see oracle/adjoint.cpp) */
+/* discrete adjoint (see oracle/adjoint.cpp); orc_adjoint_step returns -2 for
+ * a model with controlled wells (their rows are not in this adjoint) */
 double orc_oil_rate(orc_model* m, const double* u);
 int orc_adjoint_step(orc_model* m, const double* u_n, const double* u_nm1, double dt_n,
                      const double* lam_np1, const double* u_np1_unused, double dt_np1,

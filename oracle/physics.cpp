@@ -269,12 +269,15 @@ int32_t block_of(const orc_model& m, int32_t i, int32_t j) {
 }
 
 /* Peaceman inflow (well-modelling subsection): WI = 2 pi h sqrt(kx ky) /
- * (ln(re/rw) + s), re = 0.14 sqrt(dx^2 + dy^2).  Producers: fixed BHP, local
- * inflow, no backflow.  Injectors: fixed molar rate split over perforations in
- * proportion to WI, injected as gas at T_inj. */
+ * (ln(re/rw) + s), re = 0.14 sqrt(dx^2 + dy^2).  Producers (kind 1): fixed
+ * BHP, local inflow, no backflow.  Injectors (kind 2): fixed molar rate split
+ * over perforations in proportion to WI, injected as gas at T_inj.  Kinds 3
+ * and 4 take their bhp from the well state (orc_cwell); their perforations
+ * keep only WI here. */
 void compute_wells(orc_model& m) {
     m.perfs.clear();
     double re = 0.14 * std::sqrt(m.g.dx * m.g.dx + m.g.dy * m.g.dy);
+    size_t ncw = 0;
     for (size_t w = 0; w < m.wells_in.size(); ++w) {
         const orc_well& W = m.wells_in[w];
         const std::vector<int32_t>& cells = m.well_cells[w];
@@ -287,13 +290,25 @@ void compute_wells(orc_model& m) {
         }
         double Hinj = 0.0;
         for (int c = 0; c < 6; ++c) Hinj += W.z_inj[c] * gas_enthalpy(m.fl, c, W.T_inj);
+        const bool controlled = W.kind == 3 || W.kind == 4;
+        if (controlled) {
+            orc_cwell& C = m.cw[ncw];
+            C.p0 = (int32_t)m.perfs.size();
+            C.np = (int32_t)cells.size();
+            C.c0 = ncw == 0 ? 0 : m.cw[ncw - 1].c0 + m.cw[ncw - 1].np;
+            for (int c = 0; c < ORC_NSPEC; ++c) C.z[c] = W.z_inj[c];
+            C.Hinj = Hinj;
+        }
         for (size_t k = 0; k < cells.size(); ++k) {
             orc_perf P;
             std::memset(&P, 0, sizeof(P));
             P.cell = cells[k];
             P.kind = W.kind;
+            P.well = controlled ? (int32_t)ncw : -1;
             P.wi = wi[k];
-            if (W.kind == 1) {
+            if (controlled) {
+                /* bhp from the well state */
+            } else if (W.kind == 1) {
                 P.bhp = W.target;
             } else {
                 double q = W.target * wi[k] / sum;
@@ -303,7 +318,56 @@ void compute_wells(orc_model& m) {
             }
             m.perfs.push_back(P);
         }
+        if (controlled) ++ncw;
     }
+}
+
+/* Flow of one perforation of a controlled well at its cell's properties P,
+ * cell pressure p and the well's bhp (well-modelling subsection): phase molar
+ * rates Q_a = WI lambda_a (bhp - p), lambda_a = rho_a k_ra / mu_a, at a
+ * producer while p > bhp; at an injector the injected gas enters with the
+ * cell's total mobility, Q = WI (lambda_w + lambda_o + lambda_g) (bhp - p),
+ * while bhp > p; no backflow either way.  Q < 0 is production.  dQ holds
+ * dQ/dbhp. */
+template <class S> struct PerfFlow {
+    bool active = false;
+    S Q[3];         /* producer phase rates */
+    double dQ[3] = {0.0, 0.0, 0.0};
+    S Qi;           /* injector total rate */
+    double dQi = 0.0;
+};
+template <class S>
+PerfFlow<S> perf_flow(const orc_perf& W, const orc_cwell& C, const Props<S>& P, const S& p) {
+    PerfFlow<S> f;
+    for (int a = 0; a < 3; ++a) f.Q[a] = S(0.0);
+    f.Qi = S(0.0);
+    if (W.kind == 3) {
+        if (!(val(p) > C.bhp)) return f;
+        f.active = true;
+        for (int a = 0; a < 3; ++a) {
+            f.Q[a] = W.wi * P.mob[a] * (C.bhp - p);
+            f.dQ[a] = W.wi * val(P.mob[a]);
+        }
+    } else {
+        if (!(C.bhp > val(p))) return f;
+        f.active = true;
+        S lt = P.mob[0] + P.mob[1] + P.mob[2];
+        f.Qi = W.wi * lt * (C.bhp - p);
+        f.dQi = W.wi * val(lt);
+    }
+    return f;
+}
+
+/* the amount that a controlled well's perforation takes out of row e */
+template <class S> S perf_row(const orc_perf& W, const orc_cwell& C, const Props<S>& P, const PerfFlow<S>& f, int e) {
+    S t(0.0);
+    if (!f.active || e > 6) return t;
+    if (W.kind == 3) {
+        for (int a = 0; a < 3; ++a) t = t + f.Q[a] * P.xi[a][e];
+    } else {
+        t = f.Qi * (e == 6 ? C.Hinj : C.z[e]);
+    }
+    return t;
 }
 
 /* ------------------------------------------------------------- assembly */
@@ -415,9 +479,17 @@ static int assemble_impl(orc_model& m, const double* u, const double* u_old, dou
                     if (J) add_diag(J, m.diag_pos[i], -1.0, t, e);
                 }
             }
-        } else {
+        } else if (W.kind == 2) {
             for (int c = 0; c < 6; ++c) F[(size_t)i * 8 + c] -= W.q[c];
             F[(size_t)i * 8 + 6] -= W.qE;
+        } else {
+            const orc_cwell& C = m.cw[W.well];
+            PerfFlow<S8> fl = perf_flow(W, C, P[i], pp[i]);
+            for (int e = 0; e < 7; ++e) {
+                S8 t = perf_row(W, C, P[i], fl, e);
+                F[(size_t)i * 8 + e] -= val(t);
+                if (J) add_diag(J, m.diag_pos[i], -1.0, t, e);
+            }
         }
     }
     /* heater: a fixed heat rate into one cell (the ignition heater of the
@@ -560,6 +632,15 @@ orc_model* orc_create(const orc_grid* g, const orc_fluid* fl, const double* logk
     for (int32_t w = 0; w < nwells; ++w) {
         m->wells_in.push_back(wells[w]);
         m->well_cells.emplace_back(wells[w].perf_cells, wells[w].perf_cells + wells[w].nperf);
+        if (wells[w].kind == 3 || wells[w].kind == 4) {
+            orc_cwell C;
+            C.kind = wells[w].kind;
+            C.control = wells[w].control;
+            C.target = wells[w].target;
+            C.limit = wells[w].limit;
+            C.bhp = C.control == 0 ? C.target : C.limit;
+            m->cw.push_back(C);
+        }
     }
     compute_wells(*m);
     return m;
@@ -680,13 +761,211 @@ void orc_sources(orc_model* m, const double* u, double* wells_out, double* reac_
                     double Q = W.wi * P[i].mob[a] * (W.bhp - p);
                     for (int e = 0; e < 7; ++e) wells_out[(size_t)i * 8 + e] += Q * P[i].xi[a][e];
                 }
-            } else {
+            } else if (W.kind == 2) {
                 for (int c = 0; c < 6; ++c) wells_out[(size_t)i * 8 + c] += W.q[c];
                 wells_out[(size_t)i * 8 + 6] += W.qE;
+            } else {
+                const orc_cwell& C = m->cw[W.well];
+                PerfFlow<double> fl = perf_flow(W, C, P[i], p);
+                for (int e = 0; e < 7; ++e) wells_out[(size_t)i * 8 + e] += perf_row(W, C, P[i], fl, e);
             }
         }
         if (m->heater_cell >= 0) wells_out[(size_t)m->heater_cell * 8 + 6] += m->heater_W;
     }
+}
+
+int32_t orc_ncwell(const orc_model* m) { return (int32_t)m->cw.size(); }
+
+void orc_well_state(const orc_model* m, double* bhp, int32_t* on_limit) {
+    for (size_t w = 0; w < m->cw.size(); ++w) {
+        if (bhp) bhp[w] = m->cw[w].bhp;
+        if (on_limit) on_limit[w] = m->cw[w].on_limit;
+    }
+}
+
+void orc_set_well_state(orc_model* m, const double* bhp, const int32_t* on_limit) {
+    for (size_t w = 0; w < m->cw.size(); ++w) {
+        if (bhp) m->cw[w].bhp = bhp[w];
+        if (on_limit) m->cw[w].on_limit = on_limit[w] ? 1 : 0;
+    }
+}
+
+/* the controlled quantity of well C at state u and its current bhp: the
+ * produced molar rate of the phases in the mask (producer) or the injected
+ * molar rate (injector), with its gradient per perforation (C[k][8], may be
+ * NULL) and its derivative in bhp */
+static double controlled_rate(const orc_model& m, const orc_cwell& C, const double* u, double* Cg, double* dq) {
+    double q = 0.0, d = 0.0;
+    for (int32_t k = 0; k < C.np; ++k) {
+        const orc_perf& W = m.perfs[C.p0 + k];
+        D8 ui[8];
+        load_cell(u, m.n, W.cell, ui);
+        Props<D8> P;
+        props(m.fl, m.poro[W.cell], ui, P);
+        PerfFlow<D8> fl = perf_flow(W, C, P, ui[0]);
+        D8 qk(0.0);
+        double dk = 0.0;
+        if (C.kind == 3) {
+            for (int a = 0; a < 3; ++a)
+                if (C.control & (1 << a)) {
+                    qk = qk - fl.Q[a];
+                    dk -= fl.dQ[a];
+                }
+        } else {
+            qk = fl.Qi;
+            dk = fl.dQi;
+        }
+        q += qk.v;
+        d += dk;
+        if (Cg)
+            for (int v = 0; v < 8; ++v) Cg[(size_t)k * 8 + v] = qk.d[v];
+    }
+    if (dq) *dq = d;
+    return q;
+}
+
+}  // extern "C"
+
+/* The well equation of a rate-controlled well on its own.  With the cells'
+ * state fixed, the controlled rate is g(b) = sum_k a_k (p_k - b)^+ for a
+ * producer (a_k = WI times the mobilities of the phases in its mask) and
+ * sum_k a_k (b - p_k)^+ for an injector (a_k = WI lambda_t): piecewise linear
+ * and monotone in the bottom-hole pressure b, with breakpoints at the
+ * perforated cells' pressures p_k. */
+struct WellLine {
+    std::vector<double> a, p;
+    bool injector;
+    double g(double b) const {
+        double s = 0.0;
+        for (size_t k = 0; k < a.size(); ++k) {
+            const double d = injector ? b - p[k] : p[k] - b;
+            if (d > 0.0) s += a[k] * d;
+        }
+        return s;
+    }
+};
+
+static WellLine well_line(const orc_model& m, const orc_cwell& C, const double* u) {
+    WellLine L;
+    L.injector = C.kind == 4;
+    for (int32_t k = 0; k < C.np; ++k) {
+        const orc_perf& W = m.perfs[C.p0 + k];
+        double ui[8];
+        for (int v = 0; v < 8; ++v) ui[v] = u[(size_t)v * m.n + W.cell];
+        Props<double> P;
+        props(m.fl, m.poro[W.cell], ui, P);
+        double lam = 0.0;
+        for (int a = 0; a < 3; ++a)
+            if (L.injector || (C.control & (1 << a))) lam += P.mob[a];
+        L.a.push_back(W.wi * lam);
+        L.p.push_back(ui[0]);
+    }
+    return L;
+}
+
+/* the b with g(b) = c, given g(lim) >= c: walk the breakpoints away from the
+ * limit to the first segment whose far end has g <= c, and solve the linear
+ * piece there (its active perforations are those beyond that end) */
+static double well_line_root(const WellLine& L, double lim, double c) {
+    const double s = L.injector ? -1.0 : 1.0;   /* an injector in a producer's form: b -> -b */
+    std::vector<double> bp{s * lim};
+    for (double x : L.p)
+        if (s * x > s * lim) bp.push_back(s * x);
+    std::sort(bp.begin(), bp.end());
+    for (size_t i = 0; i + 1 < bp.size(); ++i) {
+        if (L.g(s * bp[i + 1]) > c) continue;
+        double sa = 0.0, sap = 0.0;
+        for (size_t k = 0; k < L.a.size(); ++k)
+            if (s * L.p[k] >= bp[i + 1]) {
+                sa += L.a[k];
+                sap += L.a[k] * s * L.p[k];
+            }
+        double b = sa > 0.0 ? (sap - c) / sa : bp[i];
+        b = std::min(std::max(b, bp[i]), bp[i + 1]);
+        return s * b;
+    }
+    return lim;   /* no perforation beyond the limit: g(lim) = 0 = c */
+}
+
+extern "C" {
+
+int32_t orc_well_solve(orc_model* m, const double* u) {
+    int32_t nsw = 0;
+    for (orc_cwell& C : m->cw) {
+        if (C.control == 0 || C.on_limit) continue;
+        WellLine L = well_line(*m, C, u);
+        if (L.g(C.limit) < C.target) {
+            C.on_limit = 1;
+            C.bhp = C.limit;
+            ++nsw;
+        } else {
+            C.bhp = well_line_root(L, C.limit, C.target);
+        }
+    }
+    return nsw;
+}
+
+int32_t orc_well_controls(orc_model* m, const double* u) {
+    int32_t nsw = 0;
+    for (orc_cwell& C : m->cw) {
+        if (C.control == 0 || !C.on_limit) continue;
+        if (well_line(*m, C, u).g(C.limit) > C.target) {
+            C.on_limit = 0;
+            ++nsw;
+        }
+    }
+    return nsw;
+}
+
+void orc_well_border(orc_model* m, const double* u, double* R, double* D, double* B, double* Cg) {
+    for (size_t w = 0; w < m->cw.size(); ++w) {
+        const orc_cwell& C = m->cw[w];
+        /* B: how the cell rows move with bhp */
+        for (int32_t k = 0; k < C.np; ++k) {
+            const orc_perf& W = m->perfs[C.p0 + k];
+            double ui[8];
+            for (int v = 0; v < 8; ++v) ui[v] = u[(size_t)v * m->n + W.cell];
+            Props<double> P;
+            props(m->fl, m->poro[W.cell], ui, P);
+            PerfFlow<double> fl = perf_flow(W, C, P, ui[0]);
+            double* b = B + (size_t)(C.c0 + k) * 8;
+            for (int e = 0; e < 8; ++e) b[e] = 0.0;
+            if (!fl.active) continue;
+            for (int e = 0; e < 7; ++e) {
+                if (C.kind == 3) {
+                    for (int a = 0; a < 3; ++a) b[e] -= fl.dQ[a] * P.xi[a][e];
+                } else {
+                    b[e] = -fl.dQi * (e == 6 ? C.Hinj : C.z[e]);
+                }
+            }
+        }
+        double* cg = Cg + (size_t)C.c0 * 8;
+        if (C.control == 0 || C.on_limit) {
+            R[w] = C.bhp - (C.control == 0 ? C.target : C.limit);
+            D[w] = 1.0;
+            std::fill(cg, cg + (size_t)C.np * 8, 0.0);
+        } else {
+            double dq;
+            R[w] = controlled_rate(*m, C, u, cg, &dq) - C.target;
+            D[w] = dq;
+        }
+    }
+}
+
+double orc_well_scaled_norm(orc_model* m, const double* R, double dt) {
+    const double V = cell_volume(*m);
+    double mx = 0.0;
+    for (size_t w = 0; w < m->cw.size(); ++w) {
+        const orc_cwell& C = m->cw[w];
+        double s;
+        if (C.control == 0 || C.on_limit)
+            s = std::max(std::fabs(C.control == 0 ? C.target : C.limit), 1.0);
+        else
+            s = V * m->poro[m->perfs[C.p0].cell] * m->fl.rho_ref[0] / dt;
+        double v = std::fabs(R[w]) / s;
+        if (!(v <= mx)) mx = v;
+    }
+    return mx;
 }
 
 }  // extern "C"

@@ -110,16 +110,25 @@ class Grid(ctypes.Structure):
 
 WELL_BHP_PRODUCER = 1
 WELL_RATE_INJECTOR = 2
+WELL_PRODUCER = 3        # bottom-hole pressure as an unknown, with a control
+WELL_INJECTOR = 4
+# controls of kinds 3/4: BHP, or a molar rate (producer: of the phases in the mask)
+CTRL_BHP, CTRL_WATER, CTRL_OIL, CTRL_GAS = 0, 1, 2, 4
+CTRL_LIQUID = CTRL_WATER | CTRL_OIL
+CTRL_TOTAL = CTRL_WATER | CTRL_OIL | CTRL_GAS
+CTRL_RATE = CTRL_TOTAL   # an injector's rate control (any nonzero value)
 
 
 class Well(ctypes.Structure):
     """``isc_well``: one well with its perforated cells (host pointer)."""
     _fields_ = [("kind", ctypes.c_int32), ("nperf", ctypes.c_int32),
                 ("perf_cells", ctypes.POINTER(ctypes.c_int32)),
-                ("target", ctypes.c_double),      # producer: BHP in Pa; injector: mol/s
+                ("target", ctypes.c_double),      # BHP in Pa (kind 1, control 0) or mol/s
                 ("T_inj", ctypes.c_double),       # K
                 ("z_inj", ctypes.c_double * NSPEC),
-                ("rw", ctypes.c_double), ("skin", ctypes.c_double)]
+                ("rw", ctypes.c_double), ("skin", ctypes.c_double),
+                ("control", ctypes.c_int32),      # kinds 3/4
+                ("limit", ctypes.c_double)]       # kinds 3/4 under rate control: BHP limit, Pa
 
 
 # --------------------------------------------------------------------------
@@ -297,7 +306,7 @@ class Workload:
     logk: np.ndarray          # [N] ln(k_h / m2)
     kv_over_kh: float
     poro: np.ndarray          # [N]
-    wells: list               # list of dicts: kind, cells, target, T_inj, z_inj
+    wells: list               # list of dicts: kind, cells, target, T_inj, z_inj, control, limit
     u0: np.ndarray            # [8][N] initial state
     dt: float                 # s
     nsteps: int
@@ -330,6 +339,8 @@ class Workload:
                 arr[i].z_inj[c] = z[c]
             arr[i].rw = w.get("rw", 0.1)
             arr[i].skin = w.get("skin", 0.0)
+            arr[i].control = w.get("control", 0)
+            arr[i].limit = w.get("limit", 0.0)
         return arr, keep
 
 
@@ -416,7 +427,8 @@ def _channels(rng, logk3, nchan, width=4, thick=2, kchan_md=100 * 500.0):
 
 
 def make_workload(name: str, nsteps: int | None = None) -> Workload:
-    """The five configurations (C1..C5) plus small test grids ("tiny:NXxNYxNZ")."""
+    """The five configurations (C1..C5), the combustion tube ("TUBE"), small test
+    grids ("tiny:NXxNYxNZ") and small grids with controlled wells ("CW:NXxNYxNZ")."""
     dx, dy, dz = 5.0, 5.0, 2.0
     dt = DT_DAYS * DAY
     if name == "C1":
@@ -512,6 +524,24 @@ def make_workload(name: str, nsteps: int | None = None) -> Workload:
         return Workload(name=name, nx=nx, ny=ny, nz=nz, dx=dx, dy=dy, dz=dz, logk=logk, kv_over_kh=kvkh,
                         poro=poro, wells=wells, u0=u0, dt=dt, nsteps=nsteps if nsteps is not None else steps,
                         seed=seed, heater=heater)
+    elif name.startswith("CW:"):
+        # Wells whose bottom-hole pressure is an unknown (well-modelling
+        # subsection) on a small grid: a column injector at (0, 0) holding
+        # the air rate of the small grids up to a maximum BHP of P0 + 5 MPa,
+        # and a column producer at the far corner holding a total molar rate
+        # of 0.3 times that down to a minimum BHP of 0.8 P0.  Tests change
+        # the controls, targets and limits in the well dicts.
+        dims = name.split(":")[1]
+        nx, ny, nz = (int(v) for v in dims.split("x"))
+        base = make_workload("tiny:" + dims, nsteps)
+        pv = float(base.poro.sum()) * dx * dy * dz
+        q = _air_rate(pv)
+        base.wells = [dict(kind=WELL_INJECTOR, cells=[cell_index(nx, ny, 0, 0, k) for k in range(nz)],
+                           target=q, T_inj=T0, z_inj=AIR, control=CTRL_RATE, limit=P0 + 5.0e6),
+                      dict(kind=WELL_PRODUCER, cells=[cell_index(nx, ny, nx - 1, ny - 1, k) for k in range(nz)],
+                           target=0.3 * q, control=CTRL_TOTAL, limit=0.8 * P0)]
+        base.name = name
+        return base
     elif name.startswith("tiny:"):
         dims = name.split(":")[1]
         nx, ny, nz = (int(v) for v in dims.split("x"))
