@@ -105,11 +105,22 @@ typedef struct {
 
 typedef struct { int32_t nx, ny, nz; double dx, dy, dz; } isc_grid;
 
-enum { ISC_WELL_BHP_PRODUCER = 1, ISC_WELL_RATE_INJECTOR = 2 };
-/* One vertical well (well-modelling subsection, Peaceman index).  Producers
- * hold a fixed bottom-hole pressure (target, Pa) with no backflow; injectors
- * inject a fixed molar rate (target, mol/s) of gas of composition z_inj at
- * T_inj, split over the perforations in proportion to their well index. */
+enum { ISC_WELL_BHP_PRODUCER = 1, ISC_WELL_RATE_INJECTOR = 2, ISC_WELL_PRODUCER = 3, ISC_WELL_INJECTOR = 4 };
+/* Well controls of kinds 3 and 4: BHP, or a molar rate (a producer's: of the
+ * phases in the mask; an injector's: any nonzero value, the injected total). */
+enum { ISC_CTRL_BHP = 0, ISC_CTRL_WATER = 1, ISC_CTRL_OIL = 2, ISC_CTRL_GAS = 4 };
+/* One vertical well (well-modelling subsection, Peaceman index).
+ * Kind 1 producers hold a fixed bottom-hole pressure (target, Pa) with no
+ * backflow; kind 2 injectors inject a fixed molar rate (target, mol/s) of gas
+ * of composition z_inj at T_inj, split over the perforations in proportion to
+ * their well index.  Kinds 3 (producer) and 4 (injector) make the bottom-hole
+ * pressure an unknown with a well equation: control ISC_CTRL_BHP holds
+ * bhp = target (Pa); otherwise the well holds a molar rate target (mol/s) --
+ * the sum over perforations of WI lambda_a (p - bhp) over the phases a in the
+ * mask for a producer (lambda_a = rho_a k_ra / mu_a, molar), or of
+ * WI (lambda_w + lambda_o + lambda_g) (bhp - p) of gas z_inj at T_inj for an
+ * injector -- and is held at its BHP limit `limit` (producer minimum,
+ * injector maximum) when the rate cannot be met within it.  No backflow. */
 typedef struct {
     int32_t kind;
     int32_t nperf;
@@ -118,6 +129,8 @@ typedef struct {
     double T_inj;
     double z_inj[ISC_NSPEC];
     double rw, skin;                  /* wellbore radius (m), skin */
+    int32_t control;                  /* kinds 3/4 */
+    double limit;                     /* kinds 3/4 under rate control: BHP limit, Pa */
 } isc_well;
 
 enum { ISC_FP64 = 0, ISC_MIXED = 1 };
@@ -253,9 +266,51 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
  * res <= tol: converged = 1, u unchanged), else decouple, the preconditioner
  * set-up and the linear solve of opts->lin (as isc_solve), and the
  * safeguarded update of u in place (saturation halving rule of the PER
- * subsection plus per-variable step limits). */
+ * subsection plus per-variable step limits).
+ * With controlled wells (kinds 3, 4) the system is bordered by one row per
+ * well in its bhp (well-modelling subsection; the bhp row of the table of
+ * unknowns and equations):
+ *   [J  B] [du  ]     [F]    B = dF/dbhp, C = dR/du, D = dR/dbhp,
+ *   [C  D] [dbhp] = - [R],   R = bhp - held BHP, or q - target (rate).
+ * First isc_well_solve sets each rate-controlled well's bhp from its own
+ * equation at the current cells (or moves it onto its BHP limit); the well
+ * rows count in res (isc_well_border's scaling); they are eliminated,
+ *   (J - B D^-1 C) du = -(F - B D^-1 R),  dbhp = -D^-1 (R + C du),
+ * the Krylov operator being the decoupled J plus the rank-one term of each
+ * well on a rate (the preconditioners see the decoupled J alone); bhp takes
+ * its Newton step with the cells. */
 isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double dt,
                            const isc_newton_opts* opts_h, isc_newton_info* info_h);
+
+/* Controlled wells (kinds 3, 4), numbered in the order of the wells given to
+ * isc_create; their perforations are listed in the same order.  The state of
+ * each is its bhp (Pa) and on_limit (1 while a rate-controlled well is held
+ * at its BHP limit); isc_create starts it at bhp = target under BHP control,
+ * else at the limit, with on_limit = 0.  Host arrays of isc_well_count's
+ * ncw entries; every call synchronises the context stream. */
+isc_status isc_well_count(const isc_ctx* ctx, int32_t* ncw_h, int32_t* ncp_h);
+isc_status isc_well_state(isc_ctx* ctx, double* bhp_h, int32_t* on_limit_h);
+isc_status isc_set_well_state(isc_ctx* ctx, const double* bhp_h, const int32_t* on_limit_h);
+/* Control switching.  With the cells at u, the rate a controlled well holds
+ * is piecewise linear and monotone in its bhp.  isc_well_solve (run by
+ * isc_newton_step first): a well on its rate whose rate at the BHP limit
+ * falls short of the target is held at the limit, else its bhp is set to the
+ * root of its rate equation.  isc_well_controls, to be called at the start of
+ * every time step (and every retry of one): a well held at its limit returns
+ * to its rate when it would move more than the target at the limit.  A well
+ * thus leaves its limit only between steps, which keeps a Newton iteration
+ * from cycling between controls.  *nswitch_h (may be NULL): wells switched.
+ * u: [8][N] device. */
+isc_status isc_well_controls(isc_ctx* ctx, const double* u, int32_t* nswitch_h);
+isc_status isc_well_solve(isc_ctx* ctx, const double* u, int32_t* nswitch_h);
+/* The well rows at (u, u_old, dt) and the current well state (assembles):
+ * R_h[ncw], D_h[ncw] (host) and B[ncp][8] = dF_cell/dbhp, C[ncp][8] =
+ * dR_w/du_cell (device; either may be NULL).  Under BHP control or at the
+ * limit R = bhp - held, D = 1, C = 0.  The Newton test scales |R| by
+ * V phi rho_ref,W / dt of the well's first perforated cell (rate rows) or by
+ * the pressure held, at least 1 Pa (BHP rows). */
+isc_status isc_well_border(isc_ctx* ctx, const double* u, const double* u_old, double dt, double* R_h,
+                           double* D_h, double* B, double* C);
 
 /* Component steps exposed for testing and profiling. */
 isc_status isc_spmv(isc_ctx* ctx, const double* Jdec, const double* x, double* y);
@@ -327,7 +382,9 @@ isc_status isc_adjoint(isc_ctx* ctx, const double* u_n, const double* u_nm1, dou
                        const double* lam_np1, double dt_np1, double* lam_n, double* g_logk,
                        double* g_A_h, const isc_solve_opts* opts_h, isc_solve_info* info_h);
 
-/* q_oil(u) defined above, summed over all producers (host output, mol/s). */
+/* q_oil(u) defined above, summed over the kind 1 producers (host output,
+ * mol/s).  isc_adjoint returns ISC_ERR_ARG for a context with controlled
+ * wells: their rows are not part of this adjoint. */
 isc_status isc_oil_rate(isc_ctx* ctx, const double* u, double* q_h);
 
 /* Kernel-class timing with HIP events on the context's stream, for

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libisc.so")
 BUILD = os.path.join(HERE, "_build")
 SOURCES = ["props.hip", "assemble.hip", "decouple.hip", "precond.hip", "krylov.hip", "bicgstab.hip", "newton.hip",
-           "adjoint.hip", "cpr.hip", "api.hip"]
+           "adjoint.hip", "cpr.hip", "wells.hip", "api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off (hipcc's host pass warns about the
          # unknown feature; that is harmless)

@@ -20,6 +20,11 @@ hipError_t isc_launch_spmv(isc_ctx*, const double* A, const double* x, double* y
 hipError_t isc_launch_update(isc_ctx*, double* u, const double* du, int32_t* flag_dev);
 hipError_t isc_launch_scaled_norm(isc_ctx*, const double* F, double dt, double* out_dev);
 hipError_t isc_launch_negate(isc_ctx*, const double* x, double* y);
+hipError_t isc_launch_well_line(isc_ctx*, const double* u, int mode);
+hipError_t isc_launch_well_rows(isc_ctx*, const double* u, const double* J);
+hipError_t isc_launch_well_reduce(isc_ctx*, double dt);
+hipError_t isc_launch_well_rhs(isc_ctx*, double* rhs);
+hipError_t isc_launch_well_update(isc_ctx*, const double* du, int32_t* nonfinite_dev);
 isc_status isc_gmres_fp64(isc_ctx*, const double* A, const double* Dinv, const double* b, double* x,
                           const isc_solve_opts* o, isc_solve_info* info);
 isc_status isc_fgmres(isc_ctx*, const double* A, const double* b, double* x, const isc_solve_opts* o,
@@ -96,9 +101,10 @@ isc_status rebuild_static(isc_ctx* ctx) {
     std::vector<int32_t> slot(n, -1);
     ctx->perf_h.assign((size_t)std::max(ctx->npf, 1) * isc::PERF_W, 0.0);
     const double re = 0.14 * std::sqrt(g.dx * g.dx + g.dy * g.dy);
-    int32_t p = 0;
+    int32_t p = 0, cwi = -1;
     for (size_t w = 0; w < ctx->wells.size(); ++w) {
         const isc_well& W = ctx->wells[w];
+        if (W.kind == ISC_WELL_PRODUCER || W.kind == ISC_WELL_INJECTOR) ++cwi;
         const std::vector<int32_t>& cells = ctx->well_cells[w];
         std::vector<double> wi(cells.size());
         double sum = 0.0;
@@ -108,6 +114,7 @@ isc_status rebuild_static(isc_ctx* ctx) {
         }
         double hinj = 0.0;
         for (int c = 0; c < 6; ++c) hinj += W.z_inj[c] * host_hgas(ctx->fluid_h, c, W.T_inj);
+        const bool controlled = W.kind == ISC_WELL_PRODUCER || W.kind == ISC_WELL_INJECTOR;
         for (size_t k = 0; k < cells.size(); ++k, ++p) {
             double* pf = ctx->perf_h.data() + (size_t)p * isc::PERF_W;
             if (slot[cells[k]] >= 0) {
@@ -117,7 +124,12 @@ isc_status rebuild_static(isc_ctx* ctx) {
             slot[cells[k]] = p;
             pf[0] = (double)W.kind;
             pf[1] = wi[k];
-            if (W.kind == ISC_WELL_BHP_PRODUCER) {
+            if (controlled) {
+                pf[2] = (double)cwi;
+                for (int c = 0; c < 7; ++c) pf[3 + c] = W.z_inj[c];
+                pf[10] = hinj;
+                pf[11] = (double)(ctx->cw_h[cwi].c0 + (int32_t)k);
+            } else if (W.kind == ISC_WELL_BHP_PRODUCER) {
                 pf[2] = W.target;
             } else {
                 const double q = W.target * wi[k] / sum;
@@ -359,10 +371,28 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     int32_t npf = 0;
     for (int32_t w = 0; w < nwells; ++w) {
         const isc_well& W = wells_h[w];
-        if (W.nperf < 1 || !W.perf_cells_h ||
-            (W.kind != ISC_WELL_BHP_PRODUCER && W.kind != ISC_WELL_RATE_INJECTOR) || !(W.rw > 0)) {
+        const bool controlled = W.kind == ISC_WELL_PRODUCER || W.kind == ISC_WELL_INJECTOR;
+        const bool ctrl_ok = !controlled ||
+                             (W.nperf <= isc::CW_MAXPERF && std::isfinite(W.target) && std::isfinite(W.limit) &&
+                              (W.control == ISC_CTRL_BHP ? W.target > 0 : (W.target >= 0 && W.limit > 0)) &&
+                              (W.kind == ISC_WELL_INJECTOR || (W.control >= 0 && W.control <= 7)));
+        if (W.nperf < 1 || !W.perf_cells_h || !(W.kind >= ISC_WELL_BHP_PRODUCER && W.kind <= ISC_WELL_INJECTOR) ||
+            !(W.rw > 0) || !ctrl_ok) {
             ctx->err = "invalid well " + std::to_string(w);
             return fail(ISC_ERR_ARG);
+        }
+        if (controlled) {
+            isc::CWell C{};
+            C.kind = W.kind;
+            C.control = W.kind == ISC_WELL_INJECTOR && W.control != ISC_CTRL_BHP ? 7 : W.control;
+            C.c0 = ctx->ncp;
+            C.np = W.nperf;
+            C.target = W.target;
+            C.limit = W.limit;
+            C.bhp = W.control == ISC_CTRL_BHP ? W.target : W.limit;
+            C.D = 1.0;
+            ctx->cw_h.push_back(C);
+            ctx->ncp += W.nperf;
         }
         std::vector<int32_t> cells(W.perf_cells_h, W.perf_cells_h + W.nperf);
         for (int32_t c : cells)
@@ -376,6 +406,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         npf += W.nperf;
     }
     ctx->npf = npf;
+    ctx->ncw = (int32_t)ctx->cw_h.size();
 
     // device allocations (all workspace lives for the context's lifetime)
     const size_t nv = (size_t)n * isc::NU;
@@ -424,6 +455,12 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->sweep32, (size_t)n * isc::NU);
     ALLOC(ctx->ticket, (size_t)1);
     ALLOC(ctx->well_off, (size_t)nwells + 1);
+    ALLOC(ctx->cw, (size_t)ctx->ncw);
+    ALLOC(ctx->cwp, (size_t)ctx->ncp * isc::CWP_W);
+    ALLOC(ctx->cwp_cell, (size_t)ctx->ncp);
+    ALLOC(ctx->cwp_well, (size_t)ctx->ncp);
+    ALLOC(ctx->wres, (size_t)1);
+    ALLOC(ctx->wsw, (size_t)1);
     ALLOC(ctx->Z, nv * ctx->mmax);
     if (ctx->inner_max > 0) {
         ALLOC(ctx->J32, (size_t)ctx->nnzb * isc::BS);
@@ -548,6 +585,27 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
             return fail(ISC_ERR_HIP);
         }
     }
+    if (ctx->ncw > 0) {   // controlled wells: perforation lists and the initial state
+        std::vector<int32_t> ccell, cwell;
+        const double vol = ctx->g.dx * ctx->g.dy * ctx->g.dz;
+        int32_t w = 0;
+        for (size_t k = 0; k < ctx->wells.size(); ++k) {
+            const isc_well& W = ctx->wells[k];
+            if (W.kind != ISC_WELL_PRODUCER && W.kind != ISC_WELL_INJECTOR) continue;
+            const std::vector<int32_t>& cells = ctx->well_cells[k];
+            ccell.insert(ccell.end(), cells.begin(), cells.end());
+            cwell.insert(cwell.end(), cells.size(), w);
+            ctx->cw_h[w].rscale = vol * ctx->poro_h[cells[0]] * ctx->fluid_h.rho_ref[0];
+            ++w;
+        }
+        if (!h2d(ctx->cwp_cell, ccell.data(), ccell.size() * sizeof(int32_t)) ||
+            !h2d(ctx->cwp_well, cwell.data(), cwell.size() * sizeof(int32_t)) ||
+            !h2d(ctx->cw, ctx->cw_h.data(), ctx->cw_h.size() * sizeof(isc::CWell)) ||
+            hipMemsetAsync(ctx->cwp, 0, (size_t)ctx->ncp * isc::CWP_W * sizeof(double), ctx->stream) != hipSuccess) {
+            ctx->err = "host to device copy failed";
+            return fail(ISC_ERR_HIP);
+        }
+    }
     if ((s = rebuild_static(ctx)) != ISC_OK) return fail(s);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
         ctx->err = "stream synchronisation failed";
@@ -571,7 +629,8 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->perf_cell, ctx->well_off, ctx->bricks_fwd, ctx->bricks_bwd, ctx->sweep64,
                     ctx->sweep32, ctx->ticket, ctx->Lt, ctx->Lt32, ctx->items_bwd_spmv,
                     ctx->mg_store, ctx->mg_cinv, ctx->cpr_pc, ctx->cpr_V, ctx->cpr_Z, ctx->cpr_w,
-                    ctx->cpr_rp, ctx->cpr_ep, ctx->cpr_w1, ctx->cpr_r2, ctx->small_p};
+                    ctx->cpr_rp, ctx->cpr_ep, ctx->cpr_w1, ctx->cpr_r2, ctx->small_p, ctx->cw, ctx->cwp,
+                    ctx->cwp_cell, ctx->cwp_well, ctx->wres, ctx->wsw};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (ctx->hscratch) hipHostFree(ctx->hscratch);
@@ -831,14 +890,26 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
     isc_newton_info inf{};
     inf.bad_cell = -1;
     hipEvent_t* ev = ctx->ev;
+    const bool wells = ctx->ncw > 0;
     ISC_HIP(hipEventRecord(ev[0], ctx->stream));
     int tk = isc_prof_begin(ctx, ISC_PROF_ASSEMBLE);
+    if (wells) ISC_HIP(isc_launch_well_line(ctx, u, 0));   // the rate wells' equations alone, for bhp
     ISC_HIP(isc_launch_props(ctx, u, u_old, dt));
     ISC_HIP(isc_launch_assemble(ctx, u, ctx->F, ctx->J));
+    if (wells) {
+        ISC_HIP(isc_launch_well_rows(ctx, u, ctx->J));
+        ISC_HIP(isc_launch_well_reduce(ctx, dt));
+    }
     isc_prof_end(ctx, tk);
     ISC_HIP(hipEventRecord(ev[1], ctx->stream));
     double res;
     TRY(isc_scaled_norm(ctx, ctx->F, dt, &res));
+    if (wells) {
+        ISC_HIP(hipMemcpyAsync(ctx->hscratch + 16, ctx->wres, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        ISC_HIP(hipStreamSynchronize(ctx->stream));
+        const double rw = ctx->hscratch[16];
+        if (!(rw <= res)) res = rw;
+    }
     inf.res_scaled = res;
     if (!std::isfinite(res)) {
         ctx->err = "isc_newton_step: non-finite residual";
@@ -856,6 +927,7 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
     ISC_HIP(isc_launch_decouple(ctx, ctx->J, ctx->F, ctx->flags + FLAG_BAD));
     isc_prof_end(ctx, tk);
     ISC_HIP(isc_launch_negate(ctx, ctx->F, ctx->rhs));
+    if (wells) ISC_HIP(isc_launch_well_rhs(ctx, ctx->rhs));
     ISC_HIP(hipEventRecord(ev[2], ctx->stream));
     isc_status st;
     TRY(check_precond(ctx, &o->lin, "isc_newton_step"));
@@ -887,16 +959,19 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
         ctx->err = "isc_newton_step: restart exceeds the context's maximum";
         return ISC_ERR_ARG;
     }
+    ctx->border = wells;   // the Krylov operator takes the eliminated well rows
     if (o->lin.precision == ISC_MIXED || cpr)
         st = isc_fgmres(ctx, ctx->J, ctx->rhs, ctx->du, &o->lin, &inf.lin);
     else
         st = isc_gmres_fp64(ctx, ctx->J, ctx->Dinv, ctx->rhs, ctx->du, &o->lin, &inf.lin);
+    ctx->border = false;
     ISC_HIP(hipEventRecord(ev[4], ctx->stream));
     if (st != ISC_OK) {
         if (info_h) *info_h = inf;
         return st;
     }
     ISC_HIP(isc_launch_update(ctx, u, ctx->du, ctx->flags + FLAG_NONFIN));
+    if (wells) ISC_HIP(isc_launch_well_update(ctx, ctx->du, ctx->flags + FLAG_NONFIN));
     ISC_HIP(hipEventRecord(ev[5], ctx->stream));
     int32_t nf;
     TRY(read_flag(ctx, FLAG_NONFIN, &nf));
@@ -917,6 +992,10 @@ isc_status isc_adjoint(isc_ctx* ctx, const double* u_n, const double* u_nm1, dou
                        double dt_np1, double* lam_n, double* g_logk, double* g_A_h, const isc_solve_opts* opts_h,
                        isc_solve_info* info_h) {
     TRY(check_ctx(ctx));
+    if (ctx->ncw > 0) {
+        ctx->err = "isc_adjoint: the well rows of bhp unknowns are not part of the adjoint";
+        return ISC_ERR_ARG;
+    }
     return isc_adjoint_impl(ctx, u_n, u_nm1, dt_n, lam_np1, dt_np1, lam_n, g_logk, g_A_h, opts_h, info_h);
 }
 
@@ -927,6 +1006,111 @@ isc_status isc_oil_rate(isc_ctx* ctx, const double* u, double* q_h) {
         return ISC_ERR_ARG;
     }
     return isc_oil_rate_impl(ctx, u, q_h);
+}
+
+// ---- controlled wells
+
+namespace {
+isc_status read_wells(isc_ctx* ctx, std::vector<isc::CWell>& cw) {
+    cw.resize((size_t)ctx->ncw);
+    if (ctx->ncw == 0) return ISC_OK;
+    ISC_HIP(hipMemcpyAsync(cw.data(), ctx->cw, cw.size() * sizeof(isc::CWell), hipMemcpyDeviceToHost, ctx->stream));
+    ISC_HIP(hipStreamSynchronize(ctx->stream));
+    return ISC_OK;
+}
+
+isc_status well_line(isc_ctx* ctx, const double* u, int mode, int32_t* nswitch_h, const char* who) {
+    TRY(check_ctx(ctx));
+    if (!u) {
+        ctx->err = std::string(who) + ": invalid argument";
+        return ISC_ERR_ARG;
+    }
+    if (ctx->ncw == 0) {
+        if (nswitch_h) *nswitch_h = 0;
+        return ISC_OK;
+    }
+    ISC_HIP(hipMemsetAsync(ctx->wsw, 0, sizeof(int32_t), ctx->stream));
+    ISC_HIP(isc_launch_well_line(ctx, u, mode));
+    int32_t nsw = 0;
+    ISC_HIP(hipMemcpyAsync(&nsw, ctx->wsw, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    ISC_HIP(hipStreamSynchronize(ctx->stream));
+    if (nswitch_h) *nswitch_h = nsw;
+    return ISC_OK;
+}
+}  // namespace
+
+isc_status isc_well_count(const isc_ctx* ctx, int32_t* ncw_h, int32_t* ncp_h) {
+    TRY(check_ctx(ctx));
+    if (ncw_h) *ncw_h = ctx->ncw;
+    if (ncp_h) *ncp_h = ctx->ncp;
+    return ISC_OK;
+}
+
+isc_status isc_well_state(isc_ctx* ctx, double* bhp_h, int32_t* on_limit_h) {
+    TRY(check_ctx(ctx));
+    std::vector<isc::CWell> cw;
+    TRY(read_wells(ctx, cw));
+    for (size_t w = 0; w < cw.size(); ++w) {
+        if (bhp_h) bhp_h[w] = cw[w].bhp;
+        if (on_limit_h) on_limit_h[w] = cw[w].on_limit;
+    }
+    return ISC_OK;
+}
+
+isc_status isc_set_well_state(isc_ctx* ctx, const double* bhp_h, const int32_t* on_limit_h) {
+    TRY(check_ctx(ctx));
+    std::vector<isc::CWell> cw;
+    TRY(read_wells(ctx, cw));
+    for (size_t w = 0; w < cw.size(); ++w) {
+        if (bhp_h) {
+            if (!std::isfinite(bhp_h[w])) {
+                ctx->err = "isc_set_well_state: non-finite bhp";
+                return ISC_ERR_ARG;
+            }
+            cw[w].bhp = bhp_h[w];
+        }
+        if (on_limit_h) cw[w].on_limit = on_limit_h[w] ? 1 : 0;
+    }
+    if (!cw.empty()) {
+        ISC_HIP(hipMemcpyAsync(ctx->cw, cw.data(), cw.size() * sizeof(isc::CWell), hipMemcpyHostToDevice,
+                               ctx->stream));
+        ISC_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    return ISC_OK;
+}
+
+isc_status isc_well_controls(isc_ctx* ctx, const double* u, int32_t* nswitch_h) {
+    return well_line(ctx, u, 1, nswitch_h, "isc_well_controls");
+}
+
+isc_status isc_well_solve(isc_ctx* ctx, const double* u, int32_t* nswitch_h) {
+    return well_line(ctx, u, 0, nswitch_h, "isc_well_solve");
+}
+
+isc_status isc_well_border(isc_ctx* ctx, const double* u, const double* u_old, double dt, double* R_h, double* D_h,
+                           double* B, double* C) {
+    TRY(check_ctx(ctx));
+    if (!u || !u_old || !(dt > 0)) {
+        ctx->err = "isc_well_border: invalid argument";
+        return ISC_ERR_ARG;
+    }
+    if (ctx->ncw == 0) return ISC_OK;
+    ISC_HIP(isc_launch_props(ctx, u, u_old, dt));
+    ISC_HIP(isc_launch_assemble(ctx, u, ctx->F, ctx->J));
+    ISC_HIP(isc_launch_well_rows(ctx, u, ctx->J));
+    ISC_HIP(isc_launch_well_reduce(ctx, dt));
+    const size_t pitch = (size_t)isc::CWP_W * sizeof(double);
+    if (B) ISC_HIP(hipMemcpy2DAsync(B, 8 * sizeof(double), ctx->cwp + isc::CWP_B, pitch, 8 * sizeof(double),
+                                    (size_t)ctx->ncp, hipMemcpyDeviceToDevice, ctx->stream));
+    if (C) ISC_HIP(hipMemcpy2DAsync(C, 8 * sizeof(double), ctx->cwp + isc::CWP_C, pitch, 8 * sizeof(double),
+                                    (size_t)ctx->ncp, hipMemcpyDeviceToDevice, ctx->stream));
+    std::vector<isc::CWell> cw;
+    TRY(read_wells(ctx, cw));
+    for (size_t w = 0; w < cw.size(); ++w) {
+        if (R_h) R_h[w] = cw[w].R;
+        if (D_h) D_h[w] = cw[w].D;
+    }
+    return ISC_OK;
 }
 
 isc_status isc_profile(isc_ctx* ctx, int32_t enable, double* ms_h, int32_t* count_h) {

@@ -56,6 +56,24 @@ struct LagUpdateT {
     const TV* w;
 };
 using LagUpdate = LagUpdateT<double>;
+
+// A well whose bottom-hole pressure is an unknown (kinds ISC_WELL_PRODUCER
+// and ISC_WELL_INJECTOR), device resident: its control, its state (bhp and
+// whether it is held at its BHP limit) and its row of the last assembly.
+struct CWell {
+    int32_t kind, control;    // 3 / 4; ISC_CTRL_BHP or a phase mask
+    int32_t c0, np;           // its perforations [c0, c0 + np) of the controlled-perforation list
+    double target, limit;
+    double bhp;               // state
+    int32_t on_limit;         // state: rate control suspended at the BHP limit
+    int32_t pad;
+    double R, D;              // well equation's residual and dR/dbhp at the last assembly
+    double rscale;            // rate rows: V phi rho_ref,W of its first perforated cell (divided by dt)
+};
+// per controlled perforation: B = dF_cell/dbhp, C = dq/du_cell, the rate q
+// and dq/dbhp it adds to its well, Bt = J_ii^-1 B
+constexpr int CWP_B = 0, CWP_C = 8, CWP_Q = 16, CWP_DQ = 17, CWP_BT = 18, CWP_W = 26;
+constexpr int CW_MAXPERF = 2048;   // perforations of one controlled well (LDS of the well-line solve)
 // Per-cell property payload written by the property pass and read by the
 // face-flux assembly (doubles, value followed by the 8 partial derivatives):
 //   [0, 72)     local residual terms of the 8 rows (accumulation change,
@@ -136,6 +154,18 @@ struct isc_ctx {
     int32_t heater_cell = -1;       // heat source into one cell's energy balance (isc_set_heater)
     double heater_W = 0.0;
     int32_t* well_slot = nullptr;   // [N] perforation index or -1
+    // controlled wells (bhp unknowns): their perforations are listed in well
+    // order; the Krylov operator of isc_newton_step subtracts the eliminated
+    // well rows while `border` is set
+    int32_t ncw = 0, ncp = 0;
+    std::vector<isc::CWell> cw_h;   // set-up copy (the state lives on the device)
+    isc::CWell* cw = nullptr;       // [ncw]
+    double* cwp = nullptr;          // [ncp][CWP_W]
+    int32_t* cwp_cell = nullptr;    // [ncp] perforated cell
+    int32_t* cwp_well = nullptr;    // [ncp] its well
+    double* wres = nullptr;         // [1] scaled residual of the well rows
+    int32_t* wsw = nullptr;         // [1] wells switched by the last well-line pass
+    bool border = false;
     double* perf = nullptr;         // [npf][PERF_W]
     std::vector<double> perf_h;
     // hyperplane level schedule for the ILU recurrences
@@ -263,7 +293,9 @@ struct isc_ctx {
 };
 
 namespace isc {
-constexpr int PERF_W = 12;  // kind, wi, bhp, q[7], qE, q_total
+// perforation table: kind, wi, bhp, q[7], qE, q_total (kinds 1, 2);
+// kinds 3, 4: kind, wi, controlled well, z_inj[7], H_inj, controlled perforation
+constexpr int PERF_W = 12;
 #ifndef ISC_NPART
 #define ISC_NPART 4096
 #endif

@@ -416,6 +416,7 @@ hipError_t isc_launch_bilu0_apply_spmv(isc_ctx*, const double*, const double*, c
 hipError_t isc_launch_update_apply_spmv(isc_ctx*, const double*, const double*, const isc::LagUpdate&, double*,
                                         double*);
 hipError_t isc_launch_bilu0_factor(isc_ctx*, const double*, double*, int32_t*);
+void isc_well_apply(isc_ctx*, const double* x, double* w);   // eliminated well rows (isc_newton_step only)
 
 namespace isc {
 
@@ -518,6 +519,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
             ISC_HIP(hipMemcpyAsync(u, b, (size_t)len * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         } else {
             isc_launch_spmv(ctx, A, x, ctx->tvec);
+            isc_well_apply(ctx, x, ctx->tvec);
             hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, u,
                                ctx->partial);
             hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
@@ -553,6 +555,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
                 } else {
                     isc_launch_bilu0_apply_spmv(ctx, A, Dinv, u, Zj, ctx->w);
                 }
+                isc_well_apply(ctx, Zj, ctx->w);
                 isc_prof_end(ctx, tk);
             }
             const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
@@ -601,6 +604,7 @@ isc_status isc_gmres_fp64(isc_ctx* ctx, const double* A, const double* Dinv, con
     }
     if (st != ISC_OK) {
         isc_launch_spmv(ctx, A, x, ctx->tvec);
+        isc_well_apply(ctx, x, ctx->tvec);
         hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, ctx->w,
                            ctx->partial);
         hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + 2 * MAXV);
@@ -846,6 +850,7 @@ isc_status isc_fgmres(isc_ctx* ctx, const double* A, const double* b, double* x,
             ISC_HIP(hipMemcpyAsync(u, b, (size_t)len * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         } else {
             isc_launch_spmv(ctx, A, x, ctx->tvec);
+            isc_well_apply(ctx, x, ctx->tvec);
             hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, u,
                                ctx->partial);
             hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb,
@@ -878,6 +883,7 @@ isc_status isc_fgmres(isc_ctx* ctx, const double* A, const double* b, double* x,
                     isc_launch_spmv(ctx, A, Zj, ctx->w);
                     isc_prof_end(ctx, tk);
                 }
+                isc_well_apply(ctx, Zj, ctx->w);
             }
             const int tk = isc_prof_begin(ctx, ISC_PROF_KRYLOV);
             hipLaunchKernelGGL(dcgs2_dots<double2>, dim3(nb2), dim3(256), 0, ctx->stream, len2, Q2, ldv2, j, u2,
@@ -924,6 +930,7 @@ isc_status isc_fgmres(isc_ctx* ctx, const double* A, const double* b, double* x,
     }
     if (st != ISC_OK) {
         isc_launch_spmv(ctx, A, x, ctx->tvec);
+        isc_well_apply(ctx, x, ctx->tvec);
         hipLaunchKernelGGL(residual_norm, dim3(nb), dim3(256), 0, ctx->stream, len, b, ctx->tvec, ctx->w,
                            ctx->partial);
         hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, ctx->stream, ctx->partial, nb, red + 2 * MAXV);

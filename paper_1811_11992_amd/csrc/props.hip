@@ -11,6 +11,8 @@
 // heaviest oil, RK mixing a = sum y Tc^1.25/sqrt(pc), b = sum y Tc/pc,
 // Tcm = (a^2/b)^(2/3), pcm = Tcm/b, zero capillary pressure, phi_f =
 // phi - C_c/rho_coke in the fluid and reaction terms, no coke conductivity.
+#include <algorithm>
+
 #include "common.h"
 
 namespace isc {
@@ -99,7 +101,7 @@ template <class S> struct Cell {
     S gam[3];      // specific weights g rho M
     S KT;          // bulk thermal conductivity
     S rate[4];     // Arrhenius rates r_R per bulk volume
-    S mob_o;       // oil mobility k_ro rho_o / mu_o
+    S mob_w, mob_o, mob_g;   // phase mobilities k_ra rho_a / mu_a
 };
 
 // Secondary variables of one cell.  u = (p, x_LO, y_O2, y_CO2, T, S_w, S_g, C_c).
@@ -231,8 +233,10 @@ template <class S> __device__ void cell_eval(const isc_fluid& f, double phi_ref,
     {
         const S mw = krw * rho[0] / mu[0];
         const S mo = kro * rho[1] / mu[1];
+        c.mob_w = mw;
         c.mob_o = mo;
         const S mg = krg * rho[2] / mu[2];
+        c.mob_g = mg;
         c.mx[mob_slot(0, 0)] = mw;
         c.mx[mob_slot(0, 6)] = mw * H[0];
         c.mx[mob_slot(1, 1)] = mo * xlo;
@@ -278,7 +282,7 @@ __global__ void __launch_bounds__(256, 2) props_kernel(
     int32_t n, const double* __restrict__ u, const double* __restrict__ acc_old_in, double vol_dt,
     double vol, const double* __restrict__ poro, const int32_t* __restrict__ well_slot,
     const double* __restrict__ perf, const isc_fluid* __restrict__ fl, double* __restrict__ payload,
-    int32_t heater_cell, double heater_W) {
+    int32_t heater_cell, double heater_W, const CWell* __restrict__ cw) {
     const int32_t i = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
     const int k = threadIdx.x & 7;
     if (i >= n) return;
@@ -301,12 +305,22 @@ __global__ void __launch_bounds__(256, 2) props_kernel(
 #pragma unroll
     for (int e = 0; e < 8; ++e) loc[e] = vol_dt * (c.acc[e] - acc_old[e]) - vol * c.src[e];
 
-    // wells: producer inflow (Peaceman, no backflow) or fixed injection
+    // wells: producer inflow (Peaceman, no backflow) at a fixed BHP or at the
+    // well's bhp unknown, fixed injection, or injection at the well's bhp
+    // with the cell's total mobility
     const int32_t ws = well_slot[i];
     if (ws >= 0) {
         const double* pf = perf + (size_t)ws * PERF_W;
-        if (pf[0] == 1.0) {
-            const double wi = pf[1], bhp = pf[2];
+        if (pf[0] == 4.0) {
+            const double wi = pf[1], bhp = cw[(int)pf[2]].bhp;
+            if (bhp > ug[0].v) {
+                const G1 Q = (wi * ((c.mob_w + c.mob_o) + c.mob_g)) * (bhp - ug[0]);   // > 0: injection
+#pragma unroll
+                for (int q = 0; q < 6; ++q) loc[q] = loc[q] - Q * pf[3 + q];
+                loc[6] = loc[6] - Q * pf[10];
+            }
+        } else if (pf[0] != 2.0) {
+            const double wi = pf[1], bhp = pf[0] == 1.0 ? pf[2] : cw[(int)pf[2]].bhp;
             if (ug[0].v > bhp) {
                 const G1 dp = wi * (bhp - ug[0]);   // < 0: production
 #pragma unroll
@@ -364,6 +378,190 @@ __global__ void __launch_bounds__(256) accgrad_kernel(
     }
 }
 
+// ---- controlled wells
+
+// the mobility a controlled well's rate is taken over: the phases of a
+// producer's mask, the total at an injector
+__device__ __forceinline__ double well_mobility(const CWell& W, const Cell<double>& c) {
+    if (W.kind == ISC_WELL_INJECTOR) return (c.mob_w + c.mob_o) + c.mob_g;
+    double lam = 0.0;
+    if (W.control & ISC_CTRL_WATER) lam += c.mob_w;
+    if (W.control & ISC_CTRL_OIL) lam += c.mob_o;
+    if (W.control & ISC_CTRL_GAS) lam += c.mob_g;
+    return lam;
+}
+
+// One wavefront per controlled well.  With the cells fixed at u, the rate a
+// rate-controlled well holds is piecewise linear and monotone in its bhp b:
+//   g(b) = sum_k a_k (p_k - b)^+   (producer, a_k = WI lambda of its phases)
+//   g(b) = sum_k a_k (b - p_k)^+   (injector, a_k = WI lambda_t),
+// evaluated here in the producer's form over s b, s = +1 / -1.
+// mode 0, before a Newton iteration: a well on its rate moves to its limit if
+// g(limit) < target, else b becomes the root of g(b) = target (the first
+// breakpoint beyond the limit with g <= target closes the linear piece that
+// holds it).  mode 1, at a time step's start: a well held at its limit
+// returns to its rate if g(limit) > target.  a and p are staged in LDS.
+__global__ void __launch_bounds__(64) well_line_kernel(int mode, const int32_t* __restrict__ pcell,
+                                                      const double* __restrict__ u, int32_t n,
+                                                      const double* __restrict__ poro,
+                                                      const int32_t* __restrict__ well_slot,
+                                                      const double* __restrict__ perf,
+                                                      const isc_fluid* __restrict__ fl, CWell* cw,
+                                                      int32_t* nswitch) {
+    extern __shared__ double sh[];
+    CWell& W = cw[blockIdx.x];
+    if (W.control == ISC_CTRL_BHP) return;
+    if ((mode == 0) == (W.on_limit != 0)) return;
+    const int np = W.np;
+    const double s = W.kind == ISC_WELL_INJECTOR ? -1.0 : 1.0;
+    double* a = sh;
+    double* sp = sh + np;   // s p_k
+    for (int k = threadIdx.x; k < np; k += 64) {
+        const int32_t i = pcell[W.c0 + k];
+        double ui[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ui[q] = u[(size_t)q * n + i];
+        Cell<double> c;
+        cell_eval<double>(*fl, poro[i], ui, c);
+        a[k] = perf[(size_t)well_slot[i] * PERF_W + 1] * well_mobility(W, c);
+        sp[k] = s * ui[0];
+    }
+    __syncthreads();
+    auto g = [&](double x) {   // g at s b = x, summed in perforation order
+        double t = 0.0;
+        for (int k = 0; k < np; ++k) {
+            const double d = sp[k] - x;
+            if (d > 0.0) t += a[k] * d;
+        }
+        return t;
+    };
+    const double slim = s * W.limit, c = W.target;
+    if (mode == 1) {
+        if (threadIdx.x == 0 && g(slim) > c) {
+            W.on_limit = 0;
+            atomicAdd(nswitch, 1);
+        }
+        return;
+    }
+    const double glim = g(slim);   // every lane, same value
+    if (glim < c) {
+        if (threadIdx.x == 0) {
+            W.on_limit = 1;
+            W.bhp = W.limit;
+            atomicAdd(nswitch, 1);
+        }
+        return;
+    }
+    // hi: the smallest breakpoint beyond the limit with g <= target
+    double hi = INFINITY;
+    for (int j = threadIdx.x; j < np; j += 64)
+        if (sp[j] > slim && sp[j] < hi && g(sp[j]) <= c) hi = sp[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) hi = fmin(hi, __shfl_xor(hi, off, 64));
+    if (threadIdx.x != 0) return;
+    if (hi == INFINITY) {   // no perforation beyond the limit: g(limit) = 0 = target
+        W.bhp = W.limit;
+        return;
+    }
+    double lo = slim, sa = 0.0, sap = 0.0;
+    for (int k = 0; k < np; ++k) {
+        if (sp[k] < hi && sp[k] > lo) lo = sp[k];
+        if (sp[k] >= hi) {
+            sa += a[k];
+            sap += a[k] * sp[k];
+        }
+    }
+    double b = sa > 0.0 ? (sap - c) / sa : lo;
+    b = fmin(fmax(b, lo), hi);
+    W.bhp = s * b;
+}
+
+// Eight lanes per controlled perforation (lane k carries d/du_k): the
+// perforation's entries of Newton's bordered system at the well's bhp --
+// B = dF_cell/dbhp, C = dq/du_cell with q the rate it adds to its well's
+// equation, dq/dbhp -- and Bt = J_ii^-1 B from the cell's (not yet
+// decoupled) diagonal block, by Gauss-Jordan elimination with partial
+// pivoting in LDS.
+__global__ void __launch_bounds__(256) well_rows_kernel(
+    int32_t ncp, const int32_t* __restrict__ pcell, const int32_t* __restrict__ pwell, const double* __restrict__ u,
+    int32_t n, const double* __restrict__ poro, const int32_t* __restrict__ well_slot,
+    const double* __restrict__ perf, const isc_fluid* __restrict__ fl, const CWell* __restrict__ cw,
+    const double* __restrict__ J, const int32_t* __restrict__ diag_pos, double* __restrict__ cwp) {
+    __shared__ double tile[32][8][9];
+    const int32_t p = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
+    const int k = threadIdx.x & 7;
+    const int gi = threadIdx.x >> 3;
+    const bool live = p < ncp;
+    double Bk = 0.0;
+    int32_t i = 0;
+    if (live) {
+        i = pcell[p];
+        const double* pf = perf + (size_t)well_slot[i] * PERF_W;
+        const CWell& W = cw[pwell[p]];
+        G1 ug[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ug[q] = G1{u[(size_t)q * n + i], q == k ? 1.0 : 0.0};
+        Cell<G1> c;
+        cell_eval<G1>(*fl, poro[i], ug, c);
+        const double wi = pf[1];
+        G1 q = G1{0.0, 0.0};
+        double dq = 0.0;
+        if (W.kind == ISC_WELL_PRODUCER) {
+            if (ug[0].v > W.bhp) {
+                const G1 dp = W.bhp - ug[0];
+                if (W.control & ISC_CTRL_WATER) { q = q - (wi * c.mob_w) * dp; dq -= wi * c.mob_w.v; }
+                if (W.control & ISC_CTRL_OIL) { q = q - (wi * c.mob_o) * dp; dq -= wi * c.mob_o.v; }
+                if (W.control & ISC_CTRL_GAS) { q = q - (wi * c.mob_g) * dp; dq -= wi * c.mob_g.v; }
+                if (k < 7) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        if (mob_slot(a, k) >= 0) t += c.mx[mob_slot(a, k)].v;
+                    Bk = -wi * t;
+                }
+            }
+        } else if (W.bhp > ug[0].v) {
+            const G1 lt = (c.mob_w + c.mob_o) + c.mob_g;
+            q = (wi * lt) * (W.bhp - ug[0]);
+            dq = wi * lt.v;
+            Bk = k < 6 ? -dq * pf[3 + k] : k == 6 ? -dq * pf[10] : 0.0;
+        }
+        double* o = cwp + (size_t)p * CWP_W;
+        o[CWP_B + k] = Bk;
+        o[CWP_C + k] = q.d;
+        if (k == 0) {
+            o[CWP_Q] = q.v;
+            o[CWP_DQ] = dq;
+        }
+        const double* Jd = J + (size_t)diag_pos[i] * 64;
+#pragma unroll
+        for (int c2 = 0; c2 < 8; ++c2) tile[gi][k][c2] = Jd[k * 8 + c2];
+        tile[gi][k][8] = Bk;
+    }
+    __syncthreads();
+    if (!live || k != 0) return;
+    double (*a)[9] = tile[gi];
+    bool ok = true;
+    for (int col = 0; col < 8 && ok; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 8; ++r)
+            if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
+        if (!(fabs(a[piv][col]) > 0.0)) { ok = false; break; }
+        if (piv != col)
+            for (int c2 = 0; c2 < 9; ++c2) { const double t = a[col][c2]; a[col][c2] = a[piv][c2]; a[piv][c2] = t; }
+        const double d = a[col][col];
+        for (int c2 = col; c2 < 9; ++c2) a[col][c2] /= d;
+        for (int r = 0; r < 8; ++r) {
+            if (r == col) continue;
+            const double f = a[r][col];
+            if (f == 0.0) continue;
+            for (int c2 = col; c2 < 9; ++c2) a[r][c2] -= f * a[col][c2];
+        }
+    }
+    double* o = cwp + (size_t)p * CWP_W;
+    for (int e = 0; e < 8; ++e) o[CWP_BT + e] = ok ? a[e][8] : 0.0;   // a singular block is reported by the decoupling
+}
+
 }  // namespace isc
 
 hipError_t isc_launch_accgrad(isc_ctx* ctx, const double* u) {
@@ -381,6 +579,27 @@ hipError_t isc_launch_props(isc_ctx* ctx, const double* u, const double* u_old, 
     const int blocks = (int)(((int64_t)ctx->n * 8 + threads - 1) / threads);
     hipLaunchKernelGGL(isc::props_kernel, dim3(blocks), dim3(threads), 0, ctx->stream, ctx->n, u,
                        ctx->acc_old, vol / dt, vol, ctx->poro, ctx->well_slot, ctx->perf, ctx->fluid_d,
-                       ctx->payload, ctx->heater_cell, ctx->heater_W);
+                       ctx->payload, ctx->heater_cell, ctx->heater_W, ctx->cw);
+    return hipGetLastError();
+}
+
+// Controlled wells: the well line (bhp from its rate equation at fixed
+// cells) and the well rows of Newton's bordered system.
+hipError_t isc_launch_well_line(isc_ctx* ctx, const double* u, int mode) {
+    if (ctx->ncw == 0) return hipSuccess;
+    int maxnp = 1;
+    for (const isc::CWell& W : ctx->cw_h) maxnp = std::max(maxnp, (int)W.np);
+    hipLaunchKernelGGL(isc::well_line_kernel, dim3(ctx->ncw), dim3(64), (size_t)2 * maxnp * sizeof(double),
+                       ctx->stream, mode, ctx->cwp_cell, u, ctx->n, ctx->poro, ctx->well_slot, ctx->perf,
+                       ctx->fluid_d, ctx->cw, ctx->wsw);
+    return hipGetLastError();
+}
+
+hipError_t isc_launch_well_rows(isc_ctx* ctx, const double* u, const double* J) {
+    if (ctx->ncp == 0) return hipSuccess;
+    const int blocks = (int)(((int64_t)ctx->ncp * 8 + 255) / 256);
+    hipLaunchKernelGGL(isc::well_rows_kernel, dim3(blocks), dim3(256), 0, ctx->stream, ctx->ncp, ctx->cwp_cell,
+                       ctx->cwp_well, u, ctx->n, ctx->poro, ctx->well_slot, ctx->perf, ctx->fluid_d, ctx->cw, J,
+                       ctx->diag_pos, ctx->cwp);
     return hipGetLastError();
 }

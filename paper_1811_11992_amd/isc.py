@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 from . import inputs as I
@@ -85,6 +86,12 @@ def lib():
         L.isc_adjoint.argtypes = [_vp, _vp, _vp, _f64, _vp, _f64, _vp, _vp, _vp, ctypes.POINTER(SolveOpts),
                                   ctypes.POINTER(SolveInfo)]
         L.isc_oil_rate.argtypes = [_vp, _vp, ctypes.POINTER(_f64)]
+        L.isc_well_count.argtypes = [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]
+        L.isc_well_state.argtypes = [_vp, _vp, _vp]
+        L.isc_set_well_state.argtypes = [_vp, _vp, _vp]
+        L.isc_well_controls.argtypes = [_vp, _vp, ctypes.POINTER(_i32)]
+        L.isc_well_solve.argtypes = [_vp, _vp, ctypes.POINTER(_i32)]
+        L.isc_well_border.argtypes = [_vp, _vp, _vp, _f64, _vp, _vp, _vp, _vp]
         L.isc_profile.argtypes = [_vp, _i32, _vp, _vp]
         L.isc_profile_vectors.argtypes = [_vp, _vp]
         L.isc_last_error.argtypes = [_vp]
@@ -145,6 +152,9 @@ class Context:
         rp, ci, nn = _vp(), _vp(), _i32()
         self._check(L.isc_bcsr_pattern(self.h, ctypes.byref(rp), ctypes.byref(ci), ctypes.byref(nn)))
         self.nnzb = nn.value
+        ncw, ncp = _i32(), _i32()
+        self._check(L.isc_well_count(self.h, ctypes.byref(ncw), ctypes.byref(ncp)))
+        self.ncw, self.ncp = ncw.value, ncp.value
 
     def close(self):
         """Destroy the context now (waits for its stream, frees its workspace).
@@ -178,6 +188,38 @@ class Context:
 
     def isc_set_heater(self, cell: int, rate_W: float):
         self._check(lib().isc_set_heater(self.h, int(cell), float(rate_W)))
+
+    # ---- controlled wells (kinds 3, 4)
+    def isc_well_state(self):
+        """(bhp [ncw], on_limit [ncw]) as numpy arrays."""
+        bhp = (ctypes.c_double * max(1, self.ncw))()
+        on = (ctypes.c_int32 * max(1, self.ncw))()
+        self._check(lib().isc_well_state(self.h, bhp, on))
+        return np.array(bhp[:self.ncw]), np.array(on[:self.ncw], dtype=np.int32)
+
+    def isc_set_well_state(self, bhp, on_limit):
+        b = (ctypes.c_double * max(1, self.ncw))(*[float(x) for x in bhp])
+        o = (ctypes.c_int32 * max(1, self.ncw))(*[int(x) for x in on_limit])
+        self._check(lib().isc_set_well_state(self.h, b, o))
+
+    def isc_well_controls(self, u):
+        nsw = _i32()
+        self._check(lib().isc_well_controls(self.h, _ptr(u), ctypes.byref(nsw)))
+        return nsw.value
+
+    def isc_well_solve(self, u):
+        nsw = _i32()
+        self._check(lib().isc_well_solve(self.h, _ptr(u), ctypes.byref(nsw)))
+        return nsw.value
+
+    def isc_well_border(self, u, u_old, dt):
+        """(R [ncw], D [ncw]) numpy and (B [ncp][8], C [ncp][8]) device tensors."""
+        R = (ctypes.c_double * max(1, self.ncw))()
+        D = (ctypes.c_double * max(1, self.ncw))()
+        B = torch.zeros((max(1, self.ncp), 8), dtype=torch.float64, device=self.device)
+        C = torch.zeros((max(1, self.ncp), 8), dtype=torch.float64, device=self.device)
+        self._check(lib().isc_well_border(self.h, _ptr(u), _ptr(u_old), float(dt), R, D, _ptr(B), _ptr(C)))
+        return np.array(R[:self.ncw]), np.array(D[:self.ncw]), B[:self.ncp], C[:self.ncp]
 
     def isc_assemble(self, u, u_old, dt, F=None, J=None):
         F = self.empty_F() if F is None else F
@@ -326,13 +368,18 @@ class Simulator:
         self.lin = lin or solve_opts()
 
     def step(self, u, dt):
-        """Advance u (in place) by one step of at most dt; returns a record."""
+        """Advance u (in place) by one step of at most dt; returns a record.
+        Each attempt starts with the controlled wells' step-start control
+        check; a failed attempt restores u and the well state."""
         u_old = u.clone()
         dts, cuts = dt, 0
         rec = dict(newton=0, lin=0, inner=0, cuts=0)
+        wells0 = self.ctx.isc_well_state() if self.ctx.ncw else None
         while True:
             ok = False
             nit = 0
+            if wells0 is not None:
+                self.ctx.isc_well_controls(u)
             for nit in range(self.max_newton + 1):
                 st, info = self.ctx.isc_newton_step(u, u_old, dts, self.tol, self.lin)
                 rec["lin"] += info.lin.iters
@@ -348,6 +395,8 @@ class Simulator:
                 rec.update(cuts=cuts, dt=dts)
                 return rec
             u.copy_(u_old)
+            if wells0 is not None:
+                self.ctx.isc_set_well_state(*wells0)
             cuts += 1
             dts *= 0.5
             if cuts > 4:

@@ -1,0 +1,168 @@
+"""Controlled wells on the GPU (libisc through its C-ABI) against the oracle:
+bottom-hole pressure unknowns with BHP / phase-rate / total-rate control and
+switching to the BHP limit (well-modelling subsection of Section 2.2).
+
+Tolerances (stated per check):
+  well line        bhp after isc_well_solve <= 1e-12 relative; on_limit equal
+  well rows        D <= 1e-10 relative; B, C per perforation row <= 1e-9 of
+                   the row's largest entry (products of property values that
+                   agree to about 1e-13); R of a rate row <= 1e-9 of the
+                   target (it is the rounding left by the well-line root)
+  Newton runs      states within 1e-9 of the oracle's per step (scaled by
+                   max(|u|, floor) per unknown), bhp within 1e-9 relative,
+                   the same switches and step sizes
+  BHP control      a kind 3 producer under BHP control runs bitwise like the
+                   kind 1 fixed-BHP producer (the well row is then bhp =
+                   target, and its elimination adds exact zeros)
+"""
+import copy
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1811_11992_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FLOOR = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 5000.0])
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _cw(dims="8x6x4", prod=None, inj=None):
+    wl = I.make_workload("CW:" + dims)
+    if prod:
+        wl.wells[1].update(prod)
+    if inj:
+        wl.wells[0].update(inj)
+    return wl
+
+
+def _ctx(wl, **kw):
+    from paper_1811_11992_amd import isc
+    return isc.Context(wl, **kw)
+
+
+@pytest.mark.parametrize("ctrl", [I.CTRL_TOTAL, I.CTRL_OIL, I.CTRL_GAS])
+@pytest.mark.parametrize("dims", ["5x4x3", "8x6x4"])
+def test_well_line_and_rows_match_oracle(dims, ctrl):
+    q = I.make_workload("CW:" + dims).wells[0]["target"]
+    wl = _cw(dims, prod=dict(control=ctrl, target=0.05 * q))
+    m = O.Model(wl)
+    st, u, _, _ = m.run(wl.u0.copy(), wl.dt, 2)
+    assert st == 2
+    uo = u.copy()
+    bhp, on = m.well_state()
+    c = _ctx(wl)
+    assert (c.ncw, c.ncp) == (2, 2 * wl.nz)
+    # from a perturbed bhp, both solve the well equations alone
+    start = bhp * np.array([1.002, 0.997])
+    m.set_well_state(start, on)
+    c.isc_set_well_state(start, on)
+    ud = dev(u)
+    ns_o = m.well_solve(u)
+    ns_g = c.isc_well_solve(ud)
+    bo, oo = m.well_state()
+    bg, og = c.isc_well_state()
+    assert ns_o == ns_g and np.array_equal(oo, og)
+    assert np.all(np.abs(bg - bo) <= 1e-12 * np.abs(bo)), (bg, bo)
+    # the well rows at the same state (the oracle's bhp on both)
+    c.isc_set_well_state(bo, oo)
+    R, D, B, C = c.isc_well_border(ud, dev(uo), wl.dt)
+    Ro, Do, Bo, Co = m.well_border(u)
+    assert np.all(np.abs(D - Do) <= 1e-10 * np.abs(Do))
+    for k in range(c.ncp):
+        for got, ref in ((host(B)[k], Bo[k]), (host(C)[k], Co[k])):
+            assert np.all(np.abs(got - ref) <= 1e-9 * np.abs(ref).max() + 1e-300), (k, got, ref)
+    for w, wd in enumerate(wl.wells):
+        assert abs(R[w] - Ro[w]) <= 1e-9 * wd["target"]
+
+
+def _run_pair(wl, nsteps, lin=None, **ctx_kw):
+    """nsteps implicit steps on the oracle and on the GPU, one step at a
+    time (each with its control check, Newton and step cuts); returns the
+    per-step states, well states and records of both."""
+    from paper_1811_11992_amd import isc
+    m = O.Model(wl)
+    c = _ctx(wl, **ctx_kw)
+    sim = isc.Simulator(c, tol=1e-10, lin=lin)
+    uo = wl.u0.copy()
+    ug = dev(wl.u0)
+    out = []
+    for s in range(nsteps):
+        st, uo, recs, _ = m.run(uo, wl.dt, 1)
+        assert st == 1, s
+        rec = sim.step(ug, wl.dt)
+        out.append((uo.copy(), m.well_state(), recs[0], host(ug), c.isc_well_state(), rec))
+    return out
+
+
+def _check_pair(out):
+    for s, (uo, (bo, oo), ro, ug, (bg, og), rg) in enumerate(out):
+        assert rg["cuts"] == ro["cuts"] and rg["dt"] == ro["dt"], (s, rg, ro)
+        assert np.array_equal(oo, og), (s, oo, og)
+        rel = np.abs(ug - uo).max(axis=1) / np.maximum(np.abs(uo).max(axis=1), FLOOR)
+        assert np.all(rel <= 1e-9), (s, rel)
+        assert np.all(np.abs(bg - bo) <= 1e-9 * np.abs(bo)), (s, bg, bo)
+
+
+@pytest.mark.parametrize("ctrl", [I.CTRL_TOTAL, I.CTRL_OIL, I.CTRL_WATER, I.CTRL_LIQUID])
+def test_rate_controlled_run_matches_oracle(ctrl):
+    _check_pair(_run_pair(_cw(prod=dict(control=ctrl)), 3))
+
+
+def test_limits_and_switching_match_oracle():
+    """A producer whose rate its limit cannot deliver and an injector held
+    at its maximum BHP: both end on their limits on both sides."""
+    wl = _cw(prod=dict(target=50.0, limit=0.97 * I.P0), inj=dict(target=20.0, limit=I.P0 + 2.0e5))
+    out = _run_pair(wl, 3)
+    _check_pair(out)
+    assert out[-1][4][1].tolist() == [1, 1]
+
+
+@pytest.mark.parametrize("mode", ["mixed", "cpr"])
+def test_other_solvers_take_the_well_rows(mode):
+    """The flexible GMRES paths (FP32 inner solver; CPR) apply the same
+    reduced operator: the same roots."""
+    from paper_1811_11992_amd import isc
+    wl = _cw()
+    if mode == "mixed":
+        lin = isc.solve_opts(precision=isc.ISC_MIXED, inner_iters=12)
+        out = _run_pair(wl, 2, lin=lin, inner_iters=12)
+    else:
+        out = _run_pair(wl, 2, lin=isc.cpr_opts(p_iters=6), cpr_p_iters=6)
+    _check_pair(out)
+
+
+def test_bhp_control_runs_bitwise_like_the_fixed_bhp_producer():
+    from paper_1811_11992_amd import isc
+    wl = I.make_workload("C1")
+    wl2 = copy.deepcopy(wl)
+    wl2.wells[1] = dict(kind=I.WELL_PRODUCER, cells=wl.wells[1]["cells"], target=I.P0, control=I.CTRL_BHP)
+    u1, r1, _ = isc.Simulator(_ctx(wl)).run(dev(wl.u0), wl.dt, 3)
+    c2 = _ctx(wl2)
+    u2, r2, _ = isc.Simulator(c2).run(dev(wl.u0), wl.dt, 3)
+    assert [r["newton"] for r in r1] == [r["newton"] for r in r2]
+    assert torch.equal(u1, u2)
+    assert c2.isc_well_state()[0][0] == I.P0
+
+
+def test_adjoint_refuses_controlled_wells():
+    from paper_1811_11992_amd import isc
+    wl = _cw("4x3x2")
+    c = _ctx(wl)
+    u = dev(wl.u0)
+    lam = torch.zeros((c.n, 8), dtype=torch.float64, device="cuda")
+    g = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(isc.IscError) as e:
+        c.isc_adjoint(u, u, wl.dt, None, wl.dt, lam, g, [0.0] * 4)
+    assert e.value.status == isc.ISC_ERR_ARG
