@@ -249,8 +249,7 @@ def adjoint_cost(name="C4", nsteps=20, every=5):
     lnA = log_frequency_factors(fl).requires_grad_(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    J = OilProduction.apply(logk, lnA, ctx, u0, dt, nsteps, every, 1e-10, progress,
-                            isc.cpr_opts(p_iters=p_iters))
+    J = OilProduction.apply(logk, lnA, ctx, u0, wl.dt, nsteps, every)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     J.backward()

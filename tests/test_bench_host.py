@@ -27,3 +27,54 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in r.stdout + r.stderr
+
+
+def _unbound_names(path):
+    """Names a function of the module reads that nothing binds: not its
+    parameters or locals (nor an enclosing function's), not a module-level
+    name, not a builtin -- what would raise NameError only when the benchmark
+    reaches that line on the GPU."""
+    import ast
+    import builtins
+    tree = ast.parse(open(path).read())
+    module = set(dir(builtins))
+    for node in tree.body:
+        if isinstance(node, (ast.FunctionDef, ast.ClassDef)):
+            module.add(node.name)
+        elif isinstance(node, (ast.Import, ast.ImportFrom)):
+            module.update((a.asname or a.name).split(".")[0] for a in node.names)
+        elif isinstance(node, (ast.Assign, ast.AnnAssign)):
+            for t in (node.targets if isinstance(node, ast.Assign) else [node.target]):
+                module.update(n.id for n in ast.walk(t) if isinstance(n, ast.Name))
+
+    def bound_in(fn):
+        names = {a.arg for a in ast.walk(fn.args) if isinstance(a, ast.arg)}
+        for n in ast.walk(fn):
+            if isinstance(n, ast.Name) and isinstance(n.ctx, (ast.Store, ast.Del)):
+                names.add(n.id)
+            elif isinstance(n, (ast.Import, ast.ImportFrom)):
+                names.update((a.asname or a.name).split(".")[0] for a in n.names)
+            elif isinstance(n, (ast.FunctionDef, ast.Lambda)) and n is not fn:
+                names.update(a.arg for a in ast.walk(n.args) if isinstance(a, ast.arg))
+                if isinstance(n, ast.FunctionDef):
+                    names.add(n.name)
+            elif isinstance(n, ast.ExceptHandler) and n.name:
+                names.add(n.name)
+            elif isinstance(n, ast.comprehension):
+                names.update(x.id for x in ast.walk(n.target) if isinstance(x, ast.Name))
+        return names
+
+    missing = []
+    for fn in (n for n in ast.walk(tree) if isinstance(n, ast.FunctionDef)):
+        ok = module | bound_in(fn)
+        for outer in (n for n in ast.walk(tree) if isinstance(n, ast.FunctionDef) and n is not fn):
+            if any(x is fn for x in ast.walk(outer)):
+                ok |= bound_in(outer)
+        for n in ast.walk(fn):
+            if isinstance(n, ast.Name) and isinstance(n.ctx, ast.Load) and n.id not in ok:
+                missing.append((fn.name, n.id, n.lineno))
+    return missing
+
+
+def test_every_name_the_benchmark_reads_is_bound():
+    assert _unbound_names(os.path.join(ROOT, "bench.py")) == []
