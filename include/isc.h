@@ -135,6 +135,7 @@ typedef struct {
 
 enum { ISC_FP64 = 0, ISC_MIXED = 1 };
 enum { ISC_PC_BILU0 = 0, ISC_PC_CPR = 1 };
+enum { ISC_KRYLOV_GMRES = 0, ISC_KRYLOV_BICGSTAB = 1 };
 typedef struct {
     int32_t restart;       /* GMRES restart length m (<= max_opts.restart) */
     int32_t max_restarts;  /* cycles before ISC_ERR_LINEAR_NOCONV */
@@ -152,6 +153,9 @@ typedef struct {
                               multigrid (0: the V-cycle alone); at most
                               max_opts.p_iters */
     double rtol;           /* stop when ||b - A x||_2 <= rtol ||b||_2 */
+    int32_t krylov;        /* ISC_KRYLOV_GMRES, or ISC_KRYLOV_BICGSTAB (ISC_FP64 with
+                              ISC_PC_BILU0 only): the BiCGSTAB of isc_solve_bicgstab
+                              with at most restart x max_restarts iterations */
 } isc_solve_opts;
 
 typedef struct {

@@ -30,6 +30,8 @@ isc_status isc_gmres_fp64(isc_ctx*, const double* A, const double* Dinv, const d
 isc_status isc_fgmres(isc_ctx*, const double* A, const double* b, double* x, const isc_solve_opts* o,
                       isc_solve_info* info);
 isc_status isc_prepare_mixed_dev(isc_ctx*, const double* A, int32_t* bad_dev);
+isc_status isc_bicgstab_run(isc_ctx*, const double* A, const double* b, double* x, int32_t max_iters, double rtol,
+                            isc_solve_info* info);
 void isc_cpr_pressure_gmres(isc_ctx*, const double* rp, double* e, int k);
 void isc_apply_spmv32_from64(isc_ctx*, const double* r, double* z, double* w);
 void isc_cpr_apply_w(isc_ctx*, const double* A, const double* u, double* z, double* w, int k);
@@ -173,6 +175,15 @@ isc_status check_ctx(const isc_ctx* ctx) { return ctx ? ISC_OK : ISC_ERR_ARG; }
 isc_status check_precond(isc_ctx* ctx, const isc_solve_opts* o, const char* who) {
     if (o->precond != ISC_PC_BILU0 && o->precond != ISC_PC_CPR) {
         ctx->err = std::string(who) + ": unknown preconditioner";
+        return ISC_ERR_ARG;
+    }
+    if (o->krylov != ISC_KRYLOV_GMRES && o->krylov != ISC_KRYLOV_BICGSTAB) {
+        ctx->err = std::string(who) + ": unknown Krylov method";
+        return ISC_ERR_ARG;
+    }
+    if (o->krylov == ISC_KRYLOV_BICGSTAB &&
+        (o->precision != ISC_FP64 || o->precond != ISC_PC_BILU0 || ctx->mmax < 6)) {
+        ctx->err = std::string(who) + ": BiCGSTAB runs in FP64 with BILU(0), on a context of max restart >= 6";
         return ISC_ERR_ARG;
     }
     if (o->precond == ISC_PC_CPR) {
@@ -788,6 +799,8 @@ isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* 
         return ISC_ERR_ARG;
     }
     TRY(check_precond(ctx, o, "isc_solve"));
+    if (o->krylov == ISC_KRYLOV_BICGSTAB)
+        return isc_solve_bicgstab(ctx, Jdec, b, x, o->restart * o->max_restarts, o->rtol, info_h);
     if (o->precond == ISC_PC_CPR) {
         TRY(isc_bilu0(ctx, Jdec, ctx->Dinv));
         TRY(reset_flags(ctx));
@@ -960,7 +973,10 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
         return ISC_ERR_ARG;
     }
     ctx->border = wells;   // the Krylov operator takes the eliminated well rows
-    if (o->lin.precision == ISC_MIXED || cpr)
+    if (o->lin.krylov == ISC_KRYLOV_BICGSTAB)
+        st = isc_bicgstab_run(ctx, ctx->J, ctx->rhs, ctx->du, o->lin.restart * o->lin.max_restarts, o->lin.rtol,
+                              &inf.lin);
+    else if (o->lin.precision == ISC_MIXED || cpr)
         st = isc_fgmres(ctx, ctx->J, ctx->rhs, ctx->du, &o->lin, &inf.lin);
     else
         st = isc_gmres_fp64(ctx, ctx->J, ctx->Dinv, ctx->rhs, ctx->du, &o->lin, &inf.lin);

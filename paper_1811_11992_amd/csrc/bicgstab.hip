@@ -11,6 +11,9 @@
 
 hipError_t isc_launch_bilu0_apply_spmv(isc_ctx*, const double*, const double*, const double*, double*, double*);
 hipError_t isc_launch_spmv(isc_ctx*, const double*, const double*, double*);
+void isc_well_apply(isc_ctx*, const double* x, double* w);   // eliminated well rows (isc_newton_step only)
+isc_status isc_bicgstab_run(isc_ctx*, const double* Jdec, const double* b, double* x, int32_t max_iters, double rtol,
+                            isc_solve_info* info_h);
 
 namespace isc {
 namespace bcg {
@@ -182,8 +185,6 @@ struct Bcg {
 
 isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b, double* x, int32_t max_iters,
                               double rtol, isc_solve_info* info_h) {
-    using namespace isc;
-    using namespace isc::bcg;
     if (!ctx) return ISC_ERR_ARG;
     if (!Jdec || !b || !x || x == b || max_iters < 1 || !(rtol > 0)) {
         ctx->err = "isc_solve_bicgstab: invalid argument (max_iters >= 1, rtol > 0, x distinct from b)";
@@ -195,7 +196,16 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
     }
     const isc_status fs = isc_bilu0(ctx, Jdec, ctx->Dinv);
     if (fs != ISC_OK) return fs;
+    return isc_bicgstab_run(ctx, Jdec, b, x, max_iters, rtol, info_h);
+}
 
+// The iteration on a factor already in ctx->Dinv (isc_solve_bicgstab, and
+// isc_newton_step with ISC_KRYLOV_BICGSTAB, where the operator also takes
+// the eliminated well rows).
+isc_status isc_bicgstab_run(isc_ctx* ctx, const double* Jdec, const double* b, double* x, int32_t max_iters,
+                            double rtol, isc_solve_info* info_h) {
+    using namespace isc;
+    using namespace isc::bcg;
     const int64_t len = (int64_t)ctx->n * NU;
     const int64_t want = (len + 255) / 256;
     Bcg B{ctx, len, (int)(want < BCG_BLOCKS ? (want > 0 ? want : 1) : BCG_BLOCKS), ctx->partial, ctx->small + 3600};
@@ -229,6 +239,7 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
     while (it < max_iters) {
         // (re)start from the true residual, the shadow vector r~ = r
         ISC_HIP(isc_launch_spmv(ctx, Jdec, x, tv));
+        isc_well_apply(ctx, x, tv);
         hipLaunchKernelGGL(bcg_restart, grid, blk, 0, ctx->stream, len, b, tv, r, rs, p, v, B.partial);
         ISC_HIP(B.read(1, h));
         const double rn0 = std::sqrt(h[0]);
@@ -246,7 +257,10 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
             if (!(std::fabs(rho) > BCG_BREAKDOWN * rn0 * rn) || !std::isfinite(rho)) { breakdown = true; break; }
             const double beta = (rho / rho_old) * (alpha / omega);
             hipLaunchKernelGGL(bcg_p, grid, blk, 0, ctx->stream, len, r, v, beta, omega, p);
+            int tk = isc_prof_begin(ctx, ISC_PROF_ILU_SPMV);
             ISC_HIP(isc_launch_bilu0_apply_spmv(ctx, Jdec, ctx->Dinv, p, ph, v));
+            isc_prof_end(ctx, tk);
+            isc_well_apply(ctx, ph, v);
             hipLaunchKernelGGL(bcg_dot2, grid, blk, 0, ctx->stream, len, rs, v, B.partial);
             ISC_HIP(B.read(2, h));
             const double rv = h[0];
@@ -265,7 +279,10 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
                 converged = true;
                 break;
             }
+            tk = isc_prof_begin(ctx, ISC_PROF_ILU_SPMV);
             ISC_HIP(isc_launch_bilu0_apply_spmv(ctx, Jdec, ctx->Dinv, r, sh, tv));
+            isc_prof_end(ctx, tk);
+            isc_well_apply(ctx, sh, tv);
             hipLaunchKernelGGL(bcg_ts, grid, blk, 0, ctx->stream, len, tv, r, B.partial);
             ISC_HIP(B.read(2, h));
             const double tt = h[1];
@@ -297,6 +314,7 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
     if (sw != ISC_OK) return sw;
     if (!done) {   // the true residual of the last iterate
         ISC_HIP(isc_launch_spmv(ctx, Jdec, x, tv));
+        isc_well_apply(ctx, x, tv);
         hipLaunchKernelGGL(bcg_restart, grid, blk, 0, ctx->stream, len, b, tv, r, rs, p, v, B.partial);
         ISC_HIP(B.read(1, h));
         inf.relres_true = std::sqrt(h[0]) / bnorm;

@@ -23,6 +23,7 @@ ISC_OK, ISC_ERR_ARG, ISC_ERR_HIP, ISC_ERR_OOM = 0, -1, -2, -3
 ISC_ERR_SINGULAR, ISC_ERR_NONFINITE, ISC_ERR_LINEAR_NOCONV, ISC_ERR_NEWTON_NOCONV = -4, -5, -6, -7
 ISC_FP64, ISC_MIXED = 0, 1
 ISC_PC_BILU0, ISC_PC_CPR = 0, 1
+ISC_KRYLOV_GMRES, ISC_KRYLOV_BICGSTAB = 0, 1
 CPR_P_ITERS = 12    # default GMRES steps of the CPR pressure solve
 
 _vp = ctypes.c_void_p
@@ -32,7 +33,7 @@ _f64 = ctypes.c_double
 
 class SolveOpts(ctypes.Structure):
     _fields_ = [("restart", _i32), ("max_restarts", _i32), ("precision", _i32), ("inner_iters", _i32),
-                ("precond", _i32), ("p_iters", _i32), ("rtol", _f64)]
+                ("precond", _i32), ("p_iters", _i32), ("rtol", _f64), ("krylov", _i32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -114,8 +115,15 @@ def _ptr(t: torch.Tensor | None):
 
 
 def solve_opts(restart=30, max_restarts=20, precision=ISC_FP64, inner_iters=0, rtol=1e-8, precond=ISC_PC_BILU0,
-               p_iters=0) -> SolveOpts:
-    return SolveOpts(restart, max_restarts, precision, inner_iters, precond, p_iters, rtol)
+               p_iters=0, krylov=None) -> SolveOpts:
+    return SolveOpts(restart, max_restarts, precision, inner_iters, precond, p_iters, rtol,
+                     ISC_KRYLOV_GMRES if krylov is None else krylov)
+
+
+def bicgstab_opts(max_iters=600, rtol=1e-8) -> SolveOpts:
+    """BiCGSTAB with BILU(0) in FP64 (at most max_iters iterations, a
+    multiple of 30)."""
+    return solve_opts(restart=30, max_restarts=max(1, max_iters // 30), rtol=rtol, krylov=ISC_KRYLOV_BICGSTAB)
 
 
 def cpr_opts(p_iters=CPR_P_ITERS, restart=30, max_restarts=20, rtol=1e-8) -> SolveOpts:

@@ -97,3 +97,54 @@ def test_bicgstab_breakdown_restarts_a_bounded_number_of_times():
     assert st == 0 and info.relres_true <= 1e-10
     r = b2 - m.spmv(Jd, _host(x))
     assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b2)
+
+
+def test_bicgstab_inside_the_newton_step_reaches_the_oracle_roots():
+    """Five implicit C1 steps with BiCGSTAB as the Krylov method of
+    isc_newton_step reach the roots of the oracle's BILU(0)-GMRES run (both
+    in parity mode), step sizes equal."""
+    from test_gpu_parity import _drive
+    from paper_1811_11992_amd import isc
+    wl = I.make_workload("C1")
+    m = O.Model(wl)
+    nsteps = 5
+
+    def o_step(u, uo, dt, tol):
+        st, v, info = m.newton_step(u, uo, dt, tol=tol)
+        u[...] = v
+        return st, bool(info.converged)
+
+    hist_o, dts_o = _drive(o_step, lambda a: np.array(a, copy=True), wl.u0, wl.dt, nsteps)
+    c = isc.Context(wl)
+    lin = isc.bicgstab_opts()
+
+    def g_step(u, uo, dt, tol):
+        st, info = c.isc_newton_step(u, uo, dt, tol=tol, lin=lin)
+        assert info.lin.iters >= 0
+        return st, bool(info.converged)
+
+    hist_g, dts_g = _drive(g_step, lambda a: _dev(a) if isinstance(a, np.ndarray) else a.clone(), wl.u0, wl.dt,
+                           nsteps)
+    assert dts_g == dts_o
+    floor = np.array([1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 5000.0])
+    for s in range(nsteps):
+        torch.cuda.synchronize()
+        ug = hist_g[s + 1].cpu().numpy()
+        rel = np.abs(ug - hist_o[s + 1]).max(axis=1) / np.maximum(np.abs(hist_o[s + 1]).max(axis=1), floor)
+        assert np.all(rel <= 1e-9), (s, rel)
+
+
+def test_isc_solve_selects_bicgstab():
+    """isc_solve with ISC_KRYLOV_BICGSTAB is isc_solve_bicgstab with
+    restart x max_restarts iterations; the other precisions and
+    preconditioners refuse it."""
+    from paper_1811_11992_amd import isc
+    wl, m, Jd, b = _system("tiny:9x17x6", 5)
+    c = isc.Context(wl)
+    x1, i1, st1 = c.isc_solve(_dev(Jd), _dev(b), isc.bicgstab_opts(rtol=1e-10))
+    x2, i2, st2 = c.isc_solve_bicgstab(_dev(Jd), _dev(b), max_iters=600, rtol=1e-10)
+    assert st1 == 0 and st2 == 0 and i1.iters == i2.iters
+    assert torch.equal(x1, x2)
+    bad = isc.solve_opts(precision=isc.ISC_MIXED, inner_iters=4, krylov=isc.ISC_KRYLOV_BICGSTAB)
+    _, _, st3 = c.isc_solve(_dev(Jd), _dev(b), bad, check=False)
+    assert st3 == isc.ISC_ERR_ARG

@@ -129,17 +129,19 @@ def test_limits_and_switching_match_oracle():
     assert out[-1][4][1].tolist() == [1, 1]
 
 
-@pytest.mark.parametrize("mode", ["mixed", "cpr"])
+@pytest.mark.parametrize("mode", ["mixed", "cpr", "bicgstab"])
 def test_other_solvers_take_the_well_rows(mode):
-    """The flexible GMRES paths (FP32 inner solver; CPR) apply the same
-    reduced operator: the same roots."""
+    """The flexible GMRES paths (FP32 inner solver; CPR) and BiCGSTAB apply
+    the same reduced operator: the same roots."""
     from paper_1811_11992_amd import isc
     wl = _cw()
     if mode == "mixed":
         lin = isc.solve_opts(precision=isc.ISC_MIXED, inner_iters=12)
         out = _run_pair(wl, 2, lin=lin, inner_iters=12)
-    else:
+    elif mode == "cpr":
         out = _run_pair(wl, 2, lin=isc.cpr_opts(p_iters=6), cpr_p_iters=6)
+    else:
+        out = _run_pair(wl, 2, lin=isc.bicgstab_opts())
     _check_pair(out)
 
 
