@@ -172,25 +172,32 @@ def test_well_rows_are_the_derivatives(ctrl):
         p0 += len(cells)
 
 
-def test_schur_elimination_solves_the_bordered_system():
+@pytest.mark.parametrize("case", ["rates", "bhp_off_target"])
+def test_schur_elimination_solves_the_bordered_system(case):
     """One Newton iteration near a root: the oracle's update of (u, bhp)
     equals the dense solution of [J B; C D] [du; dbhp] = -[F; R] (no step
-    limit active)."""
+    limit active).  "rates": both wells on a rate, the targets moved a little
+    (R ~ 0 after the well-line solve); "bhp_off_target": the producer under
+    BHP control with its bhp 2% of P0 away from the target, so that R != 0."""
     wl = _cw("4x3x2")
     m = _model(wl)
     u, _, _ = _run(m, wl, 2)
     uo = u.copy()
-    # move the targets a little so that the step's root moves
     bhp, on = m.well_state()
     wl2 = copy.deepcopy(wl)
     wl2.wells[0]["target"] *= 1.02
-    wl2.wells[1]["target"] *= 0.98
+    if case == "rates":
+        wl2.wells[1]["target"] *= 0.98
+    else:
+        wl2.wells[1].update(control=I.CTRL_BHP, target=float(bhp[1]) + 0.02 * I.P0)
     m3 = _model(wl2)
     m3.set_well_state(bhp, on)
     m3.well_solve(u)                 # what the Newton iteration does first
     bhp = m3.well_state()[0]
     F, Jb = m3.assemble(u, uo, wl.dt)
     R, Dd, B, C = m3.well_border(u)
+    if case == "bhp_off_target":
+        assert abs(R[1] + 0.02 * I.P0) <= 1e-6 and Dd[1] == 1.0 and not C[wl.nz:].any()
     n = m3.n
     Jd = np.zeros((8 * n, 8 * n))
     for i in range(n):
@@ -264,3 +271,51 @@ def test_adjoint_refuses_controlled_wells():
     g_A = np.zeros(4)
     st, _ = m.adjoint_step(wl.u0, wl.u0, wl.dt, None, wl.dt, g_logk, g_A)
     assert st == -2
+
+
+def test_switching_thresholds():
+    """Held at its limit, a well returns to its rate exactly when the limit
+    would move more than the target: a target 1% above what the limit
+    delivers keeps it there, 1% below sends it back."""
+    wl = _cw(prod=dict(target=50.0, limit=0.97 * I.P0))
+    m = _model(wl)
+    u, _, _ = _run(m, wl, 2)
+    bhp, on = m.well_state()
+    assert on[1] == 1
+    q = -_phase_rates(m, u, wl.wells)[1].sum()
+    for factor, back in ((1.01, 0), (0.99, 1)):
+        wl3 = copy.deepcopy(wl)
+        wl3.wells[1]["target"] = factor * q
+        m3 = _model(wl3)
+        m3.set_well_state(bhp, on)
+        assert m3.well_controls(u) == back
+        assert m3.well_state()[1][1] == 1 - back
+
+
+def test_well_rows_count_in_the_convergence_test():
+    """The scaled residual of the well rows, by hand: a rate row by
+    V phi rho_ref,W / dt of its first perforated cell, a BHP row by the
+    pressure held; a converged state whose BHP well is off its target is
+    not converged, by exactly that amount."""
+    wl = _cw("4x3x2", prod=dict(control=I.CTRL_BHP, target=0.95 * I.P0))
+    m = _model(wl)
+    u, _, hist = _run(m, wl, 1)
+    uo = hist[0]
+    V = wl.dx * wl.dy * wl.dz
+    fl = I.physics_card()
+    s_rate = V * wl.poro[wl.wells[0]["cells"][0]] * fl.rho_ref[0] / wl.dt
+    assert m.well_scaled_norm([3.0 * s_rate, 0.0], wl.dt) == pytest.approx(3.0, rel=1e-14)
+    assert m.well_scaled_norm([0.0, -0.01 * 0.95 * I.P0], wl.dt) == pytest.approx(0.01, rel=1e-14)
+    bhp, on = m.well_state()
+    st, _, info = m.newton_step(u, uo, wl.dt)   # the step's root
+    assert st == 0 and info.converged
+    # the same state against a BHP target moved by 1e-8: the cells still
+    # balance, the well row alone is off
+    wl2 = copy.deepcopy(wl)
+    wl2.wells[1]["target"] = 0.95 * I.P0 * (1 + 1e-8)
+    m2 = _model(wl2)
+    m2.set_well_state(bhp, on)
+    assert m2.scaled_norm(m2.residual(u, uo, wl.dt), wl.dt) <= 1e-10
+    st, _, info = m2.newton_step(u, uo, wl.dt)
+    assert st == 0 and not info.converged
+    assert info.res_scaled == pytest.approx(1e-8, rel=1e-6)
