@@ -45,8 +45,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--reps", type=int, default=20)
-    ap.add_argument("--only", choices=("linear", "assemble"), default="linear",
-                    help="time the linear-algebra kernels (default) or the assembly alone")
+    ap.add_argument("--only", choices=("linear", "assemble", "factor"), default="linear",
+                    help="time the linear-algebra kernels (default), the assembly alone, or the BILU(0) factor")
     a = ap.parse_args(argv)
     wl = I.make_workload(a.workload)
     c = isc.Context(wl)
@@ -59,6 +59,22 @@ def main(argv=None):
     F, J = c.isc_assemble(u, u, wl.dt)
     c.isc_decouple(J, F)
     D = c.isc_bilu0(J)
+    if a.only == "factor":
+        # the factor of the first Newton iteration's decoupled matrix, again and again
+        for _ in range(2):
+            c.isc_bilu0(J, D)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.reps):
+            c.isc_bilu0(J, D)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / a.reps * 1e3
+        print(json.dumps({"workload": wl.name, "cells": c.n, "reps": a.reps, "bilu0_factor_ms": round(ms, 4),
+                          "dinv_finite": bool(torch.isfinite(D).all()),
+                          "dinv_sum": float(D.double().abs().sum())}), flush=True)
+        c.close()
+        torch.cuda.synchronize()
+        return
     g = torch.Generator(device="cuda").manual_seed(1)
     r = torch.randn((c.n, 8), dtype=torch.float64, device="cuda", generator=g)
     z = torch.empty_like(r)
