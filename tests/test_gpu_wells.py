@@ -168,3 +168,13 @@ def test_adjoint_refuses_controlled_wells():
     with pytest.raises(isc.IscError) as e:
         c.isc_adjoint(u, u, wl.dt, None, wl.dt, lam, g, [0.0] * 4)
     assert e.value.status == isc.ISC_ERR_ARG
+
+
+@pytest.mark.parametrize("bad", [dict(control=9), dict(control=I.CTRL_BHP, target=-1.0),
+                                 dict(target=-1.0), dict(limit=float("nan")), dict(kind=5)])
+def test_invalid_controlled_wells_are_refused(bad):
+    from paper_1811_11992_amd import isc
+    wl = _cw("4x3x2", prod=bad)
+    with pytest.raises(isc.IscError) as e:
+        _ctx(wl)
+    assert e.value.status == isc.ISC_ERR_ARG
