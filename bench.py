@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the other precision and the adjoint-cost legs")
     ap.add_argument("--cpu-layers", type=int, default=4, help="layers of the workload in the oracle sample")
+    ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="concurrent oracle processes of the all-core CPU figure (0 or 1: none)")
+    ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     return ap.parse_args()
 
 
@@ -172,9 +175,11 @@ def host_cpu():
     return {"cpu_model": model, "host_logical_cpus": os.cpu_count()}
 
 
-def cpu_baseline(wl, layers):
-    """The oracle, as it stands, on a bounded sample of the workload: one
-    Newton iteration on its top `layers` layers."""
+def cpu_sample(wl, layers, start_at=None):
+    """One Newton iteration of the oracle, as it stands, on the top `layers`
+    layers of the workload: (cells, seconds, GMRES iterations, status, start
+    and end wall-clock times).  With start_at, the iteration starts at that
+    wall-clock time (so that concurrent samples overlap)."""
     import oracle as O
     from paper_1811_11992_amd import inputs as I
     nxy = wl.nx * wl.ny
@@ -185,14 +190,47 @@ def cpu_baseline(wl, layers):
                      u0=wl.u0[:, :n].copy(), dt=wl.dt, nsteps=1, seed=wl.seed)
     sub.wells = [w for w in sub.wells if w["cells"]]
     m = O.Model(sub)
+    if start_at is not None:
+        time.sleep(max(0.0, start_at - time.time()))
+    w0 = time.time()
     t0 = time.perf_counter()
     st, u, info = m.newton_step(sub.u0, sub.u0, sub.dt)
     el = time.perf_counter() - t0
-    return {"value": n / el, "unit": UNIT, "cores": 1, "kind": "oracle", **host_cpu(),
-            "sample": f"one Newton iteration (assemble, decouple, BILU(0)-GMRES(30) to 1e-8, update) of the "
-                      f"serial FP64 oracle on the top {layers} layers of {wl.name} ({n} cells), first step "
-                      f"from the initial state; {info.iters_lin} GMRES iterations, {el:.1f} s",
-            "status": int(st)}
+    return n, el, int(info.iters_lin), int(st), w0, time.time()
+
+
+def cpu_baseline(wl, layers, workers=0):
+    """The oracle, as it stands, on a bounded sample of the workload (one
+    Newton iteration on its top `layers` layers), in this process (one core);
+    with workers > 1 also the same sample in that many concurrent
+    single-threaded processes, for the throughput of all the host's cores."""
+    n, el, its, st, _, _ = cpu_sample(wl, layers)
+    out = {"value": n / el, "unit": UNIT, "cores": 1, "kind": "oracle", **host_cpu(),
+           "sample": f"one Newton iteration (assemble, decouple, BILU(0)-GMRES(30) to 1e-8, update) of the "
+                     f"serial FP64 oracle on the top {layers} layers of {wl.name} ({n} cells), first step "
+                     f"from the initial state; {its} GMRES iterations, {el:.1f} s",
+           "status": st}
+    if workers > 1:
+        import subprocess
+        start_at = time.time() + 20.0
+        cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", str(start_at), "--workload", wl.name,
+               "--cpu-layers", str(layers)]
+        procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True)
+                 for _ in range(workers)]
+        recs = []
+        for p in procs:
+            o, _ = p.communicate(timeout=600)
+            line = [x for x in o.splitlines() if x.startswith("{")]
+            if p.returncode == 0 and line:
+                recs.append(json.loads(line[-1]))
+        if len(recs) == workers:
+            span = max(r["end"] for r in recs) - min(r["start"] for r in recs)
+            out["all_cores"] = {"value": sum(r["cells"] for r in recs) / span, "unit": UNIT, "cores": workers,
+                                "wall_s": round(span, 2),
+                                "sample": f"the same sample in {workers} concurrent single-threaded processes, "
+                                          f"started together; cells of all of them over the span from the first "
+                                          f"start to the last end"}
+    return out
 
 
 def run_newton(wl, precision, inner, warmup, steps, precond="bilu0", p_iters=8, krylov="gmres"):
@@ -424,6 +462,12 @@ def classes_of(prof, nbytes):
 
 def main():
     a = parse()
+    if a.cpu_worker is not None:   # one process of the all-core CPU figure (no GPU)
+        from paper_1811_11992_amd import inputs as I
+        n, el, its, st, w0, w1 = cpu_sample(I.make_workload(a.workload), a.cpu_layers, a.cpu_worker)
+        print(json.dumps({"cells": n, "seconds": el, "gmres": its, "status": st, "start": w0, "end": w1}),
+              flush=True)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only: the hot path is built and measured on a single MI355X "
               f"(how it would shard is described in the design notes); got --gpus {a.gpus}", file=sys.stderr)
@@ -487,7 +531,7 @@ def main():
             "bicgstab_over_gmres_fp64": v4 / (v2 if mixed else value),
         }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_layers)
+        out["cpu_baseline"] = cpu_baseline(wl, a.cpu_layers, a.cpu_workers)
     print(json.dumps(out), flush=True)
     # every context is destroyed by now; let the device drain before the
     # interpreter's own teardown

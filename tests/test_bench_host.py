@@ -37,7 +37,7 @@ def _unbound_names(path):
     import ast
     import builtins
     tree = ast.parse(open(path).read())
-    module = set(dir(builtins))
+    module = set(dir(builtins)) | {"__file__", "__name__", "__doc__", "__spec__", "__package__"}
     for node in tree.body:
         if isinstance(node, (ast.FunctionDef, ast.ClassDef)):
             module.add(node.name)
