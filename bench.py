@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--cpu-workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="concurrent oracle processes of the all-core CPU figure (0 or 1: none)")
     ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--reference-copy", type=int, default=0, metavar="MB",
+                    help="first copy MB megabytes device to device ten times: the kernel of known bytes that "
+                         "scales the HBM counters of a profiled run")
     return ap.parse_args()
 
 
@@ -474,6 +477,14 @@ def main():
         sys.exit(2)
     from paper_1811_11992_amd import inputs as I
 
+    if a.reference_copy > 0:
+        import torch
+        src = torch.ones(a.reference_copy * 1_000_000 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = I.make_workload(a.workload)
     n = wl.ncell
     if a.precond == "cpr" and a.precision != "fp64":
