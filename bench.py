@@ -463,6 +463,11 @@ def classes_of(prof, nbytes):
     return out
 
 
+def note(msg):
+    """A progress line on stderr (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     if a.cpu_worker is not None:   # one process of the all-core CPU figure (no GPU)
@@ -493,6 +498,7 @@ def main():
     if a.krylov == "bicgstab" and (a.precision != "fp64" or a.precond != "bilu0"):
         print("BiCGSTAB runs in FP64 with BILU(0) only", file=sys.stderr)
         sys.exit(2)
+    note(f"{wl.name}: {a.precision} {a.precond} {a.krylov}, {a.warmup} + {a.steps} Newton iterations")
     value, el, stats, prof, vec = run_newton(wl, a.precision, a.inner, a.warmup, a.steps, a.precond, a.p_iters,
                                              a.krylov)
     base_bytes = algorithmic_bytes(n, stats["nnzb"])
@@ -515,6 +521,7 @@ def main():
     }
     if not a.no_forms and a.precond == "bilu0" and a.krylov == "gmres":
         other = "fp64" if mixed else "mixed"
+        note(f"{wl.name}: the {other} form")
         v2, el2, st2, prof2, vec2 = run_newton(wl, other, a.inner, a.warmup, a.steps)
         nbytes2 = launch_bytes(base_bytes, prof2, vec2, n)
         out["precision_forms"] = {
@@ -523,7 +530,9 @@ def main():
                     "roofline": roofline(prof2, nbytes2, wl.name), "kernel_classes": classes_of(prof2, nbytes2)},
             "mixed_over_fp64": (v2 / value) if not mixed else (value / v2),
         }
+        note("C4: adjoint cost")
         out["adjoint"] = adjoint_cost()
+        note(f"{wl.name}: CPR")
         v3, el3, st3, prof3, vec3 = run_newton(wl, "fp64", a.inner, a.warmup, a.steps, "cpr", a.p_iters)
         nbytes3 = launch_bytes(base_bytes, prof3, vec3, n)
         out["preconditioners"] = {
@@ -532,6 +541,7 @@ def main():
                     "roofline": roofline(prof3, nbytes3, wl.name), "kernel_classes": classes_of(prof3, nbytes3)},
             "cpr_over_bilu0_fp64": v3 / (v2 if mixed else value),
         }
+        note(f"{wl.name}: BiCGSTAB")
         v4, el4, st4, prof4, vec4 = run_newton(wl, "fp64", a.inner, a.warmup, a.steps, krylov="bicgstab")
         nbytes4 = launch_bytes(base_bytes, prof4, vec4, n)
         out["krylov_methods"] = {
@@ -542,6 +552,7 @@ def main():
             "bicgstab_over_gmres_fp64": v4 / (v2 if mixed else value),
         }
     if not a.no_cpu_baseline:
+        note("CPU baseline (the oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, a.cpu_layers, a.cpu_workers)
     print(json.dumps(out), flush=True)
     # every context is destroyed by now; let the device drain before the
