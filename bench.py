@@ -463,6 +463,25 @@ def classes_of(prof, nbytes):
     return out
 
 
+def copy_peak_gbs(nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth on this GPU: a plain device-to-device copy of
+    nbytes (read + written), the best of reps, timed with events."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    return 2 * nbytes / (best * 1e-3) / 1e9
+
+
 def note(msg):
     """A progress line on stderr (the JSON line stays alone on stdout)."""
     print(f"bench: {msg}", file=sys.stderr, flush=True)
@@ -499,6 +518,7 @@ def main():
         print("BiCGSTAB runs in FP64 with BILU(0) only", file=sys.stderr)
         sys.exit(2)
     note(f"{wl.name}: {a.precision} {a.precond} {a.krylov}, {a.warmup} + {a.steps} Newton iterations")
+    copy_gbs = copy_peak_gbs()
     value, el, stats, prof, vec = run_newton(wl, a.precision, a.inner, a.warmup, a.steps, a.precond, a.p_iters,
                                              a.krylov)
     base_bytes = algorithmic_bytes(n, stats["nnzb"])
@@ -519,6 +539,9 @@ def main():
         "roofline": roofline(prof, nbytes, wl.name),
         "kernel_classes": classes_of(prof, nbytes),
     }
+    # the same achieved rate against what a plain copy reaches on this GPU
+    out["roofline"]["copy_GB_s_measured"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_copy"] = round(out["roofline"]["achieved"] / copy_gbs, 4)
     if not a.no_forms and a.precond == "bilu0" and a.krylov == "gmres":
         other = "fp64" if mixed else "mixed"
         note(f"{wl.name}: the {other} form")

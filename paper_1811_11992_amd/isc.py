@@ -418,3 +418,12 @@ class Simulator:
             if history:
                 hist.append(u.clone())
         return u, recs, hist
+
+
+def __getattr__(name):
+    """isc.OilProduction: the differentiation form (adjoint.py), imported on
+    first use."""
+    if name == "OilProduction":
+        from .adjoint import OilProduction
+        return OilProduction
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")
