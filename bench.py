@@ -345,6 +345,42 @@ def bicgstab_cost(name="C3", reps=2):
     return out
 
 
+def precision_steps(name="C3", nsteps=10, inner=12):
+    """The precision form against FP64, step by step: `nsteps` implicit steps
+    of the workload run twice from the same initial state, by FP64
+    BILU(0)-GMRES(30) and by the precision form (FP32 inner GMRES, m_in =
+    inner), each with the time loop's step cuts; per step the largest
+    relative state difference (per unknown, scaled by max(|u|, floor)), both
+    runs' Newton iterations and step sizes.  Not part of the default run; call
+    it as bench.precision_steps()."""
+    import torch
+    from paper_1811_11992_amd import inputs as I
+    from paper_1811_11992_amd import isc
+    wl = I.make_workload(name)
+    ctx = isc.Context(wl, restart=30, inner_iters=inner)
+    lins = {"fp64": isc.solve_opts(rtol=1e-8),
+            "mixed": isc.solve_opts(rtol=1e-8, precision=isc.ISC_MIXED, inner_iters=inner)}
+    sims = {k: isc.Simulator(ctx, tol=1e-10, lin=v) for k, v in lins.items()}
+    states = {k: torch.tensor(wl.u0, dtype=torch.float64, device="cuda") for k in lins}
+    floor = torch.tensor([1.0, 1, 1, 1, 1, 1, 1, 5000.0], dtype=torch.float64, device="cuda")
+    steps = []
+    for s in range(nsteps):
+        rec = {}
+        for k in lins:
+            r = sims[k].step(states[k], wl.dt)
+            rec[k] = {"newton": r["newton"], "dt": r["dt"], "cuts": r["cuts"]}
+        d = (states["mixed"] - states["fp64"]).abs().amax(dim=1)
+        scale = torch.maximum(states["fp64"].abs().amax(dim=1), floor)
+        rec["state_rel_diff"] = float((d / scale).max())
+        steps.append(rec)
+        note(f"{name} step {s + 1}: {rec}")
+    ctx.close()
+    del ctx
+    gc.collect()
+    return {"workload": f"{name}: {wl.nx}x{wl.ny}x{wl.nz}, {nsteps} steps, FP64 vs precision form (m_in {inner})",
+            "steps": steps, "max_state_rel_diff": max(x["state_rel_diff"] for x in steps)}
+
+
 def scale_leg(name="C5", nsteps=10, every=5, inner=12, dt_days=0.0125, p_iters=12):
     """The precision and differentiation forms at the largest configured
     size: `nsteps` implicit steps of `dt_days` of the precision form (FP32
