@@ -242,8 +242,10 @@ isc_status isc_decouple(isc_ctx* ctx, double* Jval, double* F, int32_t* bad_cell
  * most 64 cells) is solved with its inverse.  Stage 2 applies block ILU(0) to
  * what the pressure correction leaves of the residual:
  *   z = E e_p + M^-1 (r - A E e_p),  e_p ~= A_p^-1 (E^T r),
- * E^T r the pressure components of r.  ISC_ERR_SINGULAR if the factor or the
- * coarsest matrix is singular. */
+ * E^T r the pressure components of r.  opts->krylov = ISC_KRYLOV_BICGSTAB
+ * (FP64, ISC_PC_BILU0) runs isc_solve_bicgstab with restart x max_restarts
+ * iterations instead.  ISC_ERR_SINGULAR if the factor or the coarsest matrix
+ * is singular. */
 isc_status isc_solve(isc_ctx* ctx, const double* Jdec, const double* b, double* x,
                      const isc_solve_opts* opts_h, isc_solve_info* info_h);
 
