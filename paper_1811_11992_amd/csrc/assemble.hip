@@ -62,7 +62,7 @@ __device__ __forceinline__ FaceOut face_eval(const double* __restrict__ Plo,
     return o;
 }
 
-__global__ void __launch_bounds__(256, 6) assemble_kernel(
+__global__ void __launch_bounds__(256, 8) assemble_kernel(
     int32_t n, int32_t nx, int32_t ny, int32_t nz, const double* __restrict__ u,
     const double* __restrict__ payload, const double* __restrict__ trans, double ah_x, double ah_y,
     double ah_z, double dz, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos,
