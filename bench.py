@@ -345,6 +345,42 @@ def bicgstab_cost(name="C3", reps=2):
     return out
 
 
+def wells_cost(name="C3", nsteps=1):
+    """The workload with its wells as controlled wells (bhp unknowns): the
+    injector column holding its air rate up to P0 + 5 MPa, the producer column
+    holding a total molar rate of half of it down to 0.8 P0; `nsteps` implicit
+    steps of FP64 BILU(0)-GMRES(30) with the time loop; ms and Krylov
+    iterations per Newton iteration and the final well state.  Not part of
+    the default run; call it as bench.wells_cost() (under a kernel trace for
+    the well kernels' share)."""
+    import torch
+    from paper_1811_11992_amd import inputs as I
+    from paper_1811_11992_amd import isc
+    wl = I.make_workload(name)
+    inj, prod = wl.wells[0], wl.wells[1]
+    wl.wells = [dict(inj, kind=I.WELL_INJECTOR, control=I.CTRL_RATE, limit=I.P0 + 5.0e6),
+                dict(kind=I.WELL_PRODUCER, cells=prod["cells"], target=0.5 * inj["target"],
+                     control=I.CTRL_TOTAL, limit=0.8 * I.P0)]
+    ctx = isc.Context(wl)
+    sim = isc.Simulator(ctx, tol=1e-10, lin=isc.solve_opts(rtol=1e-8))
+    u = torch.tensor(wl.u0, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = [sim.step(u, wl.dt) for _ in range(nsteps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    nit = sum(r["newton"] for r in recs)
+    bhp, on = ctx.isc_well_state()
+    out = {"workload": f"{name} with controlled wells, {nsteps} step(s)", "newton": nit,
+           "ms_per_newton": round(el / max(1, nit) * 1e3, 1),
+           "krylov_per_newton": round(sum(r["lin"] for r in recs) / max(1, nit), 1),
+           "cuts": sum(r["cuts"] for r in recs), "bhp": bhp.tolist(), "on_limit": on.tolist()}
+    ctx.close()
+    del ctx
+    gc.collect()
+    return out
+
+
 def precision_steps(name="C3", nsteps=10, inner=12):
     """The precision form against FP64, step by step: `nsteps` implicit steps
     of the workload run twice from the same initial state, by FP64
