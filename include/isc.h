@@ -282,9 +282,11 @@ isc_status isc_solve_bicgstab(isc_ctx* ctx, const double* Jdec, const double* b,
  * equation at the current cells (or moves it onto its BHP limit); the well
  * rows count in res (isc_well_border's scaling); they are eliminated,
  *   (J - B D^-1 C) du = -(F - B D^-1 R),  dbhp = -D^-1 (R + C du),
- * the Krylov operator being the decoupled J plus the rank-one term of each
- * well on a rate (the preconditioners see the decoupled J alone); bhp takes
- * its Newton step with the cells. */
+ * with the part of B D^-1 C that the 7-point pattern holds (a perforated
+ * cell with itself and its stencil neighbours in the same well) subtracted
+ * from J before the decoupling, so that the preconditioners see it, and the
+ * rest applied matrix-free in every Krylov product; bhp takes its Newton
+ * step with the cells. */
 isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double dt,
                            const isc_newton_opts* opts_h, isc_newton_info* info_h);
 

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -21,7 +22,8 @@ hipError_t isc_launch_update(isc_ctx*, double* u, const double* du, int32_t* fla
 hipError_t isc_launch_scaled_norm(isc_ctx*, const double* F, double dt, double* out_dev);
 hipError_t isc_launch_negate(isc_ctx*, const double* x, double* y);
 hipError_t isc_launch_well_line(isc_ctx*, const double* u, int mode);
-hipError_t isc_launch_well_rows(isc_ctx*, const double* u, const double* J);
+hipError_t isc_launch_well_rows(isc_ctx*, const double* u);
+hipError_t isc_launch_well_fold(isc_ctx*, double* J);
 hipError_t isc_launch_well_reduce(isc_ctx*, double dt);
 hipError_t isc_launch_well_rhs(isc_ctx*, double* rhs);
 hipError_t isc_launch_well_update(isc_ctx*, const double* du, int32_t* nonfinite_dev);
@@ -404,6 +406,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
             C.D = 1.0;
             ctx->cw_h.push_back(C);
             ctx->ncp += W.nperf;
+            ctx->cw_maxnp = std::max(ctx->cw_maxnp, W.nperf);
         }
         std::vector<int32_t> cells(W.perf_cells_h, W.perf_cells_h + W.nperf);
         for (int32_t c : cells)
@@ -470,6 +473,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
     ALLOC(ctx->cwp, (size_t)ctx->ncp * isc::CWP_W);
     ALLOC(ctx->cwp_cell, (size_t)ctx->ncp);
     ALLOC(ctx->cwp_well, (size_t)ctx->ncp);
+    ALLOC(ctx->cwp_nb, (size_t)ctx->ncp * isc::CW_NB * 2);
     ALLOC(ctx->wres, (size_t)1);
     ALLOC(ctx->wsw, (size_t)1);
     ALLOC(ctx->Z, nv * ctx->mmax);
@@ -609,8 +613,24 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
             ctx->cw_h[w].rscale = vol * ctx->poro_h[cells[0]] * ctx->fluid_h.rho_ref[0];
             ++w;
         }
+        // each perforation's in-pattern partners: the same well's perforations
+        // at the columns of its cell's stencil row, and those blocks of J
+        std::vector<int32_t> nb((size_t)ctx->ncp * isc::CW_NB * 2, -1);
+        std::unordered_map<int32_t, int32_t> perf_of;
+        for (int32_t p = 0; p < ctx->ncp; ++p) perf_of[ccell[p]] = p;
+        for (int32_t p = 0; p < ctx->ncp; ++p) {
+            int32_t slot = 0;
+            for (int32_t b = ctx->row_ptr_h[ccell[p]]; b < ctx->row_ptr_h[ccell[p] + 1]; ++b) {
+                const auto it = perf_of.find(ctx->col_idx_h[b]);
+                if (it == perf_of.end() || cwell[it->second] != cwell[p]) continue;
+                nb[((size_t)p * isc::CW_NB + slot) * 2] = it->second;
+                nb[((size_t)p * isc::CW_NB + slot) * 2 + 1] = b;
+                ++slot;
+            }
+        }
         if (!h2d(ctx->cwp_cell, ccell.data(), ccell.size() * sizeof(int32_t)) ||
             !h2d(ctx->cwp_well, cwell.data(), cwell.size() * sizeof(int32_t)) ||
+            !h2d(ctx->cwp_nb, nb.data(), nb.size() * sizeof(int32_t)) ||
             !h2d(ctx->cw, ctx->cw_h.data(), ctx->cw_h.size() * sizeof(isc::CWell)) ||
             hipMemsetAsync(ctx->cwp, 0, (size_t)ctx->ncp * isc::CWP_W * sizeof(double), ctx->stream) != hipSuccess) {
             ctx->err = "host to device copy failed";
@@ -641,7 +661,7 @@ isc_status isc_destroy(isc_ctx* ctx) {
                     ctx->sweep32, ctx->ticket, ctx->Lt, ctx->Lt32, ctx->items_bwd_spmv,
                     ctx->mg_store, ctx->mg_cinv, ctx->cpr_pc, ctx->cpr_V, ctx->cpr_Z, ctx->cpr_w,
                     ctx->cpr_rp, ctx->cpr_ep, ctx->cpr_w1, ctx->cpr_r2, ctx->small_p, ctx->cw, ctx->cwp,
-                    ctx->cwp_cell, ctx->cwp_well, ctx->wres, ctx->wsw};
+                    ctx->cwp_cell, ctx->cwp_well, ctx->cwp_nb, ctx->wres, ctx->wsw};
     for (void* p : ptrs)
         if (p) hipFree(p);
     if (ctx->hscratch) hipHostFree(ctx->hscratch);
@@ -910,7 +930,7 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
     ISC_HIP(isc_launch_props(ctx, u, u_old, dt));
     ISC_HIP(isc_launch_assemble(ctx, u, ctx->F, ctx->J));
     if (wells) {
-        ISC_HIP(isc_launch_well_rows(ctx, u, ctx->J));
+        ISC_HIP(isc_launch_well_rows(ctx, u));
         ISC_HIP(isc_launch_well_reduce(ctx, dt));
     }
     isc_prof_end(ctx, tk);
@@ -937,6 +957,7 @@ isc_status isc_newton_step(isc_ctx* ctx, double* u, const double* u_old, double 
     }
     TRY(reset_flags(ctx));
     tk = isc_prof_begin(ctx, ISC_PROF_DECOUPLE);
+    if (wells) ISC_HIP(isc_launch_well_fold(ctx, ctx->J));
     ISC_HIP(isc_launch_decouple(ctx, ctx->J, ctx->F, ctx->flags + FLAG_BAD));
     isc_prof_end(ctx, tk);
     ISC_HIP(isc_launch_negate(ctx, ctx->F, ctx->rhs));
@@ -1113,7 +1134,7 @@ isc_status isc_well_border(isc_ctx* ctx, const double* u, const double* u_old, d
     if (ctx->ncw == 0) return ISC_OK;
     ISC_HIP(isc_launch_props(ctx, u, u_old, dt));
     ISC_HIP(isc_launch_assemble(ctx, u, ctx->F, ctx->J));
-    ISC_HIP(isc_launch_well_rows(ctx, u, ctx->J));
+    ISC_HIP(isc_launch_well_rows(ctx, u));
     ISC_HIP(isc_launch_well_reduce(ctx, dt));
     const size_t pitch = (size_t)isc::CWP_W * sizeof(double);
     if (B) ISC_HIP(hipMemcpy2DAsync(B, 8 * sizeof(double), ctx->cwp + isc::CWP_B, pitch, 8 * sizeof(double),

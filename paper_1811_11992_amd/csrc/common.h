@@ -71,9 +71,11 @@ struct CWell {
     double rscale;            // rate rows: V phi rho_ref,W of its first perforated cell (divided by dt)
 };
 // per controlled perforation: B = dF_cell/dbhp, C = dq/du_cell, the rate q
-// and dq/dbhp it adds to its well, Bt = J_ii^-1 B
+// and dq/dbhp it adds to its well, Bt = J_ii^-1 B (J_ii after the fold of
+// the well's in-pattern couplings)
 constexpr int CWP_B = 0, CWP_C = 8, CWP_Q = 16, CWP_DQ = 17, CWP_BT = 18, CWP_W = 26;
 constexpr int CW_MAXPERF = 2048;   // perforations of one controlled well (LDS of the well-line solve)
+constexpr int CW_NB = 8;           // slots of a perforation's in-pattern partner list (stencil of 7)
 // Per-cell property payload written by the property pass and read by the
 // face-flux assembly (doubles, value followed by the 8 partial derivatives):
 //   [0, 72)     local residual terms of the 8 rows (accumulation change,
@@ -157,12 +159,15 @@ struct isc_ctx {
     // controlled wells (bhp unknowns): their perforations are listed in well
     // order; the Krylov operator of isc_newton_step subtracts the eliminated
     // well rows while `border` is set
-    int32_t ncw = 0, ncp = 0;
+    int32_t ncw = 0, ncp = 0, cw_maxnp = 0;   // wells, perforations, most perforations of one well
     std::vector<isc::CWell> cw_h;   // set-up copy (the state lives on the device)
     isc::CWell* cw = nullptr;       // [ncw]
     double* cwp = nullptr;          // [ncp][CWP_W]
     int32_t* cwp_cell = nullptr;    // [ncp] perforated cell
     int32_t* cwp_well = nullptr;    // [ncp] its well
+    int32_t* cwp_nb = nullptr;      // [ncp][CW_NB][2] the same well's perforations whose cells
+                                    // are in this cell's stencil row (itself included): the
+                                    // perforation and the block of J between them; -1 past the end
     double* wres = nullptr;         // [1] scaled residual of the well rows
     int32_t* wsw = nullptr;         // [1] wells switched by the last well-line pass
     bool border = false;

@@ -479,87 +479,54 @@ __global__ void __launch_bounds__(64) well_line_kernel(int mode, const int32_t* 
 // Eight lanes per controlled perforation (lane k carries d/du_k): the
 // perforation's entries of Newton's bordered system at the well's bhp --
 // B = dF_cell/dbhp, C = dq/du_cell with q the rate it adds to its well's
-// equation, dq/dbhp -- and Bt = J_ii^-1 B from the cell's (not yet
-// decoupled) diagonal block, by Gauss-Jordan elimination with partial
-// pivoting in LDS.
+// equation, dq/dbhp.
 __global__ void __launch_bounds__(256) well_rows_kernel(
     int32_t ncp, const int32_t* __restrict__ pcell, const int32_t* __restrict__ pwell, const double* __restrict__ u,
     int32_t n, const double* __restrict__ poro, const int32_t* __restrict__ well_slot,
     const double* __restrict__ perf, const isc_fluid* __restrict__ fl, const CWell* __restrict__ cw,
-    const double* __restrict__ J, const int32_t* __restrict__ diag_pos, double* __restrict__ cwp) {
-    __shared__ double tile[32][8][9];
+    double* __restrict__ cwp) {
     const int32_t p = (int32_t)((blockIdx.x * blockDim.x + threadIdx.x) >> 3);
     const int k = threadIdx.x & 7;
-    const int gi = threadIdx.x >> 3;
-    const bool live = p < ncp;
+    if (p >= ncp) return;
     double Bk = 0.0;
-    int32_t i = 0;
-    if (live) {
-        i = pcell[p];
-        const double* pf = perf + (size_t)well_slot[i] * PERF_W;
-        const CWell& W = cw[pwell[p]];
-        G1 ug[8];
+    const int32_t i = pcell[p];
+    const double* pf = perf + (size_t)well_slot[i] * PERF_W;
+    const CWell& W = cw[pwell[p]];
+    G1 ug[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ug[q] = G1{u[(size_t)q * n + i], q == k ? 1.0 : 0.0};
-        Cell<G1> c;
-        cell_eval<G1>(*fl, poro[i], ug, c);
-        const double wi = pf[1];
-        G1 q = G1{0.0, 0.0};
-        double dq = 0.0;
-        if (W.kind == ISC_WELL_PRODUCER) {
-            if (ug[0].v > W.bhp) {
-                const G1 dp = W.bhp - ug[0];
-                if (W.control & ISC_CTRL_WATER) { q = q - (wi * c.mob_w) * dp; dq -= wi * c.mob_w.v; }
-                if (W.control & ISC_CTRL_OIL) { q = q - (wi * c.mob_o) * dp; dq -= wi * c.mob_o.v; }
-                if (W.control & ISC_CTRL_GAS) { q = q - (wi * c.mob_g) * dp; dq -= wi * c.mob_g.v; }
-                if (k < 7) {
-                    double t = 0.0;
+    for (int q = 0; q < 8; ++q) ug[q] = G1{u[(size_t)q * n + i], q == k ? 1.0 : 0.0};
+    Cell<G1> c;
+    cell_eval<G1>(*fl, poro[i], ug, c);
+    const double wi = pf[1];
+    G1 q = G1{0.0, 0.0};
+    double dq = 0.0;
+    if (W.kind == ISC_WELL_PRODUCER) {
+        if (ug[0].v > W.bhp) {
+            const G1 dp = W.bhp - ug[0];
+            if (W.control & ISC_CTRL_WATER) { q = q - (wi * c.mob_w) * dp; dq -= wi * c.mob_w.v; }
+            if (W.control & ISC_CTRL_OIL) { q = q - (wi * c.mob_o) * dp; dq -= wi * c.mob_o.v; }
+            if (W.control & ISC_CTRL_GAS) { q = q - (wi * c.mob_g) * dp; dq -= wi * c.mob_g.v; }
+            if (k < 7) {
+                double t = 0.0;
 #pragma unroll
-                    for (int a = 0; a < 3; ++a)
-                        if (mob_slot(a, k) >= 0) t += c.mx[mob_slot(a, k)].v;
-                    Bk = -wi * t;
-                }
+                for (int a = 0; a < 3; ++a)
+                    if (mob_slot(a, k) >= 0) t += c.mx[mob_slot(a, k)].v;
+                Bk = -wi * t;
             }
-        } else if (W.bhp > ug[0].v) {
-            const G1 lt = (c.mob_w + c.mob_o) + c.mob_g;
-            q = (wi * lt) * (W.bhp - ug[0]);
-            dq = wi * lt.v;
-            Bk = k < 6 ? -dq * pf[3 + k] : k == 6 ? -dq * pf[10] : 0.0;
         }
-        double* o = cwp + (size_t)p * CWP_W;
-        o[CWP_B + k] = Bk;
-        o[CWP_C + k] = q.d;
-        if (k == 0) {
-            o[CWP_Q] = q.v;
-            o[CWP_DQ] = dq;
-        }
-        const double* Jd = J + (size_t)diag_pos[i] * 64;
-#pragma unroll
-        for (int c2 = 0; c2 < 8; ++c2) tile[gi][k][c2] = Jd[k * 8 + c2];
-        tile[gi][k][8] = Bk;
-    }
-    __syncthreads();
-    if (!live || k != 0) return;
-    double (*a)[9] = tile[gi];
-    bool ok = true;
-    for (int col = 0; col < 8 && ok; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < 8; ++r)
-            if (fabs(a[r][col]) > fabs(a[piv][col])) piv = r;
-        if (!(fabs(a[piv][col]) > 0.0)) { ok = false; break; }
-        if (piv != col)
-            for (int c2 = 0; c2 < 9; ++c2) { const double t = a[col][c2]; a[col][c2] = a[piv][c2]; a[piv][c2] = t; }
-        const double d = a[col][col];
-        for (int c2 = col; c2 < 9; ++c2) a[col][c2] /= d;
-        for (int r = 0; r < 8; ++r) {
-            if (r == col) continue;
-            const double f = a[r][col];
-            if (f == 0.0) continue;
-            for (int c2 = col; c2 < 9; ++c2) a[r][c2] -= f * a[col][c2];
-        }
+    } else if (W.bhp > ug[0].v) {
+        const G1 lt = (c.mob_w + c.mob_o) + c.mob_g;
+        q = (wi * lt) * (W.bhp - ug[0]);
+        dq = wi * lt.v;
+        Bk = k < 6 ? -dq * pf[3 + k] : k == 6 ? -dq * pf[10] : 0.0;
     }
     double* o = cwp + (size_t)p * CWP_W;
-    for (int e = 0; e < 8; ++e) o[CWP_BT + e] = ok ? a[e][8] : 0.0;   // a singular block is reported by the decoupling
+    o[CWP_B + k] = Bk;
+    o[CWP_C + k] = q.d;
+    if (k == 0) {
+        o[CWP_Q] = q.v;
+        o[CWP_DQ] = dq;
+    }
 }
 
 }  // namespace isc
@@ -587,19 +554,17 @@ hipError_t isc_launch_props(isc_ctx* ctx, const double* u, const double* u_old, 
 // cells) and the well rows of Newton's bordered system.
 hipError_t isc_launch_well_line(isc_ctx* ctx, const double* u, int mode) {
     if (ctx->ncw == 0) return hipSuccess;
-    int maxnp = 1;
-    for (const isc::CWell& W : ctx->cw_h) maxnp = std::max(maxnp, (int)W.np);
-    hipLaunchKernelGGL(isc::well_line_kernel, dim3(ctx->ncw), dim3(64), (size_t)2 * maxnp * sizeof(double),
+    hipLaunchKernelGGL(isc::well_line_kernel, dim3(ctx->ncw), dim3(64), (size_t)2 * ctx->cw_maxnp * sizeof(double),
                        ctx->stream, mode, ctx->cwp_cell, u, ctx->n, ctx->poro, ctx->well_slot, ctx->perf,
                        ctx->fluid_d, ctx->cw, ctx->wsw);
     return hipGetLastError();
 }
 
-hipError_t isc_launch_well_rows(isc_ctx* ctx, const double* u, const double* J) {
+hipError_t isc_launch_well_rows(isc_ctx* ctx, const double* u) {
     if (ctx->ncp == 0) return hipSuccess;
     const int blocks = (int)(((int64_t)ctx->ncp * 8 + 255) / 256);
     hipLaunchKernelGGL(isc::well_rows_kernel, dim3(blocks), dim3(256), 0, ctx->stream, ctx->ncp, ctx->cwp_cell,
-                       ctx->cwp_well, u, ctx->n, ctx->poro, ctx->well_slot, ctx->perf, ctx->fluid_d, ctx->cw, J,
-                       ctx->diag_pos, ctx->cwp);
+                       ctx->cwp_well, u, ctx->n, ctx->poro, ctx->well_slot, ctx->perf, ctx->fluid_d, ctx->cw,
+                       ctx->cwp);
     return hipGetLastError();
 }

@@ -8,6 +8,10 @@ Tolerances (stated per check):
                    the row's largest entry (products of property values that
                    agree to about 1e-13); R of a rate row <= 1e-9 of the
                    target (it is the rounding left by the well-line root)
+  one Newton step  both linear solves to 1e-12 from a state off the root:
+                   du within 1e-6 of the largest |du| of its unknown, dbhp
+                   within 1e-6 relative (the linear solve's residual times
+                   the conditioning, with a wide margin)
   Newton runs      states within 1e-9 of the oracle's per step (scaled by
                    max(|u|, floor) per unknown), bhp within 1e-9 relative,
                    the same switches and step sizes
@@ -85,6 +89,43 @@ def test_well_line_and_rows_match_oracle(dims, ctrl):
             assert np.all(np.abs(got - ref) <= 1e-9 * np.abs(ref).max() + 1e-300), (k, got, ref)
     for w, wd in enumerate(wl.wells):
         assert abs(R[w] - Ro[w]) <= 1e-9 * wd["target"]
+
+
+@pytest.mark.parametrize("ctrl", [I.CTRL_TOTAL, I.CTRL_OIL])
+def test_one_newton_update_matches_oracle(ctrl):
+    """One bordered Newton update from the same state on both sides.  The
+    GPU's Krylov operator holds the in-pattern couplings of B D^-1 C in the
+    matrix and applies the rest matrix-free; unless the two parts add up to
+    the reduced Jacobian exactly, du moves far beyond the tolerance (converged
+    roots alone would not show it: Newton with a wrong Jacobian still
+    converges, only more slowly)."""
+    from paper_1811_11992_amd import isc
+    wl = _cw(prod=dict(control=ctrl))
+    m = O.Model(wl)
+    st, u, _, hist = m.run(wl.u0.copy(), wl.dt, 2, keep_history=True)
+    assert st == 2
+    u_old = hist[-2]
+    bhp, on = m.well_state()
+    wl2 = copy.deepcopy(wl)          # off the root: other targets
+    wl2.wells[0]["target"] *= 1.05
+    wl2.wells[1]["target"] *= 0.95
+    m2 = O.Model(wl2)
+    m2.set_well_state(bhp, on)
+    st, uo, info = m2.newton_step(u, u_old, wl.dt, tol=1e-14, max_restarts=60, rtol=1e-12)
+    assert st == 0 and not info.converged
+    c = _ctx(wl2)
+    c.isc_set_well_state(bhp, on)
+    ug = dev(u)
+    sg, ig = c.isc_newton_step(ug, dev(u_old), wl.dt, tol=1e-14, lin=isc.solve_opts(max_restarts=60, rtol=1e-12))
+    assert sg == 0 and not ig.converged
+    duo, dug = uo - u, host(ug) - u
+    scale = np.maximum(np.abs(duo).max(axis=1), 1e-8 * FLOOR)
+    rel = np.abs(dug - duo).max(axis=1) / scale
+    assert np.all(rel <= 1e-6), rel
+    bo, oo = m2.well_state()
+    bg, og = c.isc_well_state()
+    assert np.array_equal(oo, og)
+    assert np.all(np.abs((bg - bhp) - (bo - bhp)) <= 1e-6 * np.abs(bo - bhp).max()), (bg, bo, bhp)
 
 
 def _run_pair(wl, nsteps, lin=None, **ctx_kw):
