@@ -345,11 +345,12 @@ def bicgstab_cost(name="C3", reps=2):
     return out
 
 
-def wells_cost(name="C3", nsteps=1):
+def wells_cost(name="C3", nsteps=1, cpr=False, p_iters=12):
     """The workload with its wells as controlled wells (bhp unknowns): the
     injector column holding its air rate up to P0 + 5 MPa, the producer column
     holding a total molar rate of half of it down to 0.8 P0; `nsteps` implicit
-    steps of FP64 BILU(0)-GMRES(30) with the time loop; ms and Krylov
+    steps of FP64 BILU(0)-GMRES(30) (with cpr: FP64 flexible GMRES(30) with
+    CPR, p_iters pressure GMRES steps) with the time loop; ms and Krylov
     iterations per Newton iteration and the final well state.  Not part of
     the default run; call it as bench.wells_cost() (under a kernel trace for
     the well kernels' share)."""
@@ -361,8 +362,13 @@ def wells_cost(name="C3", nsteps=1):
     wl.wells = [dict(inj, kind=I.WELL_INJECTOR, control=I.CTRL_RATE, limit=I.P0 + 5.0e6),
                 dict(kind=I.WELL_PRODUCER, cells=prod["cells"], target=0.5 * inj["target"],
                      control=I.CTRL_TOTAL, limit=0.8 * I.P0)]
-    ctx = isc.Context(wl)
-    sim = isc.Simulator(ctx, tol=1e-10, lin=isc.solve_opts(rtol=1e-8))
+    if cpr:
+        ctx = isc.Context(wl, cpr_p_iters=p_iters)
+        lin = isc.cpr_opts(p_iters=p_iters, rtol=1e-8)
+    else:
+        ctx = isc.Context(wl)
+        lin = isc.solve_opts(rtol=1e-8)
+    sim = isc.Simulator(ctx, tol=1e-10, lin=lin)
     u = torch.tensor(wl.u0, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -371,7 +377,8 @@ def wells_cost(name="C3", nsteps=1):
     el = time.perf_counter() - t0
     nit = sum(r["newton"] for r in recs)
     bhp, on = ctx.isc_well_state()
-    out = {"workload": f"{name} with controlled wells, {nsteps} step(s)", "newton": nit,
+    out = {"workload": f"{name} with controlled wells, {nsteps} step(s)", "solver": "cpr" if cpr else "bilu0",
+           "newton": nit,
            "ms_per_newton": round(el / max(1, nit) * 1e3, 1),
            "krylov_per_newton": round(sum(r["lin"] for r in recs) / max(1, nit), 1),
            "cuts": sum(r["cuts"] for r in recs), "bhp": bhp.tolist(), "on_limit": on.tolist()}

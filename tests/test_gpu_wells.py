@@ -91,16 +91,28 @@ def test_well_line_and_rows_match_oracle(dims, ctrl):
         assert abs(R[w] - Ro[w]) <= 1e-9 * wd["target"]
 
 
-@pytest.mark.parametrize("ctrl", [I.CTRL_TOTAL, I.CTRL_OIL])
-def test_one_newton_update_matches_oracle(ctrl):
+def _irregular_cells(nx=8, ny=6, nz=4):
+    """A producer's perforations in no stencil order: an L in the top layer
+    (x and y neighbours), a vertical pair with a gap below it, and a lone
+    cell, listed out of index order."""
+    ci = lambda x, y, z: I.cell_index(nx, ny, x, y, z)
+    return [ci(7, 5, 2), ci(6, 5, 0), ci(3, 2, 1), ci(7, 5, 0), ci(7, 5, 3), ci(6, 4, 0)]
+
+
+@pytest.mark.parametrize("ctrl,shape", [(I.CTRL_TOTAL, "column"), (I.CTRL_OIL, "column"),
+                                        (I.CTRL_TOTAL, "irregular")])
+def test_one_newton_update_matches_oracle(ctrl, shape):
     """One bordered Newton update from the same state on both sides.  The
     GPU's Krylov operator holds the in-pattern couplings of B D^-1 C in the
     matrix and applies the rest matrix-free; unless the two parts add up to
     the reduced Jacobian exactly, du moves far beyond the tolerance (converged
     roots alone would not show it: Newton with a wrong Jacobian still
-    converges, only more slowly)."""
+    converges, only more slowly).  The irregular producer has perforations
+    with zero, one and two in-pattern partners besides themselves."""
     from paper_1811_11992_amd import isc
     wl = _cw(prod=dict(control=ctrl))
+    if shape == "irregular":
+        wl.wells[1]["cells"] = _irregular_cells()
     m = O.Model(wl)
     st, u, _, hist = m.run(wl.u0.copy(), wl.dt, 2, keep_history=True)
     assert st == 2
@@ -159,6 +171,12 @@ def _check_pair(out):
 @pytest.mark.parametrize("ctrl", [I.CTRL_TOTAL, I.CTRL_OIL, I.CTRL_WATER, I.CTRL_LIQUID])
 def test_rate_controlled_run_matches_oracle(ctrl):
     _check_pair(_run_pair(_cw(prod=dict(control=ctrl)), 3))
+
+
+def test_irregular_perforations_run_matches_oracle():
+    out = _run_pair(_cw(prod=dict(cells=_irregular_cells())), 3)
+    _check_pair(out)
+    assert out[-1][4][1].tolist() == [0, 0]   # both wells still on their rates
 
 
 def test_limits_and_switching_match_oracle():
