@@ -522,7 +522,7 @@ __global__ void __launch_bounds__(256) well_rows_kernel(
     }
     double* o = cwp + (size_t)p * CWP_W;
     o[CWP_B + k] = Bk;
-    o[CWP_C + k] = q.d;
+    o[CWP_C + k] = (W.control == ISC_CTRL_BHP || W.on_limit) ? 0.0 : q.d;   // a held row is bhp - c
     if (k == 0) {
         o[CWP_Q] = q.v;
         o[CWP_DQ] = dq;

@@ -186,6 +186,19 @@ def test_limits_and_switching_match_oracle():
     out = _run_pair(wl, 3)
     _check_pair(out)
     assert out[-1][4][1].tolist() == [1, 1]
+    # the held rows at the last state: R = bhp - limit, D = 1, C = 0 on both sides
+    uo, (bo, oo), _, ug, _, _ = out[-1]
+    m = O.Model(wl)
+    m.set_well_state(bo, oo)
+    c = _ctx(wl)
+    c.isc_set_well_state(bo, oo)
+    R, D, B, C = c.isc_well_border(dev(uo), dev(uo), wl.dt)
+    Ro, Do, Bo, Co = m.well_border(uo)
+    assert np.array_equal(D, Do) and np.all(D == 1.0)
+    assert np.array_equal(R, Ro)
+    assert not host(C).any() and not Co.any()
+    for k in range(c.ncp):
+        assert np.all(np.abs(host(B)[k] - Bo[k]) <= 1e-9 * np.abs(Bo[k]).max() + 1e-300), k
 
 
 @pytest.mark.parametrize("mode", ["mixed", "cpr", "bicgstab"])
