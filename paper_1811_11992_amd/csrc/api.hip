@@ -387,7 +387,7 @@ isc_status isc_create(const isc_grid* grid_h, const isc_fluid* fluid_h, const do
         const bool controlled = W.kind == ISC_WELL_PRODUCER || W.kind == ISC_WELL_INJECTOR;
         const bool ctrl_ok = !controlled ||
                              (W.nperf <= isc::CW_MAXPERF && std::isfinite(W.target) && std::isfinite(W.limit) &&
-                              (W.control == ISC_CTRL_BHP ? W.target > 0 : (W.target >= 0 && W.limit > 0)) &&
+                              W.target > 0 && (W.control == ISC_CTRL_BHP || W.limit > 0) &&
                               (W.kind == ISC_WELL_INJECTOR || (W.control >= 0 && W.control <= 7)));
         if (W.nperf < 1 || !W.perf_cells_h || !(W.kind >= ISC_WELL_BHP_PRODUCER && W.kind <= ISC_WELL_INJECTOR) ||
             !(W.rw > 0) || !ctrl_ok) {

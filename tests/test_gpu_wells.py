@@ -243,7 +243,8 @@ def test_adjoint_refuses_controlled_wells():
 
 
 @pytest.mark.parametrize("bad", [dict(control=9), dict(control=I.CTRL_BHP, target=-1.0),
-                                 dict(target=-1.0), dict(limit=float("nan")), dict(kind=5)])
+                                 dict(target=-1.0), dict(target=0.0), dict(limit=float("nan")),
+                                 dict(limit=0.0), dict(kind=5)])
 def test_invalid_controlled_wells_are_refused(bad):
     from paper_1811_11992_amd import isc
     wl = _cw("4x3x2", prod=bad)
