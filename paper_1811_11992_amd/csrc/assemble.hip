@@ -23,29 +23,50 @@ __device__ __forceinline__ FaceOut face_eval(const double* __restrict__ Plo,
                                              const double* __restrict__ Phi, double plo,
                                              double phi_, double Tlo, double Thi, double trans,
                                              double area_h, double dz_lh, int e, int v) {
-    FaceOut o{0.0, 0.0, 0.0};
+    // The loads come in two independent batches: first the values every
+    // lane shares (the phases' gravity terms, the conductivities), which
+    // decide the upstream cell of each phase; then each lane's entries (the
+    // derivatives, and the upstream mobilities).  The arithmetic below is
+    // the same, in the same order, as evaluating phase by phase.
+    double gl[3], gh[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        gl[a] = Plo[PL_GAM + 9 * a];
+        gh[a] = Phi[PL_GAM + 9 * a];
+    }
     const double dp = plo - phi_;
-    const double ip = (v == 0) ? 1.0 : 0.0;
+    double dphi[3];
+    bool up_lo[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dphi[a] = dp - 0.5 * (gl[a] + gh[a]) * dz_lh;
+        up_lo[a] = !(dphi[a] < 0.0);
+    }
+    double dgl[3], dgh[3], m[3], md[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int s = mob_slot(a, e);
-        if (s < 0) continue;
-        const double gl = Plo[PL_GAM + 9 * a], gh = Phi[PL_GAM + 9 * a];
-        const double dphi = dp - 0.5 * (gl + gh) * dz_lh;
-        const double ddl = ip - 0.5 * Plo[PL_GAM + 9 * a + 1 + v] * dz_lh;
-        const double ddh = -ip - 0.5 * Phi[PL_GAM + 9 * a + 1 + v] * dz_lh;
-        const bool up_lo = !(dphi < 0.0);
-        const double* Pu = up_lo ? Plo : Phi;
-        const double m = Pu[PL_MOB + 9 * s];
-        const double md = Pu[PL_MOB + 9 * s + 1 + v];
-        const double tm = trans * m;
-        o.f += tm * dphi;
-        if (up_lo) {
-            o.dl += trans * md * dphi + tm * ddl;
+        dgl[a] = Plo[PL_GAM + 9 * a + 1 + v];
+        dgh[a] = Phi[PL_GAM + 9 * a + 1 + v];
+        const double* Pu = up_lo[a] ? Plo : Phi;
+        m[a] = s >= 0 ? Pu[PL_MOB + 9 * s] : 0.0;
+        md[a] = s >= 0 ? Pu[PL_MOB + 9 * s + 1 + v] : 0.0;
+    }
+    FaceOut o{0.0, 0.0, 0.0};
+    const double ip = (v == 0) ? 1.0 : 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (mob_slot(a, e) < 0) continue;
+        const double ddl = ip - 0.5 * dgl[a] * dz_lh;
+        const double ddh = -ip - 0.5 * dgh[a] * dz_lh;
+        const double tm = trans * m[a];
+        o.f += tm * dphi[a];
+        if (up_lo[a]) {
+            o.dl += trans * md[a] * dphi[a] + tm * ddl;
             o.dh += tm * ddh;
         } else {
             o.dl += tm * ddl;
-            o.dh += trans * md * dphi + tm * ddh;
+            o.dh += trans * md[a] * dphi[a] + tm * ddh;
         }
     }
     if (e == 6) {  // conduction with a harmonic bulk conductivity
@@ -54,20 +75,23 @@ __device__ __forceinline__ FaceOut face_eval(const double* __restrict__ Plo,
         const double kbar = 2.0 * kl * kh / sum;
         const double dT = Tlo - Thi;
         const double it = (v == 4) ? 1.0 : 0.0;
-        const double gl = 2.0 * kh * kh / (sum * sum), gh = 2.0 * kl * kl / (sum * sum);
+        const double gl2 = 2.0 * kh * kh / (sum * sum), gh2 = 2.0 * kl * kl / (sum * sum);
         o.f += area_h * kbar * dT;
-        o.dl += area_h * (gl * Plo[PL_KT + 1 + v] * dT + kbar * it);
-        o.dh += area_h * (gh * Phi[PL_KT + 1 + v] * dT - kbar * it);
+        o.dl += area_h * (gl2 * Plo[PL_KT + 1 + v] * dT + kbar * it);
+        o.dh += area_h * (gh2 * Phi[PL_KT + 1 + v] * dT - kbar * it);
     }
     return o;
 }
 
-__global__ void __launch_bounds__(256, 8) assemble_kernel(
+__global__ void __launch_bounds__(256) assemble_kernel(
     int32_t n, int32_t nx, int32_t ny, int32_t nz, const double* __restrict__ u,
     const double* __restrict__ payload, const double* __restrict__ trans, double ah_x, double ah_y,
     double ah_z, double dz, const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ diag_pos,
     double* __restrict__ F, double* __restrict__ J) {
-    const int32_t i = (int32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    // the cell is the same on all lanes of the wavefront; saying so lets the
+    // values the lanes share (its neighbours' pressures, transmissibilities,
+    // gravity terms) come through scalar loads into scalar registers
+    const int32_t i = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
     const int lane = threadIdx.x & 63;
     const int e = lane >> 3, v = lane & 7;
     if (i >= n) return;
