@@ -99,8 +99,15 @@ def _irregular_cells(nx=8, ny=6, nz=4):
     return [ci(7, 5, 2), ci(6, 5, 0), ci(3, 2, 1), ci(7, 5, 0), ci(7, 5, 3), ci(6, 4, 0)]
 
 
+def _adjacent_cells(nx=8, ny=6, nz=4):
+    """A producer column right beside the injector column: the two wells'
+    perforations are stencil neighbours, but B D^-1 C couples only
+    perforations of one well."""
+    return [I.cell_index(nx, ny, 1, 0, k) for k in range(nz)]
+
+
 @pytest.mark.parametrize("ctrl,shape", [(I.CTRL_TOTAL, "column"), (I.CTRL_OIL, "column"),
-                                        (I.CTRL_TOTAL, "irregular")])
+                                        (I.CTRL_TOTAL, "irregular"), (I.CTRL_TOTAL, "adjacent")])
 def test_one_newton_update_matches_oracle(ctrl, shape):
     """One bordered Newton update from the same state on both sides.  The
     GPU's Krylov operator holds the in-pattern couplings of B D^-1 C in the
@@ -113,6 +120,8 @@ def test_one_newton_update_matches_oracle(ctrl, shape):
     wl = _cw(prod=dict(control=ctrl))
     if shape == "irregular":
         wl.wells[1]["cells"] = _irregular_cells()
+    elif shape == "adjacent":
+        wl.wells[1]["cells"] = _adjacent_cells()
     m = O.Model(wl)
     st, u, _, hist = m.run(wl.u0.copy(), wl.dt, 2, keep_history=True)
     assert st == 2
@@ -173,8 +182,9 @@ def test_rate_controlled_run_matches_oracle(ctrl):
     _check_pair(_run_pair(_cw(prod=dict(control=ctrl)), 3))
 
 
-def test_irregular_perforations_run_matches_oracle():
-    out = _run_pair(_cw(prod=dict(cells=_irregular_cells())), 3)
+@pytest.mark.parametrize("cells", [_irregular_cells(), _adjacent_cells()], ids=["irregular", "adjacent"])
+def test_perforation_layouts_run_matches_oracle(cells):
+    out = _run_pair(_cw(prod=dict(cells=cells)), 3)
     _check_pair(out)
     assert out[-1][4][1].tolist() == [0, 0]   # both wells still on their rates
 
