@@ -397,6 +397,8 @@ class Simulator:
                 if info.converged:
                     ok = True
                     break
+            else:
+                nit += 1   # every call updated u: max_newton + 1 iterations, none converged
             rec["newton"] += nit
             rec["res"] = info.res_scaled
             if ok:

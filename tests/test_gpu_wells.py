@@ -171,6 +171,7 @@ def _run_pair(wl, nsteps, lin=None, **ctx_kw):
 def _check_pair(out):
     for s, (uo, (bo, oo), ro, ug, (bg, og), rg) in enumerate(out):
         assert rg["cuts"] == ro["cuts"] and rg["dt"] == ro["dt"], (s, rg, ro)
+        assert rg["newton"] == ro["newton"], (s, rg, ro)
         assert np.array_equal(oo, og), (s, oo, og)
         rel = np.abs(ug - uo).max(axis=1) / np.maximum(np.abs(uo).max(axis=1), FLOOR)
         assert np.all(rel <= 1e-9), (s, rel)
