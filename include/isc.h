@@ -122,9 +122,10 @@ enum { ISC_CTRL_BHP = 0, ISC_CTRL_WATER = 1, ISC_CTRL_OIL = 2, ISC_CTRL_GAS = 4 
  * injector -- and is held at its BHP limit `limit` (producer minimum,
  * injector maximum) when the rate cannot be met within it.  No backflow.
  * isc_create refuses (ISC_ERR_ARG) a kind 3/4 well with more than 2048
- * perforations, a target or limit that is not finite and positive (a well
- * that is to stay shut is left out: at a zero rate its row has no bhp
- * derivative), or an unknown control. */
+ * perforations, a target that is not finite and positive (a well that is to
+ * stay shut is left out: at a zero rate its row has no bhp derivative), a
+ * limit that is not finite (under rate control: not finite and positive), or
+ * an unknown control. */
 typedef struct {
     int32_t kind;
     int32_t nperf;
