@@ -78,3 +78,49 @@ def _unbound_names(path):
 
 def test_every_name_the_benchmark_reads_is_bound():
     assert _unbound_names(os.path.join(ROOT, "bench.py")) == []
+
+
+def test_driver_counts_solving_iterations_and_cuts_failed_steps():
+    """bench.Driver on a scripted context (CPU tensors): a converged call ends
+    the time step without counting; an update counts; an attempt that runs
+    past max_newton or fails is restored and its step halved."""
+    import types
+
+    import torch
+
+    import bench
+    from paper_1811_11992_amd import isc
+
+    class Scripted:
+        def __init__(self, script):
+            self.script, self.k = list(script), 0
+
+        def isc_newton_step(self, u, u_old, dt, tol, lin):
+            what = self.script[self.k]
+            self.k += 1
+            info = types.SimpleNamespace(converged=int(what == "c"),
+                                         lin=types.SimpleNamespace(iters=5, inner_iters_total=0))
+            if what == "u":
+                u += 1.0
+            return (isc.ISC_OK if what != "e" else isc.ISC_ERR_NEWTON_NOCONV), info
+
+    d = bench.Driver.__new__(bench.Driver)
+    d.ctx = Scripted("uuc" + "uuu" + "u" + "e" + "u")
+    d.wl = types.SimpleNamespace(dt=8.0)
+    d.lin, d.tol, d.max_newton = None, 1e-10, 2
+    d.u = torch.zeros(3, dtype=torch.float64)
+    d.u_old = d.u.clone()
+    d.dt = 8.0
+    d.ni_in_step = d.ni = d.lin_its = d.inner_its = d.steps_done = d.cuts = 0
+    d.lin_each = []
+    for _ in range(2):                 # two updates of the first step
+        d.newton_iteration()
+    assert (d.ni, d.steps_done, float(d.u[0])) == (2, 0, 2.0)
+    d.newton_iteration()               # converged: next step, then its first update
+    assert (d.ni, d.steps_done, float(d.u_old[0]), float(d.u[0])) == (3, 1, 2.0, 3.0)
+    d.newton_iteration()               # second update of step 2
+    d.newton_iteration()               # third call runs past max_newton: cut, then an update at dt/2
+    assert (d.ni, d.cuts, d.dt, float(d.u[0])) == (5, 1, 4.0, 3.0)
+    d.newton_iteration()               # an error: cut again, then an update at dt/4
+    assert (d.ni, d.cuts, d.dt, float(d.u[0])) == (6, 2, 2.0, 3.0)
+    assert d.lin_each == [5] * 6
